@@ -1,0 +1,114 @@
+"""Low Rank simulation with Eigenvalue Truncation (LRET), FP64 oracle (test infrastructure only).
+
+Follows the paper step by step:
+  * state rho = L L^H with L in C^{2^N x V}                 (Eq. "low rank decomposition", Sec. II.A)
+  * gate: L <- G L                                          (Eq. "low rank evolution G")
+  * Kraus channel: L <- [sqrt(p_1) K_1 L, ..., sqrt(p_A) K_A L]   (Eq. "low rank evolution K")
+  * truncation after each channel group                      (Sec. II.C; Algorithm 1)
+  * truncation through the small matrix L^H L instead of rho   (Sec. II.B, Theorem 1 of App. B)
+
+Readings where the paper is silent (each also listed in the design notes):
+  * Compressed factor.  Theorem 1 gives the eigenvectors of rho' = L'L'^H as u_i = L' v_i /
+    sqrt(lambda_i), so the truncated state sum_{i<=k} lambda_i u_i u_i^H equals
+    (L' V_k)(L' V_k)^H: the new factor is L' V_k (times the renormalisation scale c).
+  * Rank rule.  k = min(r, N, k_eps).  k_eps is the smallest k whose kept mass
+    K_k = sum_{i<=k} max(lambda_i, 0) reaches (1 - eps) Tr G ("picked up one by one until they
+    sum to 1 - eps", Sec. II.B, measured against the trace rather than against 1); eps = 0
+    disables the threshold (fixed-rank mode).
+  * Ties.  tie=1 ("cluster") lowers k while lambda_k - lambda_{k+1} <= TAU_CLUSTER * Tr G, so
+    that the kept set is gap-separated and the truncated state is unique; tie=0 keeps the
+    eigensolver's order.
+  * Renormalisation.  renorm=1 scales the kept part to unit trace, c = K_k^{-1/2}; renorm=0 is
+    the paper-literal truncation (c = 1).
+  * Discarded mass delta = Tr G - K_k.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .linalg import apply_gate, popcount
+
+TAU_CLUSTER = 1e-6
+
+
+def init_state(n: int) -> np.ndarray:
+    """L^(0) = [1, 0, ..., 0]^T: the |0...0> fiducial state (Algorithm 1)."""
+    L = np.zeros((2 ** n, 1), dtype=np.complex128)
+    L[0, 0] = 1.0
+    return L
+
+
+def apply_diag_weight(L: np.ndarray, n: int, phase: np.ndarray) -> np.ndarray:
+    """L[x, :] *= phase[popcount(x)] -- a diagonal gate that depends on the Hamming weight."""
+    w = popcount(np.arange(2 ** n, dtype=np.uint64))
+    return L * np.asarray(phase, dtype=np.complex128)[w][:, None]
+
+
+def kraus_expand(L: np.ndarray, n: int, qubit: int, ops: np.ndarray) -> np.ndarray:
+    """L' = [E_1 L | E_2 L | ... | E_A L] with E_a = sqrt(p_a) K_a acting on `qubit`
+    (Eq. "low rank evolution K"); the column count grows A-fold, block-major by a."""
+    return np.concatenate([apply_gate(L, n, (qubit,), E) for E in ops], axis=1)
+
+
+def select_rank(lam_desc: np.ndarray, trace: float, r: int, eps: float, tie: int,
+                tau: float = TAU_CLUSTER) -> int:
+    """Number of kept eigenvalues k from descending eigenvalues (rank rule, Sec. II.B)."""
+    N = lam_desc.shape[0]
+    k = min(r, N)
+    lp = np.maximum(lam_desc, 0.0)
+    if eps > 0.0:
+        kept = np.cumsum(lp)
+        target = (1.0 - eps) * trace
+        hit = np.nonzero(kept >= target)[0]
+        k_eps = int(hit[0]) + 1 if hit.size else N
+        k = min(k, k_eps)
+    if tie == 1:
+        while 1 < k < N and (lam_desc[k - 1] - lam_desc[k]) <= tau * trace:
+            k -= 1
+    return max(k, 1)
+
+
+def compress(L: np.ndarray, r: int, eps: float = 0.0, tie: int = 0, renorm: int = 1):
+    """Eigenvalue truncation of rho' = L'L'^H through G = L'^H L' (Theorem 1).
+
+    Returns (L_new, info) with L_new = c L' V_k and info = {k, discarded, trace, gap, lam}."""
+    G = L.conj().T @ L                       # Gram matrix, V x V (Theorem 1: shares rho's spectrum)
+    G = 0.5 * (G + G.conj().T)
+    lam, V = np.linalg.eigh(G)               # ascending
+    lam = lam[::-1]
+    V = V[:, ::-1]
+    trace = float(np.real(np.trace(G)))
+    k = select_rank(lam, trace, r, eps, tie)
+    kept = float(np.sum(np.maximum(lam[:k], 0.0)))
+    c = 1.0 / np.sqrt(kept) if renorm else 1.0
+    L_new = c * (L @ V[:, :k])
+    gap = float(lam[k - 1] - lam[k]) if k < lam.shape[0] else float("inf")
+    info = dict(k=k, discarded=max(trace - kept, 0.0), trace=trace, gap=gap, lam=lam.copy(),
+                scale=c)
+    return L_new, info
+
+
+def run_lret(program, L0: np.ndarray | None = None, log: list | None = None) -> np.ndarray:
+    """Algorithm 1: gates, then for every channel group concatenate and truncate.  Ops are
+    executed in program order; returns the final factor L^(D)."""
+    from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
+
+    n = program.n
+    L = init_state(n) if L0 is None else np.array(L0, dtype=np.complex128)
+    for op in program.ops:
+        if isinstance(op, Gate):
+            L = apply_gate(L, n, op.qubits, op.u)
+        elif isinstance(op, DiagWeight):
+            L = apply_diag_weight(L, n, op.phase)
+        elif isinstance(op, Kraus):
+            L = kraus_expand(L, n, op.qubit, op.ops)
+        elif isinstance(op, Compress):
+            L, info = compress(L, op.r, op.eps, op.tie, op.renorm)
+            if log is not None:
+                info.pop("lam")
+                log.append(info)
+        elif isinstance(op, LayerEnd):
+            pass
+        else:
+            raise TypeError(f"unknown op {op!r}")
+    return L

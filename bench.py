@@ -1,0 +1,162 @@
+"""Benchmark: noisy-circuit layers/s of the low-rank density-matrix path on one MI355X.
+
+Workload (one step): the random brickwork circuit with n = 20 qubits, rank r = 64, 40 layers
+of Haar SU(2) on every qubit plus CZ on alternating pairs, and per qubit per layer amplitude
+damping (gamma = 0.002) -> compress -> dephasing (p = 0.001) -> compress (1600 compressions);
+then <Z_i Z_{i+1}> for all neighbours and 10^4 samples.  Complex FP32 bulk (FP32 MFMA Gram and
+projection), FP64 eigensolve.  Inputs are seeded and synthetic.
+
+Prints one JSON line (rank 0).  --gpus > 1 is not supported: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "noisy-circuit layers/s at n=20 r=64 vs full-rank DM, same GPU; %HBM peak; grads/s"
+FP32_MFMA_PEAK = 157.3e12
+HBM_PEAK = 8.0e12
+CLASS_NAMES = {0: "gate_pass", 1: "gram", 2: "gram_reduce", 3: "eigensolve", 4: "projection"}
+
+
+def algorithmic_flops(n: int, r_pad: int, cls: int) -> float:
+    """Real flops one launch must do (complex MAC = 8 flops) on the split view X = [L_0 | L_1]
+    (2^(n-1) x 2r): the Gram matrix is Hermitian (half of X^H X), the projection is X W with
+    W of size 2r x 2r."""
+    rows, w = 2 ** (n - 1), 2 * r_pad
+    if cls == 1:
+        return 8.0 * rows * w * w / 2
+    if cls == 4:
+        return 8.0 * rows * w * w
+    raise ValueError(cls)
+
+
+def run_step(dm, prog, uniforms):
+    from paper_2009_06657_amd import run_program
+
+    dm.reset()
+    run_program(dm, prog)
+    z, zz, tr = dm.expect_z()
+    s = dm.sample(uniforms)
+    return zz, s, tr
+
+
+def cpu_baseline(n: int, r: int, budget_s: float = 20.0) -> dict:
+    """The CPU oracle on a bounded sample of the same workload: from a steady-state rank-r
+    factor, one layer's gates and as many channel+compress steps as fit the budget; the layer
+    time is extrapolated to 40 compressions."""
+    import oracle
+    from oracle.lret import compress, kraus_expand
+    from workloads import circuits as C
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    prog = C.cfg3_program(n=n, r=r, layers=1)
+    L = C.random_orthogonal_factor(n, r, seed=4242)
+    gates = [op for op in prog.ops if isinstance(op, C.Gate)]
+    chans = [op for op in prog.ops if isinstance(op, C.Kraus)]
+    t0 = time.perf_counter()
+    g_done = 0
+    for op in gates:
+        L = oracle.apply_gate(L, n, op.qubits, op.u)
+        g_done += 1
+        if time.perf_counter() - t0 > 0.25 * budget_s:
+            break
+    per_gate = (time.perf_counter() - t0) / g_done
+    done, t_comp = 0, 0.0
+    for ch in chans:
+        t1 = time.perf_counter()
+        L, _ = compress(kraus_expand(L, n, ch.qubit, ch.ops), r)
+        t_comp += time.perf_counter() - t1
+        done += 1
+        if t_comp > 0.75 * budget_s:
+            break
+    per_comp = t_comp / done
+    t_layer = per_gate * len(gates) + per_comp * len(chans)
+    return {"value": 1.0 / t_layer, "unit": "layers/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"n={n} r={r}, from a steady-state rank-{r} factor: {g_done} of {len(gates)} "
+                       f"gates and {done} of {len(chans)} channel+compress steps of one brickwork "
+                       f"layer, extrapolated to the whole layer ({per_gate:.2f} s per gate, "
+                       f"{per_comp:.2f} s per compress)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--layers", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2009_06657_amd as lr
+    from workloads import circuits as C
+
+    prog = C.cfg3_program(layers=args.layers)
+    uniforms = C.sample_uniforms(prog.meta["samples"], prog.meta["sample_seed"])
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, device="cuda:0")
+
+    for _ in range(args.warmup):
+        run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+
+    dominant = 4
+    dm.timing_begin(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        zz, samples, tr = run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nl, mean_ms, tot_ms = dm.timing_end()
+
+    layers = args.layers * args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    flops = algorithmic_flops(prog.n, dm.r_pad, dominant)
+    achieved = flops / (mean_ms * 1e-3)
+    out = {
+        "metric": METRIC, "value": layers / elapsed, "unit": "layers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "random brickwork, amplitude damping + dephasing per qubit per layer, "
+                               "compress after every channel, <ZZ> + 1e4 samples",
+                   "n": prog.n, "r": prog.r, "layers": args.layers, "compressions_per_step": prog.n_compress(),
+                   "eigensolve": "f64", "trace_after": tr},
+        "roofline": {"bound": "mfma", "kernel": CLASS_NAMES[dominant], "achieved": achieved / 1e12,
+                     "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
+                     "traffic": None, "launches": nl, "mean_ms": mean_ms},
+    }
+    if not args.no_breakdown:
+        br = {}
+        for cls in (0, 1, 2, 3, 4):
+            dm.timing_begin(cls)
+            run_step(dm, prog, uniforms)
+            n_, m_, t_ = dm.timing_end()
+            br[CLASS_NAMES[cls]] = {"launches": n_, "mean_ms": m_, "total_ms": t_}
+        out["breakdown_one_step"] = br
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prog.n, prog.r)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * lrdm.h -- C ABI of the low-rank density-matrix (LRET) library for AMD MI355X (gfx950).
+ *
+ * The state of n qubits is rho = L L^H with L a 2^n x r complex factor (Eq. "low rank
+ * decomposition", Sec. II.A).  Gates act column-wise on L (Eq. "low rank evolution G"), a Kraus
+ * channel concatenates [E_1 L | ... | E_m L] (Eq. "low rank evolution K"), and a compression
+ * returns to rank <= r through the Gram matrix G = L'^H L', its leading eigenpairs and the
+ * projection L' V_k (Sec. II.B and Theorem 1 of App. B).  Outputs are Prob(x) and Tr(L^H O L)
+ * (Sec. II.D).
+ *
+ * General conventions
+ *  - Every call returns an lrdm_status and never throws.  On failure lrdm_last_error() holds a
+ *    message; argument errors are detected before anything is enqueued and leave the handle
+ *    unchanged.
+ *  - The library never allocates device memory.  The caller owns the state and workspace
+ *    buffers (sizes from lrdm_workspace_size) and every host array; host arrays are consumed
+ *    before the call returns.  lrdm_destroy frees only the host-side handle.
+ *  - Work is enqueued on the stream given to lrdm_init in call order.  Calls that return host
+ *    values synchronise that stream.  Device outputs are valid after a stream synchronisation.
+ *  - Layout of L in the state buffer: row-major, L[x * ld + v], x in [0, 2^n) with qubit q =
+ *    bit q of x, v in [0, ld); complex values interleaved (re, im) as float pairs (LRDM_C64) or
+ *    double pairs (LRDM_C128).  ld = r_pad = r_max rounded up to a multiple of 8 (times m_max
+ *    in plain mode); unused columns are zero.
+ *  - Gate and Kraus matrices are FP64, row-major, interleaved (re, im).
+ *  - Asynchronous device errors (LRDM_E_HIP, LRDM_E_EIG) poison the handle: every later call
+ *    returns LRDM_E_STATE until lrdm_destroy.
+ */
+#ifndef LRDM_H
+#define LRDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lrdm_ctx* lrdm_t;
+
+typedef enum {
+  LRDM_OK = 0,
+  LRDM_E_ARG = 1,          /* invalid argument (range, null pointer, non-unitary, incomplete Kraus set) */
+  LRDM_E_NOMEM = 2,        /* a caller-provided buffer is smaller than required */
+  LRDM_E_HIP = 3,          /* the HIP runtime reported an error */
+  LRDM_E_EIG = 4,          /* non-finite Gram matrix or eigensolver failure */
+  LRDM_E_STATE = 5,        /* call not valid in the current state (poisoned handle, pending channel) */
+  LRDM_E_UNSUPPORTED = 6   /* valid request outside the supported sizes */
+} lrdm_status;
+
+typedef enum { LRDM_C64 = 0, LRDM_C128 = 1 } lrdm_dtype;
+
+/* lrdm_init flags */
+#define LRDM_FLAG_PLAIN 0x1u   /* plain low-rank form: apply_kraus materialises [E_1 L | ... | E_m L]
+                                  (Eq. "low rank evolution K") and compress diagonalises its full
+                                  (m r) x (m r) Gram matrix; the default fuses both (see lrdm_compress) */
+
+/* Per-compression record (Sec. II.B). */
+typedef struct {
+  int rank;                /* kept eigenpairs k */
+  int n_eig;               /* order N of the Gram matrix that was diagonalised */
+  double discarded;        /* Tr G - sum_{i<=k} max(lambda_i, 0) */
+  double discarded_total;  /* running sum of `discarded` since lrdm_init / lrdm_set_L */
+  double trace_before;     /* Tr G = Tr(rho') before truncation */
+  double boundary_gap;     /* lambda_k - lambda_{k+1}; +inf when k == N */
+  double lambda_max;       /* largest eigenvalue of G */
+} lrdm_compress_info;
+
+/* Required buffer sizes for a handle.  n in [1, 30]; r_max in [1, 64]; m_max in [1, 4] is the
+ * largest Kraus count that will be applied; (m_max * r_pad) must not exceed 128 (the order of
+ * the largest Gram matrix the eigensolver accepts) and, for LRDM_C128, r_pad must not exceed 32.
+ * Returns LRDM_E_UNSUPPORTED outside these limits. */
+lrdm_status lrdm_workspace_size(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags,
+                                size_t* state_bytes, size_t* work_bytes);
+
+/* Create a handle over caller-owned device buffers and set L = e_0 = |0...0> (Algorithm 1).
+ * hip_stream is a hipStream_t (NULL = the null stream).  The buffers must stay alive and
+ * untouched by the caller until lrdm_destroy. */
+lrdm_status lrdm_init(lrdm_t* out, int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags,
+                      void* state_dev, size_t state_bytes, void* work_dev, size_t work_bytes,
+                      void* hip_stream);
+
+/* Reset an existing handle to L = e_0 (rank 1), clearing the running discarded mass. */
+lrdm_status lrdm_reset(lrdm_t h);
+
+lrdm_status lrdm_destroy(lrdm_t h);
+
+/* Gate L <- G L (Eq. "low rank evolution G").  k in {1, 2}; qubits[0..k) distinct and < n;
+ * u is 2^k x 2^k, row-major, interleaved re/im, with local index i = sum_j b(qubits[j]) 2^j.
+ * Unitarity is checked in FP64 (max |U^H U - I| <= 1e-10, else LRDM_E_ARG).  Gates are queued
+ * and applied in fused passes (several qubits per HBM sweep) at the next non-gate call. */
+lrdm_status lrdm_apply_gate(lrdm_t h, int k, const int* qubits, const double* u);
+
+/* Diagonal gate depending on Hamming weight: L[x, :] *= phase[popcount(x)], phase has n + 1
+ * unit-modulus complex entries (interleaved).  Used for the Grover oracle of Sec. III.C and the
+ * reflection about |0...0>. */
+lrdm_status lrdm_apply_diagonal_weight(lrdm_t h, const double* phase);
+
+/* Kraus channel on one qubit (Eq. "low rank evolution K"): e holds m 2x2 matrices
+ * E_a = sqrt(p_a) K_a (row-major, interleaved), m in [1, m_max], sum_a E_a^H E_a = I within
+ * 1e-10.  The concatenation is lazy: the next call must be lrdm_compress (else LRDM_E_STATE),
+ * which consumes it without ever forming the 2^n x (m r) matrix.  In plain mode the
+ * concatenation is materialised here. */
+lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e);
+
+/* Eigenvalue truncation (Sec. II.B) through G = L'^H L' (Theorem 1), L <- c L' V_k.
+ *  r_target in [1, r_max]: rank cap.  eps in [0, 1): keep the smallest k whose kept mass
+ *  sum_{i<=k} max(lambda_i, 0) reaches (1 - eps) Tr G (eps = 0 disables the threshold).
+ *  tie_policy: 0 = keep eigensolver order; 1 = lower k while lambda_k - lambda_{k+1} <=
+ *  1e-6 Tr G so the kept set is gap-separated.  renorm: 1 = scale to unit trace
+ *  (c = kept^{-1/2}), 0 = c = 1.  The Gram matrix is accumulated in the bulk precision (FP32
+ *  MFMA for LRDM_C64) and diagonalised in FP64.  info may be NULL; if not, the call
+ *  synchronises the stream and fills it. */
+lrdm_status lrdm_compress(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
+                          lrdm_compress_info* info);
+
+/* Prob(x) = sum_v |L[x, v]|^2 (Sec. II.D) for all 2^n basis states into p_dev (2^n doubles,
+ * device memory owned by the caller).  Asynchronous. */
+lrdm_status lrdm_probabilities(lrdm_t h, double* p_dev);
+
+/* Tr(L^H P_t L) (Sec. II.D) for n_terms Pauli strings P_t = i^{|x&z|} X^xmask[t] Z^zmask[t]
+ * (Y where both bits are set).  summed = 0: out_host[t] = Tr(L^H P_t L) for every t (n_terms
+ * doubles); summed = 1: out_host[0] = sum_t coeff[t] Tr(L^H P_t L).  coeff may be NULL when
+ * summed = 0.  n_terms in [1, 65536].  Synchronises. */
+lrdm_status lrdm_expect_pauli(lrdm_t h, int n_terms, const uint64_t* xmask, const uint64_t* zmask,
+                              const double* coeff, int summed, double* out_host);
+
+/* <Z_i> = sum_x Prob(x) (1 - 2 x_i) for every qubit into z_host (n doubles) and, if zz_host is
+ * not NULL, <Z_i Z_{i+1}> for i in [0, n-1) (n - 1 doubles).  trace_host (nullable) receives
+ * sum_x Prob(x).  One pass over L.  Synchronises. */
+lrdm_status lrdm_expect_z(lrdm_t h, double* z_host, double* zz_host, double* trace_host);
+
+/* Measurement samples from Prob (Sec. II.D): for each of `count` uniforms u_j in [0, 1)
+ * (host array), out_host[j] = the smallest x with CDF(x) > u_j * CDF(2^n - 1), CDF being the
+ * FP64 running sum of Prob.  count in [1, 2^24].  Synchronises. */
+lrdm_status lrdm_sample(lrdm_t h, int count, const double* uniforms, uint64_t* out_host);
+
+/* Copy L out (2^n x ld, the state layout; to_host = 1: dst is host memory, else device).
+ * rank_out (nullable) receives the host-side bound on the number of non-zero columns.
+ * Synchronises when to_host = 1. */
+lrdm_status lrdm_get_L(lrdm_t h, void* dst, int to_host, int* rank_out);
+
+/* Replace L by a caller factor with `rank` columns (row-major 2^n x rank in the bulk
+ * precision, interleaved; from_host = 1: host memory, else device).  Columns beyond rank are
+ * zeroed.  Used for tests and for resuming a run. */
+lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank);
+
+/* Wait for all work queued on the handle's stream; reports asynchronous device errors. */
+lrdm_status lrdm_synchronize(lrdm_t h);
+
+/* Kernel timing for performance reports.  kernel_class: 0 = gate sweep, 1 = Gram, 2 = Gram
+ * reduction, 3 = eigensolver (all stages), 4 = projection.  Between lrdm_timing_begin and
+ * lrdm_timing_end every launch of that class is bracketed by HIP events on the handle's
+ * stream; lrdm_timing_end synchronises and returns the number of launches and their mean
+ * duration in milliseconds.  At most 65536 launches are recorded. */
+lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class);
+lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* total_ms);
+
+/* Last error message for h, or the calling thread's last error when h == NULL. */
+const char* lrdm_last_error(lrdm_t h);
+
+/* Library version string. */
+const char* lrdm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRDM_H */

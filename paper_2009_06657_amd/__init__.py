@@ -1,0 +1,7 @@
+"""lrdm: low-rank density-matrix evolution with eigenvalue truncation on AMD MI355X (gfx950).
+
+The compute path is the HIP library liblrdm.so (include/lrdm.h); this package holds its
+sources (csrc/), the build script and a thin ctypes binding (lrdm.py).
+"""
+from .lrdm import (C64, C128, FLAG_PLAIN, LowRankDM, LrdmError, load_library, run_program,  # noqa: F401
+                   workspace_size)

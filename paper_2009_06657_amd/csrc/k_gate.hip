@@ -1,0 +1,200 @@
+// Gate sweeps over the low-rank factor: L <- G L column by column (Eq. "low rank evolution G",
+// Sec. II.A), fused so that one HBM read + write of L applies every gate of a pass.
+//
+// Layout: L is row-major [2^n][ld] complex.  A pass picks k <= 8 "local" qubits; a row tile is
+// the 2^k rows that differ only in those bits (up to 64 KB).  A work-group stages one tile in
+// LDS, applies every operation of the pass in order as a sweep over row pairs (1q), quads (2q)
+// or rows (diagonal gates, which act on any qubit because the full row index is known), and
+// writes the tile back.  Consecutive threads handle consecutive columns of one row, so every
+// global load/store is a contiguous ncols-wide row segment whatever the qubit.
+#include "lrdm_internal.h"
+
+namespace lrdm {
+
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class C> __device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <class C, class T> __device__ __forceinline__ C cmk(T re, T im) {
+  C r;
+  r.x = re;
+  r.y = im;
+  return r;
+}
+
+// Row index of tile slot i: base with local bit j set iff bit j of i is set.
+__device__ __forceinline__ uint32_t slot_row(uint32_t base, uint32_t i, const int* lq, int k) {
+  uint32_t x = base;
+  for (int j = 0; j < k; ++j) x |= ((i >> j) & 1u) << lq[j];
+  return x;
+}
+__device__ __forceinline__ uint32_t insert_zero(uint32_t p, int j) {
+  return ((p >> j) << (j + 1)) | (p & ((1u << j) - 1u));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
+                                                        int cshift) {
+  using C = cx_t<T>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
+  C* tile = reinterpret_cast<C*>(gate_smem);   // [2^k][ncols]
+  const int k = P.k, nc = P.ncols, tid = threadIdx.x;
+  const size_t ld = (size_t)P.ld;
+  int lq[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) lq[j] = P.local_q[j];
+
+  // deposit the tile index into the non-local bit positions (ascending local qubits)
+  uint32_t base = blockIdx.x;
+  for (int j = 0; j < k; ++j) {
+    const int p = P.sorted_q[j];
+    base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
+  }
+  const int elems = nc << k;
+  for (int e = tid; e < elems; e += 256) {
+    const uint32_t i = (uint32_t)e >> cshift;
+    const int v = e & (nc - 1);
+    tile[e] = L[(size_t)slot_row(base, i, lq, k) * ld + v];
+  }
+  __syncthreads();
+
+  for (int o = 0; o < P.n_ops; ++o) {
+    const T* u = P.coef + P.op_coef[o];
+    const int ty = P.op_type[o];
+    if (ty == OP_1Q) {
+      const int j = P.op_a[o];
+      const C u00 = cmk<C, T>(u[0], u[1]), u01 = cmk<C, T>(u[2], u[3]);
+      const C u10 = cmk<C, T>(u[4], u[5]), u11 = cmk<C, T>(u[6], u[7]);
+      for (int e = tid; e < (elems >> 1); e += 256) {
+        const int v = e & (nc - 1);
+        const uint32_t i0 = insert_zero((uint32_t)e >> cshift, j), i1 = i0 | (1u << j);
+        C& a0 = tile[(i0 << cshift) + v];
+        C& a1 = tile[(i1 << cshift) + v];
+        const C x0 = a0, x1 = a1;
+        a0 = cadd(cmul(u00, x0), cmul(u01, x1));
+        a1 = cadd(cmul(u10, x0), cmul(u11, x1));
+      }
+    } else if (ty == OP_2Q) {
+      const int ja = P.op_a[o], jb = P.op_b[o];
+      const int jlo = ja < jb ? ja : jb, jhi = ja < jb ? jb : ja;
+      for (int e = tid; e < (elems >> 2); e += 256) {
+        const int v = e & (nc - 1);
+        const uint32_t i00 = insert_zero(insert_zero((uint32_t)e >> cshift, jlo), jhi);
+        const uint32_t idx[4] = {i00, i00 | (1u << ja), i00 | (1u << jb), i00 | (1u << ja) | (1u << jb)};
+        C x[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) x[m] = tile[(idx[m] << cshift) + v];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          C acc = cmul(cmk<C, T>(u[8 * r], u[8 * r + 1]), x[0]);
+#pragma unroll
+          for (int m = 1; m < 4; ++m) acc = cadd(acc, cmul(cmk<C, T>(u[8 * r + 2 * m], u[8 * r + 2 * m + 1]), x[m]));
+          tile[(idx[r] << cshift) + v] = acc;
+        }
+      }
+    } else {
+      // diagonal in the computational basis: phase from the full row index
+      const int qa = P.op_a[o], qb = P.op_b[o];
+      for (int e = tid; e < elems; e += 256) {
+        const uint32_t x = slot_row(base, (uint32_t)e >> cshift, lq, k);
+        int sel;
+        if (ty == OP_DIAG1)
+          sel = (int)((x >> qa) & 1u);
+        else if (ty == OP_DIAG2)
+          sel = (int)((x >> qa) & 1u) | ((int)((x >> qb) & 1u) << 1);
+        else
+          sel = __popc(x);
+        tile[e] = cmul(cmk<C, T>(u[2 * sel], u[2 * sel + 1]), tile[e]);
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < elems; e += 256) {
+    const uint32_t i = (uint32_t)e >> cshift;
+    const int v = e & (nc - 1);
+    L[(size_t)slot_row(base, i, lq, k) * ld + v] = tile[e];
+  }
+}
+
+template <class T>
+hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
+  if (p.ncols < 1 || (p.ncols & (p.ncols - 1)) || p.k < 0 || p.k > 8 || p.k > p.n)
+    return hipErrorInvalidValue;
+  int cshift = 0;
+  while ((1 << cshift) < p.ncols) ++cshift;
+  const size_t shm = ((size_t)p.ncols << p.k) * sizeof(cx_t<T>);
+  if (shm > 65536) return hipErrorInvalidValue;
+  const uint32_t tiles = 1u << (p.n - p.k);
+  hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(256), shm, s, p, L, cshift);
+  return hipGetLastError();
+}
+
+// Plain-form Kraus concatenation (Eq. "low rank evolution K"): for every row pair
+// (x0, x1) = (bit q clear, bit q set) and column v < c, column a*c + v of row x_b' becomes
+// sum_b E_a[b'][b] L[x_b][v].  Each thread reads its two inputs before writing, and no other
+// thread touches them, so the expansion is done in place inside the ld-wide rows.
+template <class T>
+__global__ __launch_bounds__(256) void kraus_expand_kernel(cx_t<T>* __restrict__ L, uint32_t half_rows,
+                                                           int ld, int c, int q, Channel ch,
+                                                           int m_pad) {
+  using C = cx_t<T>;
+  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t y = (uint32_t)(gid / (uint64_t)c);
+  const int v = (int)(gid % (uint64_t)c);
+  if (y >= half_rows) return;
+  const uint32_t lo = y & ((1u << q) - 1u);
+  const uint32_t x0 = ((y >> q) << (q + 1)) | lo, x1 = x0 | (1u << q);
+  const C l0 = L[(size_t)x0 * ld + v], l1 = L[(size_t)x1 * ld + v];
+  for (int a = 0; a < m_pad; ++a) {
+    if (a >= ch.m) {   // unused Kraus slots of the padded column blocks
+      L[(size_t)x0 * ld + a * c + v] = cmk<C, T>((T)0, (T)0);
+      L[(size_t)x1 * ld + a * c + v] = cmk<C, T>((T)0, (T)0);
+      continue;
+    }
+    for (int bp = 0; bp < 2; ++bp) {
+      const C e0 = cmk<C, T>((T)ch.e[a][bp][0][0], (T)ch.e[a][bp][0][1]);
+      const C e1 = cmk<C, T>((T)ch.e[a][bp][1][0], (T)ch.e[a][bp][1][1]);
+      const C r = cadd(cmul(e0, l0), cmul(e1, l1));
+      L[(size_t)(bp ? x1 : x0) * ld + a * c + v] = r;
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_kraus_expand(cx_t<T>* L, int n, int ld, int c, int q, const Channel& ch,
+                               int m_pad, hipStream_t s) {
+  const uint64_t total = (uint64_t)(1u << (n - 1)) * (uint64_t)c;
+  const uint32_t blocks = (uint32_t)((total + 255) / 256);
+  hipLaunchKernelGGL(kraus_expand_kernel<T>, dim3(blocks), dim3(256), 0, s, L, 1u << (n - 1), ld,
+                     c, q, ch, m_pad);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void set_e0_kernel(cx_t<T>* L) {
+  L[0].x = (T)1;
+  L[0].y = (T)0;
+}
+
+template <class T>
+hipError_t launch_set_e0(cx_t<T>* L, hipStream_t s) {
+  hipLaunchKernelGGL(set_e0_kernel<T>, dim3(1), dim3(1), 0, s, L);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gate_pass<float>(const GatePass<float>&, float2*, hipStream_t);
+template hipError_t launch_gate_pass<double>(const GatePass<double>&, double2*, hipStream_t);
+template hipError_t launch_kraus_expand<float>(float2*, int, int, int, int, const Channel&, int, hipStream_t);
+template hipError_t launch_kraus_expand<double>(double2*, int, int, int, int, const Channel&, int, hipStream_t);
+template hipError_t launch_set_e0<float>(float2*, hipStream_t);
+template hipError_t launch_set_e0<double>(double2*, hipStream_t);
+
+}  // namespace lrdm

@@ -1,0 +1,265 @@
+// Gram matrix of the (split) factor on MFMA: the contraction step of the eigenvalue truncation
+// (Sec. II.B): G = L'^H L' (Theorem 1, App. B) is formed from S = X^H X, where X is the
+// factor viewed row by row.
+//
+//  * Split view (fused Kraus step): X = [L_0 | L_1], row y of X holds row x0 = y with a zero
+//    inserted at bit q followed by row x1 = x0 | 2^q, so X is 2^(n-1) x 2c.  For a channel on
+//    qubit q, (E_a L)_{b'} = sum_b (E_a)_{b'b} L_b, hence G_{ab} = sum_{uv} (E_a^H E_b)_{uv}
+//    L_u^H L_v: G follows from S without ever forming [E_1 L | ... | E_m L].
+//  * Plain view: X = L (2^n x c).
+//
+// Complex arithmetic runs on the real embedding X_r (interleaved re/im, F = 2 * nsplit * c real
+// columns): R = X_r^T X_r, S_jk = (R[2j,2k] + R[2j+1,2k+1]) + i (R[2j,2k+1] - R[2j+1,2k]).
+// R is a tall-skinny SYRK: only its upper 16x16 tiles are computed with v_mfma_*_16x16x4, each
+// work-group reduces a contiguous slab of rows into a private partial (split-K), and a second
+// kernel sums the partials in a fixed order in FP64 (deterministic).
+#include <utility>
+
+#include "lrdm_internal.h"
+
+namespace lrdm {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <class T> struct Acc4;
+template <> struct Acc4<float> { using type = v4f; };
+template <> struct Acc4<double> { using type = v4d; };
+
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NT> struct UpperTiles {
+  static constexpr int NUP = NT * (NT + 1) / 2;
+  int ti[NUP];
+  int tj[NUP];
+  constexpr UpperTiles() : ti(), tj() {
+    int u = 0;
+    for (int i = 0; i < NT; ++i)
+      for (int j = i; j < NT; ++j) {
+        ti[u] = i;
+        tj[u] = j;
+        ++u;
+      }
+  }
+};
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int kGramKC = 64;   // rows per LDS chunk
+
+template <class T, int F> struct GramCfg {
+  static constexpr int NT = F / 16;
+  static constexpr int NUP = NT * (NT + 1) / 2;
+  static constexpr int NW = (F >= 256) ? 8 : 4;            // waves per work-group
+  static constexpr int THREADS = 64 * NW;
+  static constexpr int PER_WAVE = (NUP + NW - 1) / NW;
+  static constexpr int STRIDE = F + 16;   // conflict-free 16-lane row reads
+};
+
+// One wave's share of the upper tiles: tile u = W + NW s.
+template <class T, int F, int W>
+__device__ __forceinline__ void gram_chunk_mma(const T* __restrict__ lds, typename Acc4<T>::type* acc,
+                                               int lane) {
+  using Cfg = GramCfg<T, F>;
+  constexpr UpperTiles<Cfg::NT> tab{};
+  const int m = lane & 15, k = lane >> 4;
+#pragma unroll 2
+  for (int kk = 0; kk < kGramKC / 4; ++kk) {
+    const T* row = lds + (4 * kk + k) * Cfg::STRIDE + m;
+    T f[Cfg::NT];
+#pragma unroll
+    for (int b = 0; b < Cfg::NT; ++b) f[b] = row[16 * b];
+    static_for<Cfg::PER_WAVE>([&](auto s) {
+      constexpr int u = W + Cfg::NW * decltype(s)::value;
+      if constexpr (u < Cfg::NUP) {
+        acc[decltype(s)::value] = mfma16(f[tab.ti[u]], f[tab.tj[u]], acc[decltype(s)::value]);
+      }
+    });
+  }
+}
+
+template <class T, int F, int W>
+__device__ __forceinline__ void gram_store(T* __restrict__ out, const typename Acc4<T>::type* acc,
+                                           int lane) {
+  using Cfg = GramCfg<T, F>;
+  static_for<Cfg::PER_WAVE>([&](auto s) {
+    constexpr int u = W + Cfg::NW * decltype(s)::value;
+    if constexpr (u < Cfg::NUP) {
+      typename Acc4<T>::type v = acc[decltype(s)::value];
+      *reinterpret_cast<typename Acc4<T>::type*>(out + (size_t)u * 256 + lane * 4) = v;
+    }
+  });
+}
+
+template <class T, int F>
+__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx_t<T>* __restrict__ L, int ld, int c,
+                                                      int nsplit, int q, T* __restrict__ partials,
+                                                      uint32_t rows, uint32_t rows_per_block) {
+  using Cfg = GramCfg<T, F>;
+  using A4 = typename Acc4<T>::type;
+  __shared__ __attribute__((aligned(16))) T lds[kGramKC * Cfg::STRIDE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  A4 acc[Cfg::PER_WAVE];
+#pragma unroll
+  for (int s = 0; s < Cfg::PER_WAVE; ++s) acc[s] = A4{0, 0, 0, 0};
+
+  constexpr int VPR = 16 / sizeof(T);          // reals per 16-byte unit
+  constexpr int UNITS = kGramKC * F / VPR;     // 16-byte units per chunk
+  const int seg = 2 * c;                       // reals per half-row segment
+  const uint32_t r_begin = blockIdx.x * rows_per_block;
+  const uint32_t r_end = min(rows, r_begin + rows_per_block);
+  const T* Lr = reinterpret_cast<const T*>(L);
+
+  for (uint32_t r0 = r_begin; r0 < r_end; r0 += kGramKC) {
+    // stage kGramKC rows of X_r into LDS (zeros past the end)
+#pragma unroll 4
+    for (int u = tid; u < UNITS; u += Cfg::THREADS) {
+      const int rr = u / (F / VPR);
+      const int f = (u % (F / VPR)) * VPR;
+      const uint32_t y = r0 + rr;
+      const int h = f / seg;
+      const int w = f - h * seg;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (y < r_end) {
+        uint32_t x = y;
+        if (nsplit == 2) {
+          const uint32_t lo = y & ((1u << q) - 1u);
+          x = (((y >> q) << (q + 1)) | lo) | ((uint32_t)h << q);
+        }
+        val = *reinterpret_cast<const float4*>(Lr + ((size_t)x * ld) * 2 + w);
+      }
+      *reinterpret_cast<float4*>(lds + rr * Cfg::STRIDE + f) = val;
+    }
+    __syncthreads();
+    switch (wave) {
+      case 0: gram_chunk_mma<T, F, 0>(lds, acc, lane); break;
+      case 1: gram_chunk_mma<T, F, 1>(lds, acc, lane); break;
+      case 2: gram_chunk_mma<T, F, 2>(lds, acc, lane); break;
+      case 3: gram_chunk_mma<T, F, 3>(lds, acc, lane); break;
+      case 4: if constexpr (Cfg::NW > 4) gram_chunk_mma<T, F, 4>(lds, acc, lane); break;
+      case 5: if constexpr (Cfg::NW > 5) gram_chunk_mma<T, F, 5>(lds, acc, lane); break;
+      case 6: if constexpr (Cfg::NW > 6) gram_chunk_mma<T, F, 6>(lds, acc, lane); break;
+      default: if constexpr (Cfg::NW > 7) gram_chunk_mma<T, F, 7>(lds, acc, lane); break;
+    }
+    __syncthreads();
+  }
+  T* out = partials + (size_t)blockIdx.x * Cfg::NUP * 256;
+  switch (wave) {
+    case 0: gram_store<T, F, 0>(out, acc, lane); break;
+    case 1: gram_store<T, F, 1>(out, acc, lane); break;
+    case 2: gram_store<T, F, 2>(out, acc, lane); break;
+    case 3: gram_store<T, F, 3>(out, acc, lane); break;
+    case 4: if constexpr (Cfg::NW > 4) gram_store<T, F, 4>(out, acc, lane); break;
+    case 5: if constexpr (Cfg::NW > 5) gram_store<T, F, 5>(out, acc, lane); break;
+    case 6: if constexpr (Cfg::NW > 6) gram_store<T, F, 6>(out, acc, lane); break;
+    default: if constexpr (Cfg::NW > 7) gram_store<T, F, 7>(out, acc, lane); break;
+  }
+}
+
+int gram_blocks(int n, int nsplit) {
+  const uint64_t rows = 1ull << (n - (nsplit == 2 ? 1 : 0));
+  const uint64_t chunks = (rows + kGramKC - 1) / kGramKC;
+  return (int)(chunks < 512 ? chunks : 512);
+}
+
+template <class T, int F>
+static hipError_t launch_gram_f(const cx_t<T>* L, int n, int ld, int c, int nsplit, int q,
+                                T* partials, int nblocks, hipStream_t s) {
+  const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
+  const uint32_t chunks = (rows + kGramKC - 1) / kGramKC;
+  const uint32_t cpb = (chunks + nblocks - 1) / nblocks;
+  hipLaunchKernelGGL((gram_kernel<T, F>), dim3(nblocks), dim3(GramCfg<T, F>::THREADS), 0, s, L, ld, c, nsplit, q,
+                     partials, rows, cpb * kGramKC);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_gram(const cx_t<T>* L, int n, int ld, int c, int nsplit, int q, T* partials,
+                       int nblocks, hipStream_t s) {
+  const int F = 2 * nsplit * c;
+  switch (F) {
+    case 16: return launch_gram_f<T, 16>(L, n, ld, c, nsplit, q, partials, nblocks, s);
+    case 32: return launch_gram_f<T, 32>(L, n, ld, c, nsplit, q, partials, nblocks, s);
+    case 64: return launch_gram_f<T, 64>(L, n, ld, c, nsplit, q, partials, nblocks, s);
+    case 128: return launch_gram_f<T, 128>(L, n, ld, c, nsplit, q, partials, nblocks, s);
+    case 256:
+      if constexpr (sizeof(T) == 4) return launch_gram_f<T, 256>(L, n, ld, c, nsplit, q, partials, nblocks, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Sum the split-K partials of one upper tile (fixed order, FP64) and convert the real tile of
+// R into the complex entries of S it covers.
+template <class T>
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ partials, int nblocks,
+                                                          int NT, int NUP, double* __restrict__ S) {
+  __shared__ double R[16][17];
+  const int u = blockIdx.x;
+  int ti = 0, rem = u;
+  while (rem >= NT - ti) {
+    rem -= NT - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const int e = threadIdx.x;
+  const T* p = partials + (size_t)u * 256 + e;
+  const size_t stride = (size_t)NUP * 256;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int b = 0;
+  for (; b + 4 <= nblocks; b += 4) {
+    s0 += (double)p[(size_t)(b + 0) * stride];
+    s1 += (double)p[(size_t)(b + 1) * stride];
+    s2 += (double)p[(size_t)(b + 2) * stride];
+    s3 += (double)p[(size_t)(b + 3) * stride];
+  }
+  for (; b < nblocks; ++b) s0 += (double)p[(size_t)b * stride];
+  const double sum = (s0 + s1) + (s2 + s3);
+  const int lane = e >> 2, v = e & 3;
+  // 16x16x4 MFMA output layout: column lane % 16; row 4 (lane / 16) + v for FP32, but
+  // 4 v + lane / 16 for FP64
+  const int row = (sizeof(T) == 8) ? (4 * v + (lane >> 4)) : (4 * (lane >> 4) + v);
+  R[row][lane & 15] = sum;
+  __syncthreads();
+  if (e < 64) {
+    const int jl = e >> 3, kl = e & 7;   // complex entry inside the tile
+    const double re = R[2 * jl][2 * kl] + R[2 * jl + 1][2 * kl + 1];
+    const double im = R[2 * jl][2 * kl + 1] - R[2 * jl + 1][2 * kl];
+    const int Fc = NT * 8;
+    const int j = 8 * ti + jl, k = 8 * tj + kl;
+    S[2 * ((size_t)j * Fc + k)] = re;
+    S[2 * ((size_t)j * Fc + k) + 1] = im;
+    if (ti != tj) {
+      S[2 * ((size_t)k * Fc + j)] = re;
+      S[2 * ((size_t)k * Fc + j) + 1] = -im;
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_gram_reduce(const T* partials, int nblocks, int F, double* S, hipStream_t s) {
+  const int NT = F / 16;
+  const int NUP = NT * (NT + 1) / 2;
+  hipLaunchKernelGGL(gram_reduce_kernel<T>, dim3(NUP), dim3(256), 0, s, partials, nblocks, NT, NUP, S);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gram<float>(const float2*, int, int, int, int, int, float*, int, hipStream_t);
+template hipError_t launch_gram<double>(const double2*, int, int, int, int, int, double*, int, hipStream_t);
+template hipError_t launch_gram_reduce<float>(const float*, int, int, double*, hipStream_t);
+template hipError_t launch_gram_reduce<double>(const double*, int, int, double*, hipStream_t);
+
+}  // namespace lrdm

@@ -1,0 +1,742 @@
+// Host runtime of liblrdm: argument validation, the gate-pass scheduler, the compression
+// pipeline (Gram -> FP64 eigensolve -> projection) and the output reductions, behind the C ABI
+// declared in include/lrdm.h.  No device memory is allocated here: every device buffer is
+// carved out of the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrdm_internal.h"
+
+using namespace lrdm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxTerms = 65536;
+constexpr int kSampleBatch = 1 << 20;
+constexpr size_t kPauliPartDoubles = 4u << 20;
+constexpr int kZBlocks = 256;
+constexpr int kMaxTimed = 8192;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+struct Layout {
+  int r_pad, m_pad, ld, F_max, FO_max;
+  size_t state_bytes;
+  size_t off_info, off_part, off_S, off_P, off_d, off_e, off_tau, off_lam, off_Y, off_lu, off_trace,
+      off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
+};
+
+bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
+                    std::string& why) {
+  if (n < 1 || n > 30) { why = "n must be in [1, 30]"; return false; }
+  if (r_max < 1 || r_max > 64) { why = "r_max must be in [1, 64]"; return false; }
+  if (m_max < 1 || m_max > 4) { why = "m_max must be in [1, 4]"; return false; }
+  if (dt != LRDM_C64 && dt != LRDM_C128) { why = "unknown dtype"; return false; }
+  const bool plain = flags & LRDM_FLAG_PLAIN;
+  L.r_pad = std::max(8, next_pow2(r_max));
+  L.m_pad = next_pow2(m_max);
+  if (m_max * L.r_pad > kMaxEig) { why = "m_max * r_pad exceeds 128 (largest Gram order)"; return false; }
+  if (dt == LRDM_C128 && L.r_pad > 32) { why = "complex128 supports r_pad <= 32"; return false; }
+  L.ld = plain ? L.m_pad * L.r_pad : L.r_pad;
+  if (plain && 2 * L.ld > (dt == LRDM_C64 ? 256 : 128)) { why = "plain form exceeds the GEMM width"; return false; }
+  L.F_max = std::max(4 * L.r_pad, 2 * L.ld);
+  L.FO_max = 4 * L.r_pad;
+  const size_t cs = (dt == LRDM_C64) ? 8 : 16;   // bytes per complex
+  const size_t rs = cs / 2;                        // bytes per real
+  const size_t rows = 1ull << n;
+  L.state_bytes = rows * L.ld * cs;
+  const int NT = L.F_max / 16;
+  const int NUP = NT * (NT + 1) / 2;
+  const int nb = gram_blocks(n, 1);
+  const int Fc = L.F_max / 2;
+  const int N = kMaxEig;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+  L.off_info = take(sizeof(DevInfo));
+  L.off_part = take((size_t)nb * NUP * 256 * rs);
+  L.off_S = take((size_t)Fc * Fc * 16);
+  L.off_P = take((size_t)N * (N + 1) / 2 * 16);
+  L.off_d = take(N * 8);
+  L.off_e = take(N * 8);
+  L.off_tau = take(2 * N * 8);
+  L.off_lam = take(N * 8);
+  L.off_Y = take((size_t)N * N * 8);
+  L.off_lu = take((size_t)5 * N * N * 8);
+  L.off_trace = take(64);
+  L.off_W = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
+  L.off_out = take(4096 * 8);
+  L.off_pbuf = take(rows * 8 + (size_t)kZBlocks * 64 * 8);
+  L.off_cdf = take(rows * 8);
+  L.off_bsum = take(((rows + 1023) / 1024) * 8);
+  L.off_terms = take((size_t)kMaxTerms * 16 + (size_t)(kMaxTerms + 1) * 4);
+  L.off_pauli = take(kPauliPartDoubles * 8);
+  L.off_unif = take((size_t)kSampleBatch * 8);
+  L.off_samp = take((size_t)kSampleBatch * 8);
+  L.total = o;
+  return true;
+}
+
+struct PendingGate {
+  int type;          // GateOpType
+  int q0, q1;        // qubits (q1 = -1 for 1q); OP_WEIGHT uses neither
+  uint32_t qmask;    // qubits the gate touches (all qubits for OP_WEIGHT)
+  std::vector<double> coef;
+};
+
+}  // namespace
+
+struct lrdm_ctx {
+  int n = 0, r_max = 0, m_max = 0;
+  lrdm_dtype dt = LRDM_C64;
+  unsigned flags = 0;
+  bool plain = false;
+  Layout lay{};
+  void* state = nullptr;
+  char* work = nullptr;
+  hipStream_t stream = nullptr;
+  int ncols = 0;      // active columns in the state layout
+  int c_bound = 1;    // host bound on non-zero columns
+  bool poisoned = false;
+  std::string err;
+  std::vector<PendingGate> gates;
+  bool chan_pending = false;
+  int chan_q = 0;
+  Channel chan{};
+  // timing
+  int timing_class = -1;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  // host staging
+  std::vector<uint64_t> term_stage;
+
+  template <class P> P* ws(size_t off) { return reinterpret_cast<P*>(work + off); }
+};
+
+namespace {
+
+lrdm_status fail(lrdm_t h, lrdm_status st, const std::string& msg) {
+  g_last_error = msg;
+  if (h) h->err = msg;
+  return st;
+}
+
+lrdm_status hip_check(lrdm_t h, hipError_t e, const char* where) {
+  if (e == hipSuccess) return LRDM_OK;
+  h->poisoned = true;
+  return fail(h, LRDM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                         \
+  do {                                                          \
+    lrdm_status _s = hip_check((h), (expr), #expr);             \
+    if (_s != LRDM_OK) return _s;                               \
+  } while (0)
+
+lrdm_status check_usable(lrdm_t h) {
+  if (!h) return fail(nullptr, LRDM_E_ARG, "null handle");
+  if (h->poisoned) return fail(h, LRDM_E_STATE, "handle is poisoned by an earlier device error: " + h->err);
+  return LRDM_OK;
+}
+
+// Sync the stream and check the device-side eigensolver status.
+lrdm_status sync_and_check(lrdm_t h) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  DevInfo info;
+  HIPCHK(h, hipMemcpy(&info, h->ws<DevInfo>(h->lay.off_info), sizeof(info), hipMemcpyDeviceToHost));
+  if (info.status != 0) {
+    h->poisoned = true;
+    return fail(h, LRDM_E_EIG, "eigensolver reported a non-finite or empty Gram matrix");
+  }
+  return LRDM_OK;
+}
+
+void timed_begin(lrdm_t h, int cls) {
+  if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
+  hipEventRecord(h->ev[h->ev_used], h->stream);
+}
+void timed_end(lrdm_t h, int cls) {
+  if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
+  hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+  h->ev_used += 2;
+}
+
+bool is_unitary(const double* u, int d) {
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double re = 0, im = 0;
+      for (int k = 0; k < d; ++k) {
+        const double ar = u[2 * (k * d + i)], ai = -u[2 * (k * d + i) + 1];   // conj(U_ki)
+        const double br = u[2 * (k * d + j)], bi = u[2 * (k * d + j) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      if (std::fabs(re - (i == j ? 1.0 : 0.0)) > 1e-10 || std::fabs(im) > 1e-10) return false;
+      if (!std::isfinite(re) || !std::isfinite(im)) return false;
+    }
+  return true;
+}
+
+template <class T> void fill_coef(GatePass<T>& p, int& nc, const std::vector<double>& c) {
+  for (double v : c) p.coef[nc++] = (T)v;
+}
+
+// Local qubits per pass: the tile of 2^k rows x ncols complex values must fit 64 KB of LDS.
+int local_budget(int n, int ncols, size_t csize) {
+  int k = 0;
+  while (k < 8 && k < n && ((size_t)ncols << (k + 1)) * csize <= 65536) ++k;
+  return k;
+}
+
+template <class T>
+lrdm_status flush_gates_t(lrdm_t h) {
+  const int kloc_max = local_budget(h->n, h->ncols, sizeof(cx_t<T>));
+  std::vector<char> placed(h->gates.size(), 0);
+  size_t remaining = h->gates.size();
+  while (remaining > 0) {
+    GatePass<T> p;
+    std::memset(&p, 0, sizeof(p));
+    p.n = h->n;
+    p.ld = h->lay.ld;
+    p.ncols = h->ncols;
+    int nloc = 0, nc = 0;
+    uint32_t locmask = 0, blocked = 0;
+    std::vector<size_t> order;
+    for (size_t gi = 0; gi < h->gates.size(); ++gi) {
+      if (placed[gi]) continue;
+      const PendingGate& g = h->gates[gi];
+      if (g.qmask & blocked) { blocked |= g.qmask; continue; }
+      const bool diag = (g.type == OP_DIAG1 || g.type == OP_DIAG2 || g.type == OP_WEIGHT);
+      const bool room = p.n_ops < kGateMaxOps && nc + (int)g.coef.size() <= kGateMaxCoef;
+      if (!room) { blocked = ~0u; continue; }
+      if (!diag) {
+        const uint32_t need = g.qmask & ~locmask;
+        if (nloc + __builtin_popcount(need) > kloc_max) { blocked |= g.qmask; continue; }
+        for (int q = 0; q < h->n; ++q)
+          if (need & (1u << q)) { p.local_q[nloc++] = q; locmask |= 1u << q; }
+      }
+      // encode
+      const int o = p.n_ops++;
+      p.op_type[o] = g.type;
+      p.op_coef[o] = nc;
+      auto lidx = [&](int q) { for (int j = 0; j < nloc; ++j) if (p.local_q[j] == q) return j; return -1; };
+      if (g.type == OP_1Q) { p.op_a[o] = lidx(g.q0); }
+      else if (g.type == OP_2Q) { p.op_a[o] = lidx(g.q0); p.op_b[o] = lidx(g.q1); }
+      else { p.op_a[o] = g.q0; p.op_b[o] = g.q1; }
+      fill_coef(p, nc, g.coef);
+      placed[gi] = 1;
+      --remaining;
+    }
+    // pad the local set with unused low qubits so that every pass works on full-size tiles
+    for (int q = 0; q < h->n && nloc < kloc_max; ++q)
+      if (!(locmask & (1u << q))) { p.local_q[nloc++] = q; locmask |= 1u << q; }
+    p.k = nloc;
+    int sorted[8];
+    for (int j = 0; j < nloc; ++j) sorted[j] = p.local_q[j];
+    std::sort(sorted, sorted + nloc);
+    for (int j = 0; j < nloc; ++j) p.sorted_q[j] = sorted[j];
+    timed_begin(h, 0);
+    HIPCHK(h, launch_gate_pass<T>(p, static_cast<cx_t<T>*>(h->state), h->stream));
+    timed_end(h, 0);
+  }
+  h->gates.clear();
+  return LRDM_OK;
+}
+
+lrdm_status flush_gates(lrdm_t h) {
+  if (h->gates.empty()) return LRDM_OK;
+  return h->dt == LRDM_C64 ? flush_gates_t<float>(h) : flush_gates_t<double>(h);
+}
+
+lrdm_status ready_for_output(lrdm_t h) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  return flush_gates(h);
+}
+
+EigBufs eig_bufs(lrdm_t h) {
+  EigBufs b;
+  b.S = h->ws<double>(h->lay.off_S);
+  b.P = h->ws<double>(h->lay.off_P);
+  b.d = h->ws<double>(h->lay.off_d);
+  b.e = h->ws<double>(h->lay.off_e);
+  b.tau = h->ws<double>(h->lay.off_tau);
+  b.lam = h->ws<double>(h->lay.off_lam);
+  b.Y = h->ws<double>(h->lay.off_Y);
+  b.lu = h->ws<double>(h->lay.off_lu);
+  b.trace = h->ws<double>(h->lay.off_trace);
+  b.info = h->ws<DevInfo>(h->lay.off_info);
+  return b;
+}
+
+template <class T>
+lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm) {
+  const int nsplit = (h->chan_pending && !h->plain) ? 2 : 1;
+  const int q = nsplit == 2 ? h->chan_q : 0;
+  Channel ch{};
+  int c, N, F;
+  if (nsplit == 2) {
+    ch = h->chan;
+    c = h->lay.r_pad;
+    N = ch.m * c;
+    F = 4 * c;
+  } else {
+    ch.m = 1;
+    c = h->ncols;
+    N = c;
+    F = 2 * c;
+  }
+  const int Fc = F / 2;
+  const int kmax = std::min(r_target + 1, N);
+  const int c_out = h->lay.r_pad;
+  const int nb = gram_blocks(h->n, nsplit);
+  EigBufs b = eig_bufs(h);
+  auto* L = static_cast<cx_t<T>*>(h->state);
+  T* part = h->ws<T>(h->lay.off_part);
+  cx_t<T>* W = h->ws<cx_t<T>>(h->lay.off_W);
+  timed_begin(h, 1);
+  HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
+  timed_end(h, 1);
+  timed_begin(h, 2);
+  HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
+  timed_end(h, 2);
+  timed_begin(h, 3);
+  HIPCHK(h, launch_eig_tridiag(b.S, Fc, ch, nsplit, c, N, b, h->stream));
+  HIPCHK(h, launch_eig_solve(N, kmax, b, h->stream));
+  HIPCHK(h, launch_eig_finish<T>(N, kmax, r_target, eps, tie, renorm, ch, nsplit, c, c_out, b, W,
+                                 h->stream));
+  timed_end(h, 3);
+  timed_begin(h, 4);
+  HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W, h->stream));
+  timed_end(h, 4);
+  h->ncols = c_out;
+  const int grown = (nsplit == 2) ? h->c_bound * ch.m : h->c_bound;
+  h->c_bound = std::min(std::min(grown, r_target), N);
+  h->chan_pending = false;
+  return LRDM_OK;
+}
+
+template <class T>
+lrdm_status reset_t(lrdm_t h) {
+  HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
+  HIPCHK(h, launch_set_e0<T>(static_cast<cx_t<T>*>(h->state), h->stream));
+  h->ncols = h->lay.r_pad;
+  h->c_bound = 1;
+  h->gates.clear();
+  h->chan_pending = false;
+  return LRDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lrdm_version(void) { return "lrdm 0.1 (gfx950)"; }
+
+const char* lrdm_last_error(lrdm_t h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+lrdm_status lrdm_workspace_size(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags,
+                                size_t* state_bytes, size_t* work_bytes) {
+  if (!state_bytes || !work_bytes) return fail(nullptr, LRDM_E_ARG, "null output pointer");
+  Layout L;
+  std::string why;
+  if (!compute_layout(n, r_max, dt, m_max, flags, L, why)) {
+    const bool range = (n < 1 || n > 30 || r_max < 1 || r_max > 64 || m_max < 1 || m_max > 4 ||
+                        (dt != LRDM_C64 && dt != LRDM_C128));
+    return fail(nullptr, range ? LRDM_E_ARG : LRDM_E_UNSUPPORTED, why);
+  }
+  *state_bytes = L.state_bytes;
+  *work_bytes = L.total;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_init(lrdm_t* out, int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags,
+                      void* state_dev, size_t state_bytes, void* work_dev, size_t work_bytes,
+                      void* hip_stream) {
+  if (!out) return fail(nullptr, LRDM_E_ARG, "null output handle pointer");
+  *out = nullptr;
+  Layout L;
+  std::string why;
+  if (!compute_layout(n, r_max, dt, m_max, flags, L, why)) return fail(nullptr, LRDM_E_ARG, why);
+  if (!state_dev || !work_dev) return fail(nullptr, LRDM_E_ARG, "null device buffer");
+  if (state_bytes < L.state_bytes || work_bytes < L.total)
+    return fail(nullptr, LRDM_E_NOMEM, "state or workspace buffer smaller than lrdm_workspace_size");
+  if ((reinterpret_cast<uintptr_t>(state_dev) | reinterpret_cast<uintptr_t>(work_dev)) & 255)
+    return fail(nullptr, LRDM_E_ARG, "device buffers must be 256-byte aligned");
+  lrdm_ctx* h = new lrdm_ctx();
+  h->n = n;
+  h->r_max = r_max;
+  h->m_max = m_max;
+  h->dt = dt;
+  h->flags = flags;
+  h->plain = flags & LRDM_FLAG_PLAIN;
+  h->lay = L;
+  h->state = state_dev;
+  h->work = static_cast<char*>(work_dev);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  lrdm_status st = dt == LRDM_C64 ? reset_t<float>(h) : reset_t<double>(h);
+  if (st != LRDM_OK) {
+    g_last_error = h->err;
+    delete h;
+    return st;
+  }
+  *out = h;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_reset(lrdm_t h) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  return h->dt == LRDM_C64 ? reset_t<float>(h) : reset_t<double>(h);
+}
+
+lrdm_status lrdm_destroy(lrdm_t h) {
+  if (!h) return fail(nullptr, LRDM_E_ARG, "null handle");
+  for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  delete h;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_apply_gate(lrdm_t h, int k, const int* qubits, const double* u) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (k != 1 && k != 2) return fail(h, LRDM_E_ARG, "k must be 1 or 2");
+  if (!qubits || !u) return fail(h, LRDM_E_ARG, "null qubits or matrix");
+  for (int j = 0; j < k; ++j)
+    if (qubits[j] < 0 || qubits[j] >= h->n) return fail(h, LRDM_E_ARG, "qubit out of range");
+  if (k == 2 && qubits[0] == qubits[1]) return fail(h, LRDM_E_ARG, "repeated qubit");
+  const int d = 1 << k;
+  if (!is_unitary(u, d)) return fail(h, LRDM_E_ARG, "gate matrix is not unitary within 1e-10");
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  bool diag = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (i != j && (u[2 * (i * d + j)] != 0.0 || u[2 * (i * d + j) + 1] != 0.0)) diag = false;
+  PendingGate g;
+  g.q0 = qubits[0];
+  g.q1 = (k == 2) ? qubits[1] : -1;
+  g.qmask = (1u << qubits[0]) | (k == 2 ? (1u << qubits[1]) : 0u);
+  if (diag) {
+    g.type = (k == 1) ? OP_DIAG1 : OP_DIAG2;
+    for (int i = 0; i < d; ++i) {
+      g.coef.push_back(u[2 * (i * d + i)]);
+      g.coef.push_back(u[2 * (i * d + i) + 1]);
+    }
+  } else {
+    g.type = (k == 1) ? OP_1Q : OP_2Q;
+    g.coef.assign(u, u + 2 * d * d);
+  }
+  h->gates.push_back(std::move(g));
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_apply_diagonal_weight(lrdm_t h, const double* phase) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (!phase) return fail(h, LRDM_E_ARG, "null phase table");
+  for (int w = 0; w <= h->n; ++w) {
+    const double m = std::hypot(phase[2 * w], phase[2 * w + 1]);
+    if (!(std::fabs(m - 1.0) <= 1e-10)) return fail(h, LRDM_E_ARG, "phase entries must have unit modulus");
+  }
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  PendingGate g;
+  g.type = OP_WEIGHT;
+  g.q0 = g.q1 = -1;
+  g.qmask = (h->n >= 32) ? ~0u : ((1u << h->n) - 1u);
+  g.coef.assign(phase, phase + 2 * (h->n + 1));
+  h->gates.push_back(std::move(g));
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (qubit < 0 || qubit >= h->n) return fail(h, LRDM_E_ARG, "qubit out of range");
+  if (m < 1 || m > h->m_max) return fail(h, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
+  if (!e) return fail(h, LRDM_E_ARG, "null Kraus matrices");
+  // completeness sum_a E_a^H E_a = I
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double re = 0, im = 0;
+      for (int a = 0; a < m; ++a)
+        for (int r = 0; r < 2; ++r) {
+          const double ar = e[((a * 2 + r) * 2 + i) * 2], ai = -e[((a * 2 + r) * 2 + i) * 2 + 1];
+          const double br = e[((a * 2 + r) * 2 + j) * 2], bi = e[((a * 2 + r) * 2 + j) * 2 + 1];
+          re += ar * br - ai * bi;
+          im += ar * bi + ai * br;
+        }
+      if (!(std::fabs(re - (i == j)) <= 1e-10 && std::fabs(im) <= 1e-10))
+        return fail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
+    }
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is already pending: compress first");
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  Channel ch{};
+  ch.m = m;
+  for (int a = 0; a < m; ++a)
+    for (int r = 0; r < 2; ++r)
+      for (int cidx = 0; cidx < 2; ++cidx)
+        for (int z = 0; z < 2; ++z) ch.e[a][r][cidx][z] = e[((a * 2 + r) * 2 + cidx) * 2 + z];
+  if (h->plain) {
+    const int c = h->ncols;
+    hipError_t he = h->dt == LRDM_C64
+                        ? launch_kraus_expand<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, c,
+                                                     qubit, ch, h->lay.m_pad, h->stream)
+                        : launch_kraus_expand<double>(static_cast<double2*>(h->state), h->n, h->lay.ld,
+                                                      c, qubit, ch, h->lay.m_pad, h->stream);
+    HIPCHK(h, he);
+    h->ncols = c * h->lay.m_pad;
+    h->c_bound = std::min(h->c_bound * m, h->ncols);
+    h->chan_pending = true;   // compress must follow (same contract as the fused form)
+    h->chan_q = qubit;
+    h->chan = ch;
+    return LRDM_OK;
+  }
+  h->chan_pending = true;
+  h->chan_q = qubit;
+  h->chan = ch;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_compress(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
+                          lrdm_compress_info* info) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (r_target < 1 || r_target > h->r_max) return fail(h, LRDM_E_ARG, "r_target must be in [1, r_max]");
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(h, LRDM_E_ARG, "eps must be in [0, 1)");
+  if (tie_policy != 0 && tie_policy != 1) return fail(h, LRDM_E_ARG, "tie_policy must be 0 or 1");
+  if (renorm != 0 && renorm != 1) return fail(h, LRDM_E_ARG, "renorm must be 0 or 1");
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  st = h->dt == LRDM_C64 ? compress_t<float>(h, r_target, eps, tie_policy, renorm)
+                         : compress_t<double>(h, r_target, eps, tie_policy, renorm);
+  if (st != LRDM_OK) return st;
+  if (info) {
+    st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+    DevInfo d;
+    HIPCHK(h, hipMemcpy(&d, h->ws<DevInfo>(h->lay.off_info), sizeof(d), hipMemcpyDeviceToHost));
+    info->rank = d.k;
+    info->n_eig = d.n_eig;
+    info->discarded = d.discarded;
+    info->discarded_total = d.discarded_total;
+    info->trace_before = d.trace;
+    info->boundary_gap = d.gap;
+    info->lambda_max = d.lambda_max;
+  }
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_probabilities(lrdm_t h, double* p_dev) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (!p_dev) return fail(h, LRDM_E_ARG, "null output buffer");
+  hipError_t e = h->dt == LRDM_C64
+                     ? launch_probabilities<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, p_dev, h->stream)
+                     : launch_probabilities<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, p_dev, h->stream);
+  HIPCHK(h, e);
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_expect_z(lrdm_t h, double* z_host, double* zz_host, double* trace_host) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (!z_host) return fail(h, LRDM_E_ARG, "null z output");
+  double* pbuf = h->ws<double>(h->lay.off_pbuf);
+  double* out = h->ws<double>(h->lay.off_out);
+  hipError_t e = h->dt == LRDM_C64
+                     ? launch_zstats<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, pbuf, kZBlocks, out, h->stream)
+                     : launch_zstats<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, pbuf, kZBlocks, out, h->stream);
+  HIPCHK(h, e);
+  std::vector<double> r(2 * h->n);
+  HIPCHK(h, hipMemcpyAsync(r.data(), out, r.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  st = sync_and_check(h);
+  if (st != LRDM_OK) return st;
+  const double tot = r[0];
+  for (int i = 0; i < h->n; ++i) z_host[i] = tot - 2.0 * r[1 + i];
+  if (zz_host)
+    for (int i = 0; i + 1 < h->n; ++i) zz_host[i] = tot - 2.0 * r[1 + h->n + i];
+  if (trace_host) *trace_host = tot;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_expect_pauli(lrdm_t h, int n_terms, const uint64_t* xmask, const uint64_t* zmask,
+                              const double* coeff, int summed, double* out_host) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (n_terms < 1 || n_terms > kMaxTerms) return fail(h, LRDM_E_ARG, "n_terms must be in [1, 65536]");
+  if (!xmask || !zmask || !out_host || (summed && !coeff)) return fail(h, LRDM_E_ARG, "null argument");
+  if (summed != 0 && summed != 1) return fail(h, LRDM_E_ARG, "summed must be 0 or 1");
+  const uint64_t lim = (h->n >= 64) ? ~0ull : ((1ull << h->n) - 1ull);
+  for (int t = 0; t < n_terms; ++t)
+    if ((xmask[t] & ~lim) || (zmask[t] & ~lim)) return fail(h, LRDM_E_ARG, "Pauli mask beyond n qubits");
+  // group terms by X mask
+  std::vector<int> idx(n_terms);
+  for (int t = 0; t < n_terms; ++t) idx[t] = t;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
+  const uint32_t rows = 1u << h->n;
+  const int nchunks = (int)((rows + 1023) / 1024);
+  const int batch_cap = std::max(1, (int)(kPauliPartDoubles / (2 * (size_t)nchunks)));
+  std::vector<double> vals(n_terms);
+  uint64_t* dterms = h->ws<uint64_t>(h->lay.off_terms);
+  double* dpart = h->ws<double>(h->lay.off_pauli);
+  double* dout = h->ws<double>(h->lay.off_out);
+  for (int b0 = 0; b0 < n_terms; b0 += std::min(batch_cap, 4096)) {
+    const int nb = std::min(n_terms - b0, std::min(batch_cap, 4096));
+    // staging: xm[nb], zm[nb], gstart[ngroups + 1] (int)
+    std::vector<uint64_t> xm(nb), zm(nb);
+    std::vector<int> gstart;
+    for (int t = 0; t < nb; ++t) {
+      xm[t] = xmask[idx[b0 + t]];
+      zm[t] = zmask[idx[b0 + t]];
+      if (t == 0 || xm[t] != xm[t - 1]) gstart.push_back(t);
+    }
+    const int ngroups = (int)gstart.size();
+    gstart.push_back(nb);
+    h->term_stage.assign(2 * nb + (gstart.size() + 1) / 2 + 1, 0);
+    std::memcpy(h->term_stage.data(), xm.data(), nb * 8);
+    std::memcpy(h->term_stage.data() + nb, zm.data(), nb * 8);
+    std::memcpy(h->term_stage.data() + 2 * nb, gstart.data(), gstart.size() * 4);
+    HIPCHK(h, hipMemcpyAsync(dterms, h->term_stage.data(), h->term_stage.size() * 8, hipMemcpyHostToDevice, h->stream));
+    hipError_t e = h->dt == LRDM_C64
+                       ? launch_pauli<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, h->stream)
+                       : launch_pauli<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, h->stream);
+    HIPCHK(h, e);
+    std::vector<double> r(nb);
+    HIPCHK(h, hipMemcpyAsync(r.data(), dout, nb * 8, hipMemcpyDeviceToHost, h->stream));
+    st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+    for (int t = 0; t < nb; ++t) vals[idx[b0 + t]] = r[t];
+  }
+  if (summed) {
+    double s = 0;
+    for (int t = 0; t < n_terms; ++t) s += coeff[t] * vals[t];
+    out_host[0] = s;
+  } else {
+    for (int t = 0; t < n_terms; ++t) out_host[t] = vals[t];
+  }
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_sample(lrdm_t h, int count, const double* uniforms, uint64_t* out_host) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (count < 1 || count > (1 << 24)) return fail(h, LRDM_E_ARG, "count must be in [1, 2^24]");
+  if (!uniforms || !out_host) return fail(h, LRDM_E_ARG, "null argument");
+  for (int j = 0; j < count; ++j)
+    if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0)) return fail(h, LRDM_E_ARG, "uniforms must lie in [0, 1)");
+  double* p = h->ws<double>(h->lay.off_pbuf);
+  hipError_t e = h->dt == LRDM_C64
+                     ? launch_probabilities<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, p, h->stream)
+                     : launch_probabilities<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, p, h->stream);
+  HIPCHK(h, e);
+  double* du = h->ws<double>(h->lay.off_unif);
+  uint64_t* ds = h->ws<uint64_t>(h->lay.off_samp);
+  for (int b0 = 0; b0 < count; b0 += kSampleBatch) {
+    const int nb = std::min(count - b0, kSampleBatch);
+    HIPCHK(h, hipMemcpyAsync(du, uniforms + b0, (size_t)nb * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_sample(p, h->n, h->ws<double>(h->lay.off_cdf), h->ws<double>(h->lay.off_bsum), du, nb, ds, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out_host + b0, ds, (size_t)nb * 8, hipMemcpyDeviceToHost, h->stream));
+    st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+  }
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_get_L(lrdm_t h, void* dst, int to_host, int* rank_out) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (!dst) return fail(h, LRDM_E_ARG, "null destination");
+  // only the active columns carry the factor (plain form leaves stale expansion columns
+  // beyond them); the rest of every row is returned as zeros
+  const size_t cs = (h->dt == LRDM_C64) ? 8 : 16;
+  const size_t rows = 1ull << h->n;
+  if (to_host)
+    std::memset(dst, 0, h->lay.state_bytes);
+  else
+    HIPCHK(h, hipMemsetAsync(dst, 0, h->lay.state_bytes, h->stream));
+  HIPCHK(h, hipMemcpy2DAsync(dst, h->lay.ld * cs, h->state, h->lay.ld * cs, h->ncols * cs, rows,
+                             to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, h->stream));
+  if (to_host) {
+    st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+  }
+  if (rank_out) *rank_out = h->c_bound;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (!src) return fail(h, LRDM_E_ARG, "null source");
+  if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  h->gates.clear();
+  const size_t cs = (h->dt == LRDM_C64) ? 8 : 16;
+  const size_t rows = 1ull << h->n;
+  HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
+  HIPCHK(h, hipMemcpy2DAsync(h->state, h->lay.ld * cs, src, rank * cs, rank * cs, rows,
+                             from_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, h->stream));
+  if (from_host) HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->ncols = h->lay.r_pad;
+  h->c_bound = rank;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_synchronize(lrdm_t h) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  return sync_and_check(h);
+}
+
+lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (kernel_class < 0 || kernel_class > 4) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 4]");
+  if (h->ev.empty()) {
+    h->ev.resize(2 * kMaxTimed);
+    for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
+  }
+  h->timing_class = kernel_class;
+  h->ev_used = 0;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* total_ms) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  double tot = 0;
+  const int nl = h->ev_used / 2;
+  for (int i = 0; i < nl; ++i) {
+    float ms = 0;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+    tot += ms;
+  }
+  if (launches) *launches = nl;
+  if (total_ms) *total_ms = tot;
+  if (mean_ms) *mean_ms = nl ? tot / nl : 0.0;
+  h->timing_class = -1;
+  h->ev_used = 0;
+  return LRDM_OK;
+}
+
+}  // extern "C"

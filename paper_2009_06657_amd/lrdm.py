@@ -1,0 +1,250 @@
+"""Python binding of liblrdm (argument marshalling only).
+
+Every step of the low-rank evolution runs in the HIP library; this module converts NumPy
+matrices to the FP64 interleaved layout of include/lrdm.h, allocates the caller-owned device
+buffers with torch, and passes pointers and the current HIP stream through ctypes.  It raises
+if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrdm.so")
+
+C64, C128 = 0, 1
+FLAG_PLAIN = 0x1
+STATUS = {0: "LRDM_OK", 1: "LRDM_E_ARG", 2: "LRDM_E_NOMEM", 3: "LRDM_E_HIP", 4: "LRDM_E_EIG",
+          5: "LRDM_E_STATE", 6: "LRDM_E_UNSUPPORTED"}
+SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lrdm_apply_gate",
+           "lrdm_apply_diagonal_weight", "lrdm_apply_kraus", "lrdm_compress", "lrdm_probabilities",
+           "lrdm_expect_pauli", "lrdm_expect_z", "lrdm_sample", "lrdm_get_L", "lrdm_set_L",
+           "lrdm_synchronize", "lrdm_timing_begin", "lrdm_timing_end", "lrdm_last_error",
+           "lrdm_version"]
+
+
+class LrdmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CompressInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int), ("n_eig", ctypes.c_int), ("discarded", ctypes.c_double),
+                ("discarded_total", ctypes.c_double), ("trace_before", ctypes.c_double),
+                ("boundary_gap", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblrdm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2009_06657_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I, D, U, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lrdm_workspace_size": [I, I, I, I, U, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
+        "lrdm_init": [ctypes.POINTER(P), I, I, I, I, U, P, SZ, P, SZ, P],
+        "lrdm_reset": [P],
+        "lrdm_destroy": [P],
+        "lrdm_apply_gate": [P, I, ctypes.POINTER(I), dp],
+        "lrdm_apply_diagonal_weight": [P, dp],
+        "lrdm_apply_kraus": [P, I, I, dp],
+        "lrdm_compress": [P, I, D, I, I, ctypes.POINTER(CompressInfo)],
+        "lrdm_probabilities": [P, P],
+        "lrdm_expect_pauli": [P, I, P, P, P, I, dp],
+        "lrdm_expect_z": [P, dp, dp, dp],
+        "lrdm_sample": [P, I, dp, ctypes.POINTER(ctypes.c_uint64)],
+        "lrdm_get_L": [P, P, I, ctypes.POINTER(I)],
+        "lrdm_set_L": [P, P, I, I],
+        "lrdm_synchronize": [P],
+        "lrdm_timing_begin": [P, I],
+        "lrdm_timing_end": [P, ctypes.POINTER(I), dp, dp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lrdm_last_error.argtypes = [P]
+    lib.lrdm_last_error.restype = ctypes.c_char_p
+    lib.lrdm_version.argtypes = []
+    lib.lrdm_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int, handle=None):
+    if st != 0:
+        lib = load_library()
+        msg = lib.lrdm_last_error(handle).decode()
+        raise LrdmError(st, msg)
+
+
+def _cplx(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def workspace_size(n: int, r_max: int, dtype: int = C64, m_max: int = 4, flags: int = 0):
+    lib = load_library()
+    s, w = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.lrdm_workspace_size(n, r_max, dtype, m_max, flags, ctypes.byref(s), ctypes.byref(w)))
+    return s.value, w.value
+
+
+class LowRankDM:
+    """A handle over caller-owned device memory; method names follow the C ABI."""
+
+    def __init__(self, n: int, r_max: int, dtype: int = C64, m_max: int = 4, flags: int = 0,
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        self.lib = load_library()
+        self.n, self.r_max, self.dtype, self.m_max, self.flags = n, r_max, dtype, m_max, flags
+        sb, wb = workspace_size(n, r_max, dtype, m_max, flags)
+        self.device = torch.device(device)
+        self.state = torch.empty(sb, dtype=torch.uint8, device=self.device)
+        self.work = torch.empty(wb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = ctypes.c_void_p()
+        _check(self.lib.lrdm_init(ctypes.byref(self.h), n, r_max, dtype, m_max, flags,
+                                  self.state.data_ptr(), sb, self.work.data_ptr(), wb,
+                                  ctypes.c_void_p(self.stream.cuda_stream)))
+        r_pad = max(8, 1 << (r_max - 1).bit_length())
+        m_pad = 1 << (m_max - 1).bit_length()
+        self.r_pad = r_pad
+        self.ld = r_pad * (m_pad if flags & FLAG_PLAIN else 1)
+
+    # -------------------------------------------------------------- lifetime
+    def close(self):
+        if self.h:
+            self.lib.lrdm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        _check(self.lib.lrdm_reset(self.h), self.h)
+
+    def synchronize(self):
+        _check(self.lib.lrdm_synchronize(self.h), self.h)
+
+    # -------------------------------------------------------------- evolution
+    def apply_gate(self, qubits: Sequence[int], u):
+        q = (ctypes.c_int * len(qubits))(*[int(x) for x in qubits])
+        m = _cplx(u)
+        _check(self.lib.lrdm_apply_gate(self.h, len(qubits), q, _dptr(m)), self.h)
+
+    def apply_diagonal_weight(self, phase):
+        m = _cplx(phase)
+        _check(self.lib.lrdm_apply_diagonal_weight(self.h, _dptr(m)), self.h)
+
+    def apply_kraus(self, qubit: int, ops):
+        ops = np.asarray(ops, dtype=np.complex128)
+        m = _cplx(ops)
+        _check(self.lib.lrdm_apply_kraus(self.h, int(qubit), ops.shape[0], _dptr(m)), self.h)
+
+    def compress(self, r: int, eps: float = 0.0, tie: int = 0, renorm: int = 1,
+                 info: bool = False) -> Optional[dict]:
+        ci = CompressInfo()
+        _check(self.lib.lrdm_compress(self.h, int(r), float(eps), int(tie), int(renorm),
+                                      ctypes.byref(ci) if info else None), self.h)
+        return ci.as_dict() if info else None
+
+    # -------------------------------------------------------------- outputs
+    def probabilities(self, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(2 ** self.n, dtype=torch.float64, device=self.device)
+        _check(self.lib.lrdm_probabilities(self.h, ctypes.c_void_p(out.data_ptr())), self.h)
+        return out
+
+    def expect_z(self):
+        z = np.zeros(self.n)
+        zz = np.zeros(max(self.n - 1, 1))
+        tr = np.zeros(1)
+        _check(self.lib.lrdm_expect_z(self.h, _dptr(z), _dptr(zz), _dptr(tr)), self.h)
+        return z, zz[: self.n - 1], float(tr[0])
+
+    def expect_pauli(self, xmask, zmask, coeff=None, summed: bool = False):
+        xm = np.ascontiguousarray(xmask, dtype=np.uint64)
+        zm = np.ascontiguousarray(zmask, dtype=np.uint64)
+        nt = xm.shape[0]
+        out = np.zeros(1 if summed else nt)
+        cf = np.ascontiguousarray(coeff, dtype=np.float64) if coeff is not None else None
+        _check(self.lib.lrdm_expect_pauli(self.h, nt, xm.ctypes.data, zm.ctypes.data,
+                                          cf.ctypes.data if cf is not None else None,
+                                          1 if summed else 0, _dptr(out)), self.h)
+        return float(out[0]) if summed else out
+
+    def sample(self, uniforms) -> np.ndarray:
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        out = np.zeros(u.shape[0], dtype=np.uint64)
+        _check(self.lib.lrdm_sample(self.h, u.shape[0], _dptr(u),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))), self.h)
+        return out
+
+    def get_L(self) -> np.ndarray:
+        """The factor as a (2^n, ld) complex128 array (converted from the bulk precision)."""
+        dt = np.complex64 if self.dtype == C64 else np.complex128
+        buf = np.zeros((2 ** self.n, self.ld), dtype=dt)
+        rk = ctypes.c_int()
+        _check(self.lib.lrdm_get_L(self.h, buf.ctypes.data, 1, ctypes.byref(rk)), self.h)
+        return buf.astype(np.complex128)
+
+    def set_L(self, L: np.ndarray):
+        dt = np.complex64 if self.dtype == C64 else np.complex128
+        a = np.ascontiguousarray(np.asarray(L), dtype=dt)
+        _check(self.lib.lrdm_set_L(self.h, a.ctypes.data, 1, a.shape[1]), self.h)
+
+    # -------------------------------------------------------------- timing
+    def timing_begin(self, kernel_class: int):
+        _check(self.lib.lrdm_timing_begin(self.h, int(kernel_class)), self.h)
+
+    def timing_end(self):
+        n = ctypes.c_int()
+        mean, tot = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.lrdm_timing_end(self.h, ctypes.byref(n), ctypes.byref(mean), ctypes.byref(tot)),
+               self.h)
+        return n.value, mean.value, tot.value
+
+
+def run_program(dm: LowRankDM, program, on_layer=None):
+    """Issue every op of a workloads.circuits.Program through the C ABI, in order."""
+    from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
+
+    for op in program.ops:
+        if isinstance(op, Gate):
+            dm.apply_gate(op.qubits, op.u)
+        elif isinstance(op, DiagWeight):
+            dm.apply_diagonal_weight(op.phase)
+        elif isinstance(op, Kraus):
+            dm.apply_kraus(op.qubit, op.ops)
+        elif isinstance(op, Compress):
+            dm.compress(op.r, op.eps, op.tie, op.renorm)
+        elif isinstance(op, LayerEnd):
+            if on_layer is not None:
+                on_layer(op.index)
+        else:
+            raise TypeError(f"unknown op {op!r}")

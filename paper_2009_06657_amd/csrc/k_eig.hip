@@ -1,22 +1,27 @@
 // FP64 eigensolver of the small Gram matrix G (order N <= 128) and the truncation rule
-// (Sec. II.B; Theorem 1, App. B).  Three single-work-group kernels on the serial path between
-// the Gram and projection GEMMs:
+// (Sec. II.B; Theorem 1, App. B), as one single-work-group kernel on the serial path between
+// the Gram and projection GEMMs.
 //
-//  1. eig_tridiag: assemble G from S = X^H X and the Kraus set, G_{(a,v),(b,w)} =
-//     sum_{uv'} (E_a^H E_b)_{uv'} S_{(u,v),(v',w)}, in packed lower storage in LDS (132 KB at
-//     N = 128), then reduce it to a real symmetric tridiagonal T = Q^H G Q with N - 2 Householder
-//     reflectors H_j = I - tau_j v_j v_j^H (v_j(j+1) = 1), each a Hermitian matrix-vector product
-//     and a rank-2 update over the trailing block.
-//  2. eig_solve: the wanted (largest) eigenvalues of T by multisection on Sturm counts (one
-//     group of 8 or 16 lanes per eigenvalue), then eigenvectors by inverse iteration on a
-//     pivoted LU of T - lambda I (one lane per eigenvector).  Eigenvalues closer than 1e-9 ||T||
-//     form clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending
-//     order) after every iteration, so degenerate eigenvalues yield an orthonormal basis of the
-//     cluster.
-//  3. eig_finish: the rank rule (cap r, threshold eps, tie policy), discarded mass,
-//     renormalisation scale, back-transform V = Q Y, and the projection matrix W in the bulk
-//     precision: W_{(b,v),(b',j)} = c sum_a (E_a)_{b'b} V[(a,v),j] (split view) or W = c V_k.
+//  1. Assemble G from S = X^H X and the Kraus set, G_{(a,v),(b,w)} = sum_{uv'} (E_a^H E_b)_{uv'}
+//     S_{(u,v),(v',w)} (split view) or G = S (plain view).  G lives in registers: a grid of
+//     (32 BC / BR) x 32 threads holds BR x BC blocks (N <= 32 BC), so a row of blocks is one
+//     half-wave.
+//  2. Householder reduction to a real symmetric tridiagonal T = Q^H G Q with reflectors
+//     H_j = I - tau_j v_j v_j^H, v_j(j+1) = 1.  Every half-wave forms the reflector from the
+//     broadcast column, the matrix-vector product reduces across a half-wave with shuffles, and
+//     the rank-2 update is register arithmetic: two barriers per step.
+//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a group of 8 or 16
+//     lanes per eigenvalue).
+//  4. Eigenvectors of T by inverse iteration on the LDL^T factorisation of T - lambda I (one
+//     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than 1e-9 ||T|| form
+//     clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending order)
+//     after every iteration, so (near-)degenerate eigenvalues yield an orthonormal basis.
+//  5. The rank rule (cap r, threshold eps, tie policy), discarded mass and renormalisation
+//     scale; back-transform V = Q Y; the projection matrix in the bulk precision:
+//     W_{(b,v),(b',j)} = c sum_a (E_a)_{b'b} V[(a,v), j] (split view) or W = c V_k (plain).
 #include <math.h>
+
+#include <utility>
 
 #include "lrdm_internal.h"
 
@@ -35,204 +40,9 @@ __device__ __forceinline__ z64 zcmul(z64 a, z64 b) {  // conj(a) * b
 }
 __device__ __forceinline__ z64 zscale(z64 a, double s) { return z64{a.x * s, a.y * s}; }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double group_sum(double v, int width) {
+__device__ __forceinline__ double xsum(double v, int width) {   // butterfly over `width` lanes
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-__device__ __forceinline__ int poff(int j, int N) { return j * N - (j * (j - 1)) / 2; }
-
-// ------------------------------------------------------------------------------------------
-// 1. assemble + Householder tridiagonalisation
-// ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void eig_tridiag_kernel(const double* __restrict__ S, int Fc,
-                                                           Channel ch, int nsplit, int c, int N,
-                                                           EigBufs B) {
-  extern __shared__ double smem[];
-  z64* P = reinterpret_cast<z64*>(smem);                 // N(N+1)/2
-  z64* vb = P + (N * (N + 1)) / 2;                        // N
-  z64* pb = vb + N;                                       // N
-  z64* Mab = pb + N;                                      // m*m*4 entries of E_a^H E_b
-  double* scal = reinterpret_cast<double*>(Mab + 64);    // tau.re, tau.im, flag, trace
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = (nsplit == 2) ? ch.m : 1;
-
-  if (nsplit == 2 && tid < m * m * 4) {
-    const int a = tid / (m * 4), b = (tid / 4) % m, u = (tid >> 1) & 1, v = tid & 1;
-    z64 acc = zmk(0, 0);
-    for (int r = 0; r < 2; ++r) {
-      const z64 ea = zmk(ch.e[a][r][u][0], ch.e[a][r][u][1]);
-      const z64 eb = zmk(ch.e[b][r][v][0], ch.e[b][r][v][1]);
-      acc = zadd(acc, zcmul(ea, eb));
-    }
-    Mab[tid] = acc;   // (E_a^H E_b)_{uv} at index ((a*m + b)*2 + u)*2 + v
-  }
-  __syncthreads();
-  // packed lower G
-  const int npk = (N * (N + 1)) / 2;
-  for (int e = tid; e < N * N; e += 1024) {
-    const int i = e / N, j = e % N;
-    if (i < j) continue;
-    z64 g;
-    if (nsplit == 2) {
-      const int a = i / c, vv = i % c, b = j / c, w = j % c;
-      g = zmk(0, 0);
-      for (int u = 0; u < 2; ++u)
-        for (int v = 0; v < 2; ++v) {
-          const z64 mm = Mab[((a * m + b) * 2 + u) * 2 + v];
-          const size_t si = 2 * ((size_t)(u * c + vv) * Fc + (v * c + w));
-          g = zadd(g, zmul(mm, zmk(S[si], S[si + 1])));
-        }
-    } else {
-      const size_t si = 2 * ((size_t)i * Fc + j);
-      g = zmk(S[si], S[si + 1]);
-    }
-    P[poff(j, N) + (i - j)] = g;
-  }
-  __syncthreads();
-  if (wave == 0) {
-    double t = 0;
-    for (int i = lane; i < N; i += 64) t += P[poff(i, N)].x;
-    t = wave_sum(t);
-    if (lane == 0) scal[3] = t;
-  }
-  (void)npk;
-
-  for (int j = 0; j + 1 < N; ++j) {
-    const int mlen = N - 1 - j;   // trailing order
-    // ---- reflector for column j (wave 0)
-    if (wave == 0) {
-      const z64 alpha = P[poff(j, N) + 1];
-      double xn2 = 0;
-      for (int i = j + 2 + lane; i < N; i += 64) {
-        const z64 x = P[poff(j, N) + (i - j)];
-        xn2 += x.x * x.x + x.y * x.y;
-      }
-      xn2 = wave_sum(xn2);
-      double taur = 0, taui = 0, beta = alpha.x;
-      z64 sc = zmk(0, 0);
-      const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
-      if (!trivial) {
-        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-        beta = (alpha.x >= 0) ? -nrm : nrm;
-        taur = (beta - alpha.x) / beta;
-        taui = -alpha.y / beta;
-        // sc = 1 / (alpha - beta)
-        const double dr = alpha.x - beta, di = alpha.y;
-        const double den = dr * dr + di * di;
-        sc = zmk(dr / den, -di / den);
-      }
-      for (int i = j + 2 + lane; i < N; i += 64) {
-        const z64 x = P[poff(j, N) + (i - j)];
-        const z64 v = trivial ? zmk(0, 0) : zmul(sc, x);
-        P[poff(j, N) + (i - j)] = v;
-        vb[i - j - 1] = v;
-      }
-      if (lane == 0) {
-        vb[0] = zmk(1, 0);
-        P[poff(j, N) + 1] = zmk(beta, 0);
-        B.e[j] = beta;
-        B.d[j] = P[poff(j, N)].x;
-        B.tau[2 * j] = taur;
-        B.tau[2 * j + 1] = taui;
-        scal[0] = taur;
-        scal[1] = taui;
-      }
-    }
-    __syncthreads();
-    const z64 tau = zmk(scal[0], scal[1]);
-    if (tau.x == 0.0 && tau.y == 0.0) {
-      __syncthreads();   // everyone has read scal before wave 0 rewrites it
-      continue;
-    }
-    const int base = j + 1;
-    // ---- p = tau * A_sub v  (8 lanes per row)
-    {
-      const int i = tid >> 3, g = tid & 7;
-      z64 s = zmk(0, 0);
-      if (i < mlen) {
-        for (int k = g; k < mlen; k += 8) {
-          z64 a;
-          if (i >= k)
-            a = P[poff(base + k, N) + (i - k)];
-          else
-            a = zconj(P[poff(base + i, N) + (k - i)]);
-          s = zadd(s, zmul(a, vb[k]));
-        }
-      }
-      s.x = group_sum(s.x, 8);
-      s.y = group_sum(s.y, 8);
-      if (i < mlen && g == 0) pb[i] = zmul(tau, s);
-    }
-    __syncthreads();
-    // ---- alpha2 = -1/2 tau (p^H v) (every wave), w = p + alpha2 v, A -= v w^H + w v^H
-    z64 dot = zmk(0, 0);
-    for (int i = lane; i < mlen; i += 64) dot = zadd(dot, zcmul(pb[i], vb[i]));
-    dot.x = wave_sum(dot.x);
-    dot.y = wave_sum(dot.y);
-    const z64 alpha2 = zscale(zmul(tau, dot), -0.5);
-    for (int k = wave; k < mlen; k += 16) {
-      const z64 vk = vb[k];
-      const z64 wk = zadd(pb[k], zmul(alpha2, vk));
-      for (int i = k + lane; i < mlen; i += 64) {
-        const z64 vi = vb[i];
-        const z64 wi = zadd(pb[i], zmul(alpha2, vi));
-        z64& a = P[poff(base + k, N) + (i - k)];
-        // a -= v_i conj(w_k) + w_i conj(v_k)
-        a = zsub(a, zadd(zmul(vi, zconj(wk)), zmul(wi, zconj(vk))));
-      }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (tid == 0) {
-    B.d[N - 1] = P[poff(N - 1, N)].x;
-    if (N == 1) B.d[0] = P[0].x;
-    B.trace[0] = scal[3];
-  }
-  double* Pg = B.P;
-  for (int e = tid; e < (N * (N + 1)) / 2; e += 1024) {
-    Pg[2 * e] = P[e].x;
-    Pg[2 * e + 1] = P[e].y;
-  }
-}
-
-hipError_t launch_eig_tridiag(const double* S, int Fc, const Channel& ch, int nsplit, int c,
-                              int N, const EigBufs& b, hipStream_t s) {
-  const size_t shm = ((size_t)(N * (N + 1)) / 2 + 2 * N + 64) * sizeof(z64) + 8 * sizeof(double);
-  if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_tridiag_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(eig_tridiag_kernel, dim3(1), dim3(1024), shm, s, S, Fc, ch, nsplit, c, N, b);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// 2. eigenvalues (multisection) + eigenvectors (inverse iteration) of T
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int N, double x,
-                                           double pivmin) {
-  double q = d[0] - x;
-  int cnt = 0;
-  if (q <= pivmin) {
-    ++cnt;
-    q = fmin(q, -pivmin);
-  }
-  for (int i = 1; i < N; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
-    if (q <= pivmin) {
-      ++cnt;
-      q = fmin(q, -pivmin);
-    }
-  }
-  return cnt;
 }
 
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
@@ -245,54 +55,263 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
   return ((double)(h >> 8) + 0.5) * (1.0 / 16777216.0) - 0.5;  // (-0.5, 0.5)
 }
 
-__global__ __launch_bounds__(1024) void eig_solve_kernel(int N, int kmax, EigBufs B) {
-  __shared__ double d[kMaxEig], e2[kMaxEig], es[kMaxEig], lam[kMaxEig];
-  __shared__ int cl_start[kMaxEig], cl_len[kMaxEig];
-  __shared__ double red[2];
-  extern __shared__ double X[];                 // N x kmax, X[i * kmax + t]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// offset of reflector j's entries i >= j + 2 in packed storage
+__device__ __forceinline__ int refl_off(int j, int N) { return j * (N - 2) - (j * (j - 1)) / 2; }
 
-  // scale T to unit norm (Gershgorin)
+// number of eigenvalues of T (scaled, diagonal d, squared off-diagonal e2) below x
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int N, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  int cnt = 0;
+  if (q <= pivmin) {
+    ++cnt;
+    q = fmin(q, -pivmin);
+  }
+  int i = 1;
+  for (; i + 3 < N; i += 4) {
+    const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+    q = (d0 - x) - f0 / q;
+    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+    q = (d1 - x) - f1 / q;
+    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+    q = (d2 - x) - f2 / q;
+    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+    q = (d3 - x) - f3 / q;
+    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+  }
+  for (; i < N; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+  }
+  return cnt;
+}
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <class T, int BR, int BC>
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* __restrict__ S, int Fc, Channel ch,
+                                                   int nsplit, int c, int N, int kmax, int r_target,
+                                                   double eps, int tie, int renorm, int c_out,
+                                                   EigBufs B, cx_t<T>* __restrict__ W) {
+  constexpr int NP = 32 * BC;            // padded order; the thread grid is (NP / BR) x 32
+  constexpr int NTH = 32 * (NP / BR);    // threads
+  extern __shared__ __attribute__((aligned(16))) double dyn[];   // phase-dependent scratch
+  __shared__ z64 Mab[64];
+  __shared__ z64 col_buf[NP], vbuf[NP], pbuf[NP];
+  __shared__ double d_s[NP], e_s[NP], e2_s[NP], lam_s[NP + 1], tau_s[2 * NP], trp[32];
+  __shared__ int cl_start[NP], cl_len[NP];
+  __shared__ double sc_s[4];
+  __shared__ int k_s;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = tid >> 5, Cc = tid & 31;   // block row / block column of this thread
+  const int m = (nsplit == 2) ? ch.m : 1;
+
+  // ---------------------------------------------------------------- 1. assemble G
+  if (nsplit == 2 && tid < m * m * 4) {
+    const int a = tid / (m * 4), b = (tid / 4) % m, u = (tid >> 1) & 1, v = tid & 1;
+    z64 acc = zmk(0, 0);
+    for (int r = 0; r < 2; ++r)
+      acc = zadd(acc, zcmul(zmk(ch.e[a][r][u][0], ch.e[a][r][u][1]), zmk(ch.e[b][r][v][0], ch.e[b][r][v][1])));
+    Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
+  }
+  __syncthreads();
+  z64 A[BR][BC];
+#pragma unroll
+  for (int a = 0; a < BR; ++a)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int i = BR * R + a, j = BC * Cc + b;
+      z64 g = zmk(0, 0);
+      if (i < N && j < N) {
+        if (nsplit == 2) {
+          const int ai = i / c, vv = i % c, bj = j / c, w = j % c;
+          for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v) {
+              const z64 mm = Mab[((ai * m + bj) * 2 + u) * 2 + v];
+              const size_t si = 2 * ((size_t)(u * c + vv) * Fc + (v * c + w));
+              g = zadd(g, zmul(mm, zmk(S[si], S[si + 1])));
+            }
+        } else {
+          const size_t si = 2 * ((size_t)i * Fc + j);
+          g = zmk(S[si], S[si + 1]);
+        }
+      }
+      A[a][b] = g;
+    }
+  {
+    double t = 0;
+#pragma unroll
+    for (int a = 0; a < BR; ++a) {
+      const int i = BR * R + a;
+      if (i / BC == Cc) t += A[a][a % BC].x;   // BR is a multiple of BC
+    }
+    t = xsum(t, 32);
+    if (Cc == 0) trp[R] = t;
+  }
+  if (Cc == 0) {
+#pragma unroll
+    for (int a = 0; a < BR; ++a) col_buf[BR * R + a] = A[a][0];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0;
+    for (int i = 0; i < NTH / 32; ++i) t += trp[i];
+    sc_s[0] = t;   // trace
+  }
+
+  // ---------------------------------------------------------------- 2. tridiagonalisation
+  double* refl = B.P;   // packed reflector entries i >= j + 2, complex interleaved
+  auto step = [&](const int j, auto bbc) {
+    constexpr int bb = decltype(bbc)::value;   // j % BC
+    // reflector from column j (every half-wave redundantly; lane Cc owns entries BC Cc + b)
+    const z64 alpha = col_buf[j + 1];
+    z64 cv[BC];
+    double xn2 = 0;
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int i = BC * Cc + b;
+      cv[b] = col_buf[i];
+      if (i > j + 1 && i < N) xn2 += cv[b].x * cv[b].x + cv[b].y * cv[b].y;
+    }
+    xn2 = xsum(xn2, 32);
+    double beta = alpha.x;
+    z64 tau = zmk(0, 0), sc = zmk(0, 0);
+    const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
+    if (!trivial) {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+      beta = (alpha.x >= 0) ? -nrm : nrm;
+      tau = zmk((beta - alpha.x) / beta, -alpha.y / beta);
+      const double dr = alpha.x - beta, di = alpha.y, den = dr * dr + di * di;
+      sc = zmk(dr / den, -di / den);
+    }
+    z64 (&vloc)[BC] = cv;   // v overwrites the column entries it is built from
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int i = BC * Cc + b;
+      vloc[b] = (i == j + 1) ? zmk(1, 0) : ((i > j + 1 && i < N) ? zmul(sc, cv[b]) : zmk(0, 0));
+    }
+    if (tid < 32) {
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        const int i = BC * Cc + b;
+        vbuf[i] = vloc[b];
+        if (i >= j + 2 && i < N) {
+          const int o = refl_off(j, N) + (i - j - 2);
+          refl[2 * o] = vloc[b].x;
+          refl[2 * o + 1] = vloc[b].y;
+        }
+      }
+      if (tid == 0) {
+        d_s[j] = col_buf[j].x;
+        e_s[j] = beta;
+        tau_s[2 * j] = tau.x;
+        tau_s[2 * j + 1] = tau.y;
+      }
+    }
+    // p = tau A v for this thread's rows, reduced over the half-wave
+#pragma unroll
+    for (int a = 0; a < BR; ++a) {
+      z64 s = zmk(0, 0);
+#pragma unroll
+      for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+      s.x = xsum(s.x, 32);
+      s.y = xsum(s.y, 32);
+      const int i = BR * R + a;
+      if (Cc == 0) pbuf[i] = (i > j && i < N) ? zmul(tau, s) : zmk(0, 0);
+    }
+    __syncthreads();
+    // alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
+    z64 dt = zmk(0, 0);
+    z64 pcol[BC];
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      pcol[b] = pbuf[BC * Cc + b];
+      dt = zadd(dt, zcmul(pcol[b], vloc[b]));
+    }
+    dt.x = xsum(dt.x, 32);
+    dt.y = xsum(dt.y, 32);
+    const z64 alpha2 = zscale(zmul(tau, dt), -0.5);
+#pragma unroll
+    for (int a = 0; a < BR; ++a) {
+      const z64 vr = vbuf[BR * R + a];
+      const z64 wr = zadd(pbuf[BR * R + a], zmul(alpha2, vr));
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
+        A[a][b] = zsub(A[a][b], zadd(zmul(vr, zconj(wc)), zmul(wr, zconj(vloc[b]))));
+      }
+    }
+    // owners of column j + 1 broadcast it for the next step
+    if (Cc == (j + 1) / BC) {
+      constexpr int bsel = (bb + 1) % BC;
+#pragma unroll
+      for (int a = 0; a < BR; ++a) col_buf[BR * R + a] = A[a][bsel];
+    }
+    __syncthreads();
+  };
+  for (int jb = 0; jb + 1 < N; jb += BC) {
+    static_for<BC>([&](auto bbc) {
+      const int j = jb + decltype(bbc)::value;
+      if (j + 1 < N) step(j, bbc);
+    });
+  }
+  if (tid == 0) {
+    d_s[N - 1] = col_buf[N - 1].x;
+    e_s[N - 1] = 0.0;
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- 3. eigenvalues
+  // scale T to unit Gershgorin norm
   if (wave == 0) {
     double mx = 0;
     for (int i = lane; i < N; i += 64) {
-      const double el = (i > 0) ? fabs(B.e[i - 1]) : 0.0;
-      const double er = (i + 1 < N) ? fabs(B.e[i]) : 0.0;
-      mx = fmax(mx, fabs(B.d[i]) + el + er);
+      const double el = (i > 0) ? fabs(e_s[i - 1]) : 0.0;
+      const double er = (i + 1 < N) ? fabs(e_s[i]) : 0.0;
+      mx = fmax(mx, fabs(d_s[i]) + el + er);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) red[0] = mx;
+    if (lane == 0) sc_s[1] = mx;
   }
   __syncthreads();
-  const double tnorm = red[0];
+  const double tnorm = sc_s[1];
   const bool zero = !(tnorm > 0.0);
   const double inv = zero ? 1.0 : 1.0 / tnorm;
-  for (int i = tid; i < N; i += 1024) {
-    d[i] = B.d[i] * inv;
-    es[i] = (i + 1 < N) ? B.e[i] * inv : 0.0;
-    e2[i] = es[i] * es[i];
+  const double epsm = 2.220446049250313e-16;
+  const double pivmin = 1e-290;
+  for (int i = tid; i < N; i += NTH) {
+    d_s[i] *= inv;
+    e_s[i] = (i + 1 < N) ? e_s[i] * inv : 0.0;
+    e2_s[i] = e_s[i] * e_s[i];
   }
   __syncthreads();
-  const double eps = 2.220446049250313e-16;
-  const double pivmin = 1e-290;
-
-  // ---- multisection: group of G lanes per wanted eigenvalue (descending index t)
-  const int G = (kmax <= 64) ? 16 : 8;
   {
+    int G = 16;   // lanes per eigenvalue: the largest power of two <= 16 with G kmax <= NTH
+    while (G * kmax > NTH) G >>= 1;
     const int t = tid / G, g = tid % G;
     const bool active = (t < kmax) && !zero;
-    const int a = N - 1 - t;                      // ascending index
-    double lo = -1.0 - 4 * eps, hi = 1.0 + 4 * eps;   // |lambda| <= ||T|| = 1
+    const int asc = N - 1 - t;
+    double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
     for (int it = 0; it < 24; ++it) {
       const double w = hi - lo;
-      const bool done = !(w > 2 * eps * fmax(fabs(lo), fabs(hi)) + 4 * eps * eps);
+      const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + 4 * epsm * epsm);
+      if (__ballot(active && !done) == 0ull) break;
       const double x = lo + w * (double)(g + 1) / (double)(G + 1);
-      const int cnt = active ? sturm_count(d, e2, N, x, pivmin) : 0;
-      const unsigned long long ball = __ballot(active && cnt > a);
+      const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
+      const unsigned long long ball = __ballot(active && !done && cnt > asc);
       const int gb = lane & ~(G - 1);
       const unsigned long long grp = (ball >> gb) & ((1ull << G) - 1ull);
-      const int first = grp ? (__ffsll((long long)grp) - 1) : G;   // G: no sample above
+      const int first = grp ? (__ffsll((long long)grp) - 1) : G;
       const double xh = __shfl(x, gb + (first < G ? first : 0), 64);
       const double xl = __shfl(x, gb + (first == 0 ? 0 : first - 1), 64);
       if (active && !done) {
@@ -300,174 +319,103 @@ __global__ __launch_bounds__(1024) void eig_solve_kernel(int N, int kmax, EigBuf
         if (first > 0) lo = xl;
       }
     }
-    if (active && g == 0) lam[t] = 0.5 * (lo + hi);
-    if (zero && g == 0 && t < kmax) lam[t] = 0.0;
+    if (g == 0 && t < kmax) lam_s[t] = active ? 0.5 * (lo + hi) : 0.0;
   }
   __syncthreads();
-
-  // ---- clusters (descending order)
   if (tid == 0) {
     const double ctol = 1e-9;
     int s = 0;
     for (int t = 0; t < kmax; ++t) {
-      if (t > 0 && !(lam[t - 1] - lam[t] <= ctol)) s = t;
+      if (t > 0 && !(lam_s[t - 1] - lam_s[t] <= ctol)) s = t;
       cl_start[t] = s;
+      cl_len[t] = 0;
     }
-    for (int t = kmax - 1; t >= 0; --t) cl_len[t] = 0;
     for (int t = 0; t < kmax; ++t) cl_len[cl_start[t]] += 1;
   }
   __syncthreads();
 
-  // ---- inverse iteration: lane t owns eigenvector t
-  double* la = B.lu;                 // U diagonal (inverse stored)
-  double* lb = la + N * kmax;        // U first superdiagonal
-  double* lc = lb + N * kmax;        // multipliers
-  double* ldd = lc + N * kmax;       // U second superdiagonal
-  double* lp = ldd + N * kmax;       // pivot flags
-  const int t = tid;
-  const bool owner = t < kmax;
-  if (owner) {
-    const double sigma = lam[t];
-    // factor T - sigma I = P L U (partial pivoting)
-    double ak = d[0] - sigma;
-    double bk = (N > 1) ? es[0] : 0.0;
-    for (int k = 0; k + 1 < N; ++k) {
-      const double ck = es[k];
-      const double a1 = d[k + 1] - sigma;
-      const double b1 = (k + 2 < N) ? es[k + 1] : 0.0;
-      double piv, mult, u0, u1, u2, an, bn;
-      if (fabs(ak) >= fabs(ck)) {
-        piv = 0;
-        mult = (ak != 0.0) ? ck / ak : 0.0;
-        u0 = ak; u1 = bk; u2 = 0.0;
-        an = a1 - mult * bk;
-        bn = b1;
-      } else {
-        piv = 1;
-        mult = ak / ck;
-        u0 = ck; u1 = a1; u2 = b1;
-        an = bk - mult * a1;
-        bn = -mult * b1;
-      }
-      if (fabs(u0) < eps) u0 = (u0 >= 0) ? eps : -eps;
-      la[k * kmax + t] = 1.0 / u0;
-      lb[k * kmax + t] = u1;
-      ldd[k * kmax + t] = u2;
-      lc[k * kmax + t] = mult;
-      lp[k * kmax + t] = piv;
-      ak = an;
-      bk = bn;
+  // ---------------------------------------------------------------- 4. eigenvectors of T
+  const int KP = kmax;
+  double* Dp = dyn;              // LDL^T pivots, [i * KP + t]
+  double* X = dyn + NP * KP;     // vectors, [i * KP + t]
+  if (tid < kmax) {
+    const int t = tid;
+    const double sigma = lam_s[t];
+    double dp = d_s[0] - sigma;
+    if (fabs(dp) < pivmin) dp = -pivmin;
+    Dp[t] = dp;
+    for (int i = 1; i < N; ++i) {
+      dp = (d_s[i] - sigma) - e2_s[i - 1] / dp;
+      if (fabs(dp) < pivmin) dp = -pivmin;
+      Dp[i * KP + t] = dp;
     }
-    if (fabs(ak) < eps) ak = (ak >= 0) ? eps : -eps;
-    la[(N - 1) * kmax + t] = 1.0 / ak;
-    for (int i = 0; i < N; ++i) X[i * kmax + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
+    for (int i = 0; i < N; ++i) X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
   }
   __syncthreads();
-
-  for (int iter = 0; iter < 3; ++iter) {
-    if (owner) {
-      // forward: y <- L^{-1} P y
-      double yk = X[t];
-      for (int k = 0; k + 1 < N; ++k) {
-        double yk1 = X[(k + 1) * kmax + t];
-        if (lp[k * kmax + t] != 0.0) {
-          const double tmp = yk;
-          yk = yk1;
-          yk1 = tmp;
-        }
-        X[k * kmax + t] = yk;
-        yk = yk1 - lc[k * kmax + t] * yk;
+  for (int iter = 0; iter < 2; ++iter) {
+    if (tid < kmax) {
+      const int t = tid;
+      // forward: y_i -= l_{i-1} y_{i-1}, l_{i-1} = e_{i-1} / D_{i-1}
+      double y = X[t];
+      double dprev = Dp[t];
+      for (int i = 1; i < N; ++i) {
+        const double di = Dp[i * KP + t];
+        y = X[i * KP + t] - (e_s[i - 1] / dprev) * y;
+        X[i * KP + t] = y;
+        dprev = di;
       }
-      X[(N - 1) * kmax + t] = yk;
-      // backward: U x = y
-      double x1 = 0.0, x2 = 0.0, mx = 0.0;
-      for (int k = N - 1; k >= 0; --k) {
-        double v = X[k * kmax + t];
-        if (k + 1 < N) v -= lb[k * kmax + t] * x1;
-        if (k + 2 < N) v -= ldd[k * kmax + t] * x2;
-        v *= la[k * kmax + t];
-        X[k * kmax + t] = v;
-        x2 = x1;
-        x1 = v;
-        mx = fmax(mx, fabs(v));
+      // backward: x_i = y_i / D_i - l_i x_{i+1}
+      double xn = X[(N - 1) * KP + t] / Dp[(N - 1) * KP + t];
+      X[(N - 1) * KP + t] = xn;
+      double mx = fabs(xn);
+      for (int i = N - 2; i >= 0; --i) {
+        const double di = Dp[i * KP + t];
+        xn = X[i * KP + t] / di - (e_s[i] / di) * xn;
+        X[i * KP + t] = xn;
+        mx = fmax(mx, fabs(xn));
       }
-      const double sc = (mx > 0) ? 1.0 / mx : 1.0;
+      const double s1 = (mx > 0) ? 1.0 / mx : 1.0;
       double nn = 0;
       for (int i = 0; i < N; ++i) {
-        const double v = X[i * kmax + t] * sc;
+        const double v = X[i * KP + t] * s1;
         nn += v * v;
-        X[i * kmax + t] = v;
+        X[i * KP + t] = v;
       }
-      const double s2 = 1.0 / sqrt(nn);
-      for (int i = 0; i < N; ++i) X[i * kmax + t] *= s2;
+      const double s2 = (nn > 0) ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = 0; i < N; ++i) X[i * KP + t] *= s2;
     }
     __syncthreads();
-    // cluster re-orthonormalisation, one wave per cluster
-    for (int cs = 0; cs < kmax; ++cs) {
+    for (int cs = wave; cs < kmax; cs += NTH / 64) {
       if (cl_start[cs] != cs || cl_len[cs] < 2) continue;
-      if ((cs % 16) != wave) continue;
       const int len = cl_len[cs];
       for (int jj = cs; jj < cs + len; ++jj) {
         for (int ii = cs; ii < jj; ++ii) {
-          double dt = 0;
-          for (int i = lane; i < N; i += 64) dt += X[i * kmax + ii] * X[i * kmax + jj];
-          dt = wave_sum(dt);
-          for (int i = lane; i < N; i += 64) X[i * kmax + jj] -= dt * X[i * kmax + ii];
+          double dtt = 0;
+          for (int i = lane; i < N; i += 64) dtt += X[i * KP + ii] * X[i * KP + jj];
+          dtt = xsum(dtt, 64);
+          for (int i = lane; i < N; i += 64) X[i * KP + jj] -= dtt * X[i * KP + ii];
         }
         double nn = 0;
-        for (int i = lane; i < N; i += 64) nn += X[i * kmax + jj] * X[i * kmax + jj];
-        nn = wave_sum(nn);
+        for (int i = lane; i < N; i += 64) nn += X[i * KP + jj] * X[i * KP + jj];
+        nn = xsum(nn, 64);
         const double s2 = (nn > 0) ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = lane; i < N; i += 64) X[i * kmax + jj] *= s2;
+        for (int i = lane; i < N; i += 64) X[i * KP + jj] *= s2;
       }
     }
     __syncthreads();
   }
-  // outputs: lam (unscaled, descending) and Y column-major by eigenvector
-  for (int e = tid; e < kmax; e += 1024) B.lam[e] = lam[e] * tnorm;
-  for (int e = tid; e < N * kmax; e += 1024) {
-    const int tt = e / N, i = e % N;
-    B.Y[e] = zero ? ((i == tt) ? 1.0 : 0.0) : X[i * kmax + tt];
-  }
-}
 
-hipError_t launch_eig_solve(int N, int kmax, const EigBufs& b, hipStream_t s) {
-  const size_t shm = (size_t)N * kmax * sizeof(double);
-  if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_solve_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(eig_solve_kernel, dim3(1), dim3(1024), shm, s, N, kmax, b);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// 3. rank rule, back-transform, projection matrix W
-// ------------------------------------------------------------------------------------------
-template <class T>
-__global__ __launch_bounds__(1024) void eig_finish_kernel(int N, int kmax, int r_target, double eps,
-                                                          int tie, int renorm, Channel ch,
-                                                          int nsplit, int c, int c_out, EigBufs B,
-                                                          cx_t<T>* __restrict__ W) {
-  extern __shared__ double smem[];
-  z64* P = reinterpret_cast<z64*>(smem);          // packed reflectors, later V (N x k)
-  __shared__ double tau_s[2 * kMaxEig];
-  __shared__ int k_s;
-  __shared__ double scale_s;
-  const int tid = threadIdx.x;
-  const int npk = (N * (N + 1)) / 2;
-
+  // ---------------------------------------------------------------- 5. rank rule, V = Q Y, W
   if (tid == 0) {
-    const double trace = B.trace[0];
+    const double trace = sc_s[0];
+    for (int t = 0; t < kmax; ++t) lam_s[t] = zero ? 0.0 : lam_s[t] * tnorm;
     int k = min(r_target, N);
-    bool bad = !isfinite(trace);
-    for (int i = 0; i < kmax; ++i) bad = bad || !isfinite(B.lam[i]);
+    bool bad = !isfinite(trace) || !isfinite(tnorm);
     if (eps > 0.0) {
       double kept = 0;
       int keps = N;
       for (int i = 0; i < kmax; ++i) {
-        kept += fmax(B.lam[i], 0.0);
+        kept += fmax(lam_s[i], 0.0);
         if (kept >= (1.0 - eps) * trace) {
           keps = i + 1;
           break;
@@ -475,14 +423,13 @@ __global__ __launch_bounds__(1024) void eig_finish_kernel(int N, int kmax, int r
       }
       k = min(k, keps);
     }
-    if (tie == 1) {
-      while (k > 1 && k < N && (B.lam[k - 1] - B.lam[k]) <= 1e-6 * trace) --k;
-    }
+    if (tie == 1)
+      while (k > 1 && k < N && (lam_s[k - 1] - lam_s[k]) <= 1e-6 * trace) --k;
     if (k < 1) k = 1;
     double kept = 0;
-    for (int i = 0; i < k; ++i) kept += fmax(B.lam[i], 0.0);
+    for (int i = 0; i < k; ++i) kept += fmax(lam_s[i], 0.0);
     if (!(kept > 0.0)) bad = true;
-    const double sc = (renorm && kept > 0.0) ? 1.0 / sqrt(kept) : 1.0;
+    const double scl = (renorm && kept > 0.0) ? 1.0 / sqrt(kept) : 1.0;
     DevInfo* inf = B.info;
     const double disc = fmax(trace - kept, 0.0);
     inf->k = k;
@@ -490,114 +437,133 @@ __global__ __launch_bounds__(1024) void eig_finish_kernel(int N, int kmax, int r
     inf->discarded = disc;
     inf->discarded_total += disc;
     inf->trace = trace;
-    inf->gap = (k < N) ? (B.lam[k - 1] - B.lam[k]) : INFINITY;
-    inf->lambda_max = B.lam[0];
-    inf->scale = sc;
+    inf->gap = (k < N) ? (lam_s[k - 1] - lam_s[k]) : INFINITY;
+    inf->lambda_max = lam_s[0];
+    inf->scale = scl;
     if (bad) inf->status = (int)LRDM_E_EIG;
     k_s = k;
-    scale_s = sc;
+    sc_s[2] = scl;
   }
-  for (int e = tid; e < npk; e += 1024) P[e] = zmk(B.P[2 * e], B.P[2 * e + 1]);
-  for (int e = tid; e < 2 * (N - 1); e += 1024) tau_s[e] = B.tau[e];
   __syncthreads();
+  for (int t = tid; t < kmax; t += NTH) B.lam[t] = lam_s[t];
   const int k = k_s;
-  const double sc = scale_s;
-
-  // back-transform: 16 lanes per kept column, lane g holds rows g, g+16, ...
-  const int col = tid >> 4, g = tid & 15;
-  z64 z[kMaxEig / 16];
-  if (col < k) {
+  const double scl = sc_s[2];
+  // LPC lanes per kept column (64 columns); lane g holds rows g, g + LPC, ...
+  constexpr int LPC = NTH / 64;
+  const int col = tid / LPC, g = tid % LPC;
+  constexpr int ZR = NP / LPC;
+  z64 z[ZR];
 #pragma unroll
-    for (int s = 0; s < kMaxEig / 16; ++s) {
-      const int i = g + 16 * s;
-      z[s] = zmk(i < N ? B.Y[(size_t)col * N + i] : 0.0, 0.0);
-    }
+  for (int s = 0; s < ZR; ++s) {
+    const int i = g + LPC * s;
+    z[s] = zmk((col < k && i < N) ? (zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col]) : 0.0, 0.0);
+  }
+  __syncthreads();
+  // stage the reflectors in LDS (packed, complex)
+  z64* Rf = reinterpret_cast<z64*>(dyn);
+  const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
+  for (int e = tid; e < nref; e += NTH) Rf[e] = zmk(refl[2 * e], refl[2 * e + 1]);
+  __syncthreads();
+  if (col < k) {
     for (int j = N - 2; j >= 0; --j) {
       const z64 tj = zmk(tau_s[2 * j], tau_s[2 * j + 1]);
       if (tj.x == 0.0 && tj.y == 0.0) continue;
+      const int ro = refl_off(j, N);
       z64 s = zmk(0, 0);
 #pragma unroll
-      for (int q = 0; q < kMaxEig / 16; ++q) {
-        const int i = g + 16 * q;
+      for (int q = 0; q < ZR; ++q) {
+        const int i = g + LPC * q;
         if (i >= j + 1 && i < N) {
-          const z64 v = (i == j + 1) ? zmk(1, 0) : P[poff(j, N) + (i - j)];
+          const z64 v = (i == j + 1) ? zmk(1, 0) : Rf[ro + (i - j - 2)];
           s = zadd(s, zcmul(v, z[q]));
         }
       }
-      s.x = group_sum(s.x, 16);
-      s.y = group_sum(s.y, 16);
+      s.x = xsum(s.x, LPC);
+      s.y = xsum(s.y, LPC);
       const z64 ts = zmul(tj, s);
 #pragma unroll
-      for (int q = 0; q < kMaxEig / 16; ++q) {
-        const int i = g + 16 * q;
+      for (int q = 0; q < ZR; ++q) {
+        const int i = g + LPC * q;
         if (i >= j + 1 && i < N) {
-          const z64 v = (i == j + 1) ? zmk(1, 0) : P[poff(j, N) + (i - j)];
+          const z64 v = (i == j + 1) ? zmk(1, 0) : Rf[ro + (i - j - 2)];
           z[q] = zsub(z[q], zmul(v, ts));
         }
       }
     }
   }
   __syncthreads();
-  // V in LDS as V[i * 64 + col]
-  z64* V = P;
+  z64* V = reinterpret_cast<z64*>(dyn);   // V[i * 64 + col]
   if (col < k) {
 #pragma unroll
-    for (int s = 0; s < kMaxEig / 16; ++s) {
-      const int i = g + 16 * s;
+    for (int s = 0; s < ZR; ++s) {
+      const int i = g + LPC * s;
       if (i < N) V[i * 64 + col] = z[s];
     }
   }
   __syncthreads();
-  // W in the bulk precision
   using C = cx_t<T>;
   if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
-    for (int e = tid; e < rows * cols; e += 1024) {
+    for (int e = tid; e < rows * cols; e += NTH) {
       const int rw = e / cols, cl = e % cols;
-      const int b = rw / c, v = rw % c, bp = cl / c_out, j = cl % c_out;
+      const int b = rw / c, v = rw % c, bp = cl / c_out, jj = cl % c_out;
       z64 acc = zmk(0, 0);
-      if (j < k) {
+      if (jj < k) {
         for (int a = 0; a < ch.m; ++a)
-          acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), V[(a * c + v) * 64 + j]));
+          acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), V[(a * c + v) * 64 + jj]));
       }
       C o;
-      o.x = (T)(acc.x * sc);
-      o.y = (T)(acc.y * sc);
+      o.x = (T)(acc.x * scl);
+      o.y = (T)(acc.y * scl);
       W[e] = o;
     }
   } else {
-    const int cols = c_out;
-    for (int e = tid; e < N * cols; e += 1024) {
-      const int i = e / cols, j = e % cols;
-      const z64 acc = (j < k) ? V[i * 64 + j] : zmk(0, 0);
+    for (int e = tid; e < N * c_out; e += NTH) {
+      const int i = e / c_out, jj = e % c_out;
+      const z64 acc = (jj < k) ? V[i * 64 + jj] : zmk(0, 0);
       C o;
-      o.x = (T)(acc.x * sc);
-      o.y = (T)(acc.y * sc);
+      o.x = (T)(acc.x * scl);
+      o.y = (T)(acc.y * scl);
       W[e] = o;
     }
   }
 }
 
-template <class T>
-hipError_t launch_eig_finish(int N, int kmax, int r_target, double eps, int tie, int renorm,
-                             const Channel& ch, int nsplit, int c, int c_out, const EigBufs& b,
-                             cx_t<T>* W, hipStream_t s) {
-  const size_t npk = (size_t)(N * (N + 1)) / 2;
-  const size_t nv = (size_t)N * 64;
-  const size_t shm = (npk > nv ? npk : nv) * sizeof(z64);
+template <class T, int BR, int BC>
+static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int nsplit, int c,
+                                int N, int kmax, int r_target, double eps, int tie, int renorm,
+                                int c_out, const EigBufs& b, cx_t<T>* W, hipStream_t s) {
+  constexpr int NP = 32 * BC;
+  constexpr int NTH = 32 * (NP / BR);
+  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);
+  const size_t ph5a = (size_t)(NP * (NP - 1) / 2) * 16;   // packed reflectors
+  const size_t ph5b = (size_t)NP * 64 * 16;               // V
+  size_t shm = ph4;
+  if (ph5a > shm) shm = ph5a;
+  if (ph5b > shm) shm = ph5b;
   if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_finish_kernel<T>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_kernel<T, BR, BC>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(eig_finish_kernel<T>, dim3(1), dim3(1024), shm, s, N, kmax, r_target, eps, tie,
-                     renorm, ch, nsplit, c, c_out, b, W);
+  hipLaunchKernelGGL((eig_kernel<T, BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax,
+                     r_target, eps, tie, renorm, c_out, b, W);
   return hipGetLastError();
 }
 
-template hipError_t launch_eig_finish<float>(int, int, int, double, int, int, const Channel&, int,
-                                             int, int, const EigBufs&, float2*, hipStream_t);
-template hipError_t launch_eig_finish<double>(int, int, int, double, int, int, const Channel&, int,
-                                              int, int, const EigBufs&, double2*, hipStream_t);
+template <class T>
+hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, int c, int N,
+                      int kmax, int r_target, double eps, int tie, int renorm, int c_out,
+                      const EigBufs& b, cx_t<T>* W, hipStream_t s) {
+  if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64) return hipErrorInvalidValue;
+  if (N <= 32) return launch_eig_bs<T, 1, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
+  if (N <= 64) return launch_eig_bs<T, 2, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
+  return launch_eig_bs<T, 8, 4>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
+}
+
+template hipError_t launch_eig<float>(const double*, int, const Channel&, int, int, int, int, int, double,
+                                      int, int, int, const EigBufs&, float2*, hipStream_t);
+template hipError_t launch_eig<double>(const double*, int, const Channel&, int, int, int, int, int, double,
+                                       int, int, int, const EigBufs&, double2*, hipStream_t);
 
 }  // namespace lrdm

@@ -11,6 +11,8 @@
 
 namespace lrdm {
 
+typedef float f4v __attribute__((ext_vector_type(4)));   // 16-byte register unit
+
 template <class C> __device__ __forceinline__ C cmul(C a, C b) {
   C r;
   r.x = a.x * b.x - a.y * b.y;
@@ -30,12 +32,6 @@ template <class C, class T> __device__ __forceinline__ C cmk(T re, T im) {
   return r;
 }
 
-// Row index of tile slot i: base with local bit j set iff bit j of i is set.
-__device__ __forceinline__ uint32_t slot_row(uint32_t base, uint32_t i, const int* lq, int k) {
-  uint32_t x = base;
-  for (int j = 0; j < k; ++j) x |= ((i >> j) & 1u) << lq[j];
-  return x;
-}
 __device__ __forceinline__ uint32_t insert_zero(uint32_t p, int j) {
   return ((p >> j) << (j + 1)) | (p & ((1u << j) - 1u));
 }
@@ -46,11 +42,15 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
   using C = cx_t<T>;
   extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
   C* tile = reinterpret_cast<C*>(gate_smem);   // [2^k][ncols]
+  __shared__ uint32_t slot_off[256];           // row offset of tile slot i (local bits of i)
   const int k = P.k, nc = P.ncols, tid = threadIdx.x;
   const size_t ld = (size_t)P.ld;
-  int lq[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) lq[j] = P.local_q[j];
+  if (tid < (1 << k)) {
+    uint32_t off = 0;
+    for (int j = 0; j < k; ++j) off |= ((uint32_t)(tid >> j) & 1u) << P.local_q[j];
+    slot_off[tid] = off;
+  }
+  __syncthreads();
 
   // deposit the tile index into the non-local bit positions (ascending local qubits)
   uint32_t base = blockIdx.x;
@@ -59,10 +59,27 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
     base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
   }
   const int elems = nc << k;
-  for (int e = tid; e < elems; e += 256) {
-    const uint32_t i = (uint32_t)e >> cshift;
-    const int v = e & (nc - 1);
-    tile[e] = L[(size_t)slot_row(base, i, lq, k) * ld + v];
+  // HBM -> LDS with 16-byte accesses, kUnroll loads in flight per thread before the LDS writes
+  constexpr int CPU = 16 / (int)sizeof(C);   // complex values per 16-byte unit
+  constexpr int kUnroll = 8;
+  const int units = elems / CPU;
+  for (int u0 = 0; u0 < units; u0 += 256 * kUnroll) {
+    f4v buf[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      const int uu = u0 + j * 256 + tid;
+      if (uu < units) {
+        const int e = uu * CPU;
+        const uint32_t i = (uint32_t)e >> cshift;
+        const int v = e & (nc - 1);
+        buf[j] = *reinterpret_cast<const f4v*>(L + (size_t)(base | slot_off[i]) * ld + v);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      const int uu = u0 + j * 256 + tid;
+      if (uu < units) *reinterpret_cast<f4v*>(tile + uu * CPU) = buf[j];
+    }
   }
   __syncthreads();
 
@@ -73,6 +90,7 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
       const int j = P.op_a[o];
       const C u00 = cmk<C, T>(u[0], u[1]), u01 = cmk<C, T>(u[2], u[3]);
       const C u10 = cmk<C, T>(u[4], u[5]), u11 = cmk<C, T>(u[6], u[7]);
+#pragma unroll 4
       for (int e = tid; e < (elems >> 1); e += 256) {
         const int v = e & (nc - 1);
         const uint32_t i0 = insert_zero((uint32_t)e >> cshift, j), i1 = i0 | (1u << j);
@@ -85,6 +103,7 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
     } else if (ty == OP_2Q) {
       const int ja = P.op_a[o], jb = P.op_b[o];
       const int jlo = ja < jb ? ja : jb, jhi = ja < jb ? jb : ja;
+#pragma unroll 2
       for (int e = tid; e < (elems >> 2); e += 256) {
         const int v = e & (nc - 1);
         const uint32_t i00 = insert_zero(insert_zero((uint32_t)e >> cshift, jlo), jhi);
@@ -104,7 +123,7 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
       // diagonal in the computational basis: phase from the full row index
       const int qa = P.op_a[o], qb = P.op_b[o];
       for (int e = tid; e < elems; e += 256) {
-        const uint32_t x = slot_row(base, (uint32_t)e >> cshift, lq, k);
+        const uint32_t x = base | slot_off[(uint32_t)e >> cshift];
         int sel;
         if (ty == OP_DIAG1)
           sel = (int)((x >> qa) & 1u);
@@ -117,10 +136,23 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
     }
     __syncthreads();
   }
-  for (int e = tid; e < elems; e += 256) {
-    const uint32_t i = (uint32_t)e >> cshift;
-    const int v = e & (nc - 1);
-    L[(size_t)slot_row(base, i, lq, k) * ld + v] = tile[e];
+  for (int u0 = 0; u0 < units; u0 += 256 * kUnroll) {
+    f4v buf[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      const int uu = u0 + j * 256 + tid;
+      if (uu < units) buf[j] = *reinterpret_cast<const f4v*>(tile + uu * CPU);
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      const int uu = u0 + j * 256 + tid;
+      if (uu < units) {
+        const int e = uu * CPU;
+        const uint32_t i = (uint32_t)e >> cshift;
+        const int v = e & (nc - 1);
+        *reinterpret_cast<f4v*>(L + (size_t)(base | slot_off[i]) * ld + v) = buf[j];
+      }
+    }
   }
 }
 

@@ -56,14 +56,8 @@ struct Channel {
 // Scratch carved from the caller's workspace for one compression.
 struct EigBufs {
   double* S;        // (F/2)^2 complex, Gram of the split view, full Hermitian, row-major
-  double* P;        // packed lower Householder storage, N(N+1)/2 complex
-  double* d;        // N
-  double* e;        // N
-  double* tau;      // N complex
-  double* lam;      // N, descending
-  double* Y;        // N x kmax, tridiagonal eigenvectors, column t contiguous
-  double* lu;       // 5 N kmax inverse-iteration factors
-  double* trace;    // 1
+  double* P;        // packed Householder reflector entries, (N-1)(N-2)/2 complex
+  double* lam;      // kept-candidate eigenvalues, descending
   DevInfo* info;
 };
 
@@ -82,14 +76,11 @@ hipError_t launch_gram(const cx_t<T>* L, int n, int ld, int c, int nsplit, int q
 template <class T>
 hipError_t launch_gram_reduce(const T* partials, int nblocks, int F, double* S, hipStream_t s);
 
-hipError_t launch_eig_tridiag(const double* S, int Fc, const Channel& ch, int nsplit, int c,
-                              int N, const EigBufs& b, hipStream_t s);
-hipError_t launch_eig_solve(int N, int kmax, const EigBufs& b, hipStream_t s);
-
+// Eigensolve of G (order N <= 128), rank rule and projection matrix W; one work-group.
 template <class T>
-hipError_t launch_eig_finish(int N, int kmax, int r_target, double eps, int tie, int renorm,
-                             const Channel& ch, int nsplit, int c, int c_out, const EigBufs& b,
-                             cx_t<T>* W, hipStream_t s);
+hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, int c, int N,
+                      int kmax, int r_target, double eps, int tie, int renorm, int c_out,
+                      const EigBufs& b, cx_t<T>* W, hipStream_t s);
 
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,

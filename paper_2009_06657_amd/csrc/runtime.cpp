@@ -36,8 +36,7 @@ int next_pow2(int x) {
 struct Layout {
   int r_pad, m_pad, ld, F_max, FO_max;
   size_t state_bytes;
-  size_t off_info, off_part, off_S, off_P, off_d, off_e, off_tau, off_lam, off_Y, off_lu, off_trace,
-      off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
+  size_t off_info, off_part, off_S, off_P, off_lam, off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
 };
 
 bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
@@ -70,13 +69,7 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   L.off_part = take((size_t)nb * NUP * 256 * rs);
   L.off_S = take((size_t)Fc * Fc * 16);
   L.off_P = take((size_t)N * (N + 1) / 2 * 16);
-  L.off_d = take(N * 8);
-  L.off_e = take(N * 8);
-  L.off_tau = take(2 * N * 8);
   L.off_lam = take(N * 8);
-  L.off_Y = take((size_t)N * N * 8);
-  L.off_lu = take((size_t)5 * N * N * 8);
-  L.off_trace = take(64);
   L.off_W = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
   L.off_out = take(4096 * 8);
   L.off_pbuf = take(rows * 8 + (size_t)kZBlocks * 64 * 8);
@@ -272,13 +265,7 @@ EigBufs eig_bufs(lrdm_t h) {
   EigBufs b;
   b.S = h->ws<double>(h->lay.off_S);
   b.P = h->ws<double>(h->lay.off_P);
-  b.d = h->ws<double>(h->lay.off_d);
-  b.e = h->ws<double>(h->lay.off_e);
-  b.tau = h->ws<double>(h->lay.off_tau);
   b.lam = h->ws<double>(h->lay.off_lam);
-  b.Y = h->ws<double>(h->lay.off_Y);
-  b.lu = h->ws<double>(h->lay.off_lu);
-  b.trace = h->ws<double>(h->lay.off_trace);
   b.info = h->ws<DevInfo>(h->lay.off_info);
   return b;
 }
@@ -315,10 +302,8 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm) 
   HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
   timed_end(h, 2);
   timed_begin(h, 3);
-  HIPCHK(h, launch_eig_tridiag(b.S, Fc, ch, nsplit, c, N, b, h->stream));
-  HIPCHK(h, launch_eig_solve(N, kmax, b, h->stream));
-  HIPCHK(h, launch_eig_finish<T>(N, kmax, r_target, eps, tie, renorm, ch, nsplit, c, c_out, b, W,
-                                 h->stream));
+  HIPCHK(h, launch_eig<T>(b.S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b,
+                          W, h->stream));
   timed_end(h, 3);
   timed_begin(h, 4);
   HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W, h->stream));

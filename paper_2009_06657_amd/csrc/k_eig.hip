@@ -40,8 +40,24 @@ __device__ __forceinline__ z64 zcmul(z64 a, z64 b) {  // conj(a) * b
 }
 __device__ __forceinline__ z64 zscale(z64 a, double s) { return z64{a.x * s, a.y * s}; }
 
-__device__ __forceinline__ double xsum(double v, int width) {   // butterfly over `width` lanes
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Lane-group sums.  Inside a row of 16 lanes the exchanges are DPP moves (quad_perm xor 1,
+// quad_perm xor 2, row_half_mirror, row_mirror: after the first two steps every lane of a quad
+// holds the quad sum, so the mirrors add the other quad / half-row); the 16- and 32-lane
+// exchanges use ds_bpermute.  Every lane of the group ends with the identical value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int W>
+__device__ __forceinline__ double gsum(double v) {
+  if constexpr (W >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  if constexpr (W >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  if constexpr (W >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
+  if constexpr (W >= 16) v += dpp_mov<0x140>(v);  // row_mirror
+  if constexpr (W >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (W >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -58,6 +74,14 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
 // offset of reflector j's entries i >= j + 2 in packed storage
 __device__ __forceinline__ int refl_off(int j, int N) { return j * (N - 2) - (j * (j - 1)) / 2; }
 
+// f / q through the hardware reciprocal refined by one Newton step (a few ulp; the Sturm
+// count only needs the sign pattern of the recurrence)
+__device__ __forceinline__ double fdiv(double f, double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return f * r;
+}
+
 // number of eigenvalues of T (scaled, diagonal d, squared off-diagonal e2) below x
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int N, double x,
                                            double pivmin) {
@@ -71,17 +95,17 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
   for (; i + 3 < N; i += 4) {
     const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
     const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
-    q = (d0 - x) - f0 / q;
+    q = (d0 - x) - fdiv(f0, q);
     if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d1 - x) - f1 / q;
+    q = (d1 - x) - fdiv(f1, q);
     if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d2 - x) - f2 / q;
+    q = (d2 - x) - fdiv(f2, q);
     if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d3 - x) - f3 / q;
+    q = (d3 - x) - fdiv(f3, q);
     if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
   }
   for (; i < N; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - fdiv(e2[i - 1], q);
     if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
   }
   return cnt;
@@ -154,7 +178,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
       const int i = BR * R + a;
       if (i / BC == Cc) t += A[a][a % BC].x;   // BR is a multiple of BC
     }
-    t = xsum(t, 32);
+    t = gsum<32>(t);
     if (Cc == 0) trp[R] = t;
   }
   if (Cc == 0) {
@@ -169,7 +193,11 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
   }
 
   // ---------------------------------------------------------------- 2. tridiagonalisation
-  double* refl = B.P;   // packed reflector entries i >= j + 2, complex interleaved
+  // Reflector entries i >= j + 2 are kept in LDS while reducing (a global store inside the
+  // loop would make every barrier wait for its completion); they are spilled to the workspace
+  // in one pass afterwards, because the eigenvector phase reuses this LDS.
+  z64* Rf = reinterpret_cast<z64*>(dyn);
+  double* refl = B.P;
   auto step = [&](const int j, auto bbc) {
     constexpr int bb = decltype(bbc)::value;   // j % BC
     // reflector from column j (every half-wave redundantly; lane Cc owns entries BC Cc + b)
@@ -182,7 +210,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
       cv[b] = col_buf[i];
       if (i > j + 1 && i < N) xn2 += cv[b].x * cv[b].x + cv[b].y * cv[b].y;
     }
-    xn2 = xsum(xn2, 32);
+    xn2 = gsum<32>(xn2);
     double beta = alpha.x;
     z64 tau = zmk(0, 0), sc = zmk(0, 0);
     const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
@@ -204,11 +232,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
       for (int b = 0; b < BC; ++b) {
         const int i = BC * Cc + b;
         vbuf[i] = vloc[b];
-        if (i >= j + 2 && i < N) {
-          const int o = refl_off(j, N) + (i - j - 2);
-          refl[2 * o] = vloc[b].x;
-          refl[2 * o + 1] = vloc[b].y;
-        }
+        if (i >= j + 2 && i < N) Rf[refl_off(j, N) + (i - j - 2)] = vloc[b];
       }
       if (tid == 0) {
         d_s[j] = col_buf[j].x;
@@ -217,16 +241,23 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
         tau_s[2 * j + 1] = tau.y;
       }
     }
-    // p = tau A v for this thread's rows, reduced over the half-wave
+    // p = tau A v for this thread's rows, reduced over the half-wave; row blocks that lie
+    // entirely in the eliminated part (rows <= j) only publish zeros
+    const bool live = BR * R + BR - 1 > j;   // uniform over the half-wave
+    if (live) {
 #pragma unroll
-    for (int a = 0; a < BR; ++a) {
-      z64 s = zmk(0, 0);
+      for (int a = 0; a < BR; ++a) {
+        z64 s = zmk(0, 0);
 #pragma unroll
-      for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
-      s.x = xsum(s.x, 32);
-      s.y = xsum(s.y, 32);
-      const int i = BR * R + a;
-      if (Cc == 0) pbuf[i] = (i > j && i < N) ? zmul(tau, s) : zmk(0, 0);
+        for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+        s.x = gsum<32>(s.x);
+        s.y = gsum<32>(s.y);
+        const int i = BR * R + a;
+        if (Cc == 0) pbuf[i] = (i > j && i < N) ? zmul(tau, s) : zmk(0, 0);
+      }
+    } else if (Cc == 0) {
+#pragma unroll
+      for (int a = 0; a < BR; ++a) pbuf[BR * R + a] = zmk(0, 0);
     }
     __syncthreads();
     // alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
@@ -237,9 +268,10 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
       pcol[b] = pbuf[BC * Cc + b];
       dt = zadd(dt, zcmul(pcol[b], vloc[b]));
     }
-    dt.x = xsum(dt.x, 32);
-    dt.y = xsum(dt.y, 32);
+    dt.x = gsum<32>(dt.x);
+    dt.y = gsum<32>(dt.y);
     const z64 alpha2 = zscale(zmul(tau, dt), -0.5);
+    if (live) {
 #pragma unroll
     for (int a = 0; a < BR; ++a) {
       const z64 vr = vbuf[BR * R + a];
@@ -249,6 +281,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
         const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
         A[a][b] = zsub(A[a][b], zadd(zmul(vr, zconj(wc)), zmul(wr, zconj(vloc[b]))));
       }
+    }
     }
     // owners of column j + 1 broadcast it for the next step
     if (Cc == (j + 1) / BC) {
@@ -267,6 +300,11 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
   if (tid == 0) {
     d_s[N - 1] = col_buf[N - 1].x;
     e_s[N - 1] = 0.0;
+  }
+  const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
+  for (int e = tid; e < nref; e += NTH) {
+    refl[2 * e] = Rf[e].x;
+    refl[2 * e + 1] = Rf[e].y;
   }
   __syncthreads();
 
@@ -336,18 +374,21 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
 
   // ---------------------------------------------------------------- 4. eigenvectors of T
   const int KP = kmax;
-  double* Dp = dyn;              // LDL^T pivots, [i * KP + t]
+  double* Dp = dyn;              // inverse LDL^T pivots, [i * KP + t]
   double* X = dyn + NP * KP;     // vectors, [i * KP + t]
   if (tid < kmax) {
     const int t = tid;
     const double sigma = lam_s[t];
+    // pivots D_i of T - sigma I = L D L^T, stored as 1 / D_i
     double dp = d_s[0] - sigma;
     if (fabs(dp) < pivmin) dp = -pivmin;
-    Dp[t] = dp;
+    double rinv = 1.0 / dp;
+    Dp[t] = rinv;
     for (int i = 1; i < N; ++i) {
-      dp = (d_s[i] - sigma) - e2_s[i - 1] / dp;
+      dp = (d_s[i] - sigma) - e2_s[i - 1] * rinv;
       if (fabs(dp) < pivmin) dp = -pivmin;
-      Dp[i * KP + t] = dp;
+      rinv = 1.0 / dp;
+      Dp[i * KP + t] = rinv;
     }
     for (int i = 0; i < N; ++i) X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
   }
@@ -357,20 +398,19 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
       const int t = tid;
       // forward: y_i -= l_{i-1} y_{i-1}, l_{i-1} = e_{i-1} / D_{i-1}
       double y = X[t];
-      double dprev = Dp[t];
+      double rprev = Dp[t];
       for (int i = 1; i < N; ++i) {
-        const double di = Dp[i * KP + t];
-        y = X[i * KP + t] - (e_s[i - 1] / dprev) * y;
+        const double ri = Dp[i * KP + t];
+        y = X[i * KP + t] - (e_s[i - 1] * rprev) * y;
         X[i * KP + t] = y;
-        dprev = di;
+        rprev = ri;
       }
-      // backward: x_i = y_i / D_i - l_i x_{i+1}
-      double xn = X[(N - 1) * KP + t] / Dp[(N - 1) * KP + t];
+      // backward: x_i = (y_i - e_i x_{i+1}) / D_i
+      double xn = X[(N - 1) * KP + t] * Dp[(N - 1) * KP + t];
       X[(N - 1) * KP + t] = xn;
       double mx = fabs(xn);
       for (int i = N - 2; i >= 0; --i) {
-        const double di = Dp[i * KP + t];
-        xn = X[i * KP + t] / di - (e_s[i] / di) * xn;
+        xn = (X[i * KP + t] - e_s[i] * xn) * Dp[i * KP + t];
         X[i * KP + t] = xn;
         mx = fmax(mx, fabs(xn));
       }
@@ -392,12 +432,12 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
         for (int ii = cs; ii < jj; ++ii) {
           double dtt = 0;
           for (int i = lane; i < N; i += 64) dtt += X[i * KP + ii] * X[i * KP + jj];
-          dtt = xsum(dtt, 64);
+          dtt = gsum<64>(dtt);
           for (int i = lane; i < N; i += 64) X[i * KP + jj] -= dtt * X[i * KP + ii];
         }
         double nn = 0;
         for (int i = lane; i < N; i += 64) nn += X[i * KP + jj] * X[i * KP + jj];
-        nn = xsum(nn, 64);
+        nn = gsum<64>(nn);
         const double s2 = (nn > 0) ? 1.0 / sqrt(nn) : 0.0;
         for (int i = lane; i < N; i += 64) X[i * KP + jj] *= s2;
       }
@@ -459,9 +499,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
     z[s] = zmk((col < k && i < N) ? (zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col]) : 0.0, 0.0);
   }
   __syncthreads();
-  // stage the reflectors in LDS (packed, complex)
-  z64* Rf = reinterpret_cast<z64*>(dyn);
-  const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
+  // bring the reflectors back into LDS
   for (int e = tid; e < nref; e += NTH) Rf[e] = zmk(refl[2 * e], refl[2 * e + 1]);
   __syncthreads();
   if (col < k) {
@@ -478,8 +516,8 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
           s = zadd(s, zcmul(v, z[q]));
         }
       }
-      s.x = xsum(s.x, LPC);
-      s.y = xsum(s.y, LPC);
+      s.x = gsum<LPC>(s.x);
+      s.y = gsum<LPC>(s.y);
       const z64 ts = zmul(tj, s);
 #pragma unroll
       for (int q = 0; q < ZR; ++q) {

@@ -12,7 +12,8 @@
 // columns): R = X_r^T X_r, S_jk = (R[2j,2k] + R[2j+1,2k+1]) + i (R[2j,2k+1] - R[2j+1,2k]).
 // R is a tall-skinny SYRK: only its upper 16x16 tiles are computed with v_mfma_*_16x16x4, each
 // work-group reduces a contiguous slab of rows into a private partial (split-K), and a second
-// kernel sums the partials in a fixed order in FP64 (deterministic).
+// kernel sums the partials in a fixed order in FP64 (deterministic).  Row chunks are staged
+// through two LDS buffers, the next one fetched into registers during the MFMAs.
 #include <utility>
 
 #include "lrdm_internal.h"
@@ -102,13 +103,25 @@ __device__ __forceinline__ void gram_store(T* __restrict__ out, const typename A
   });
 }
 
+typedef float gf4 __attribute__((ext_vector_type(4)));   // 16-byte register unit
+
+// The chunk loop is software-pipelined: the next kGramKC rows are fetched into registers while
+// the MFMAs consume the current chunk from one of two LDS buffers (one barrier per chunk).
 template <class T, int F>
-__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx_t<T>* __restrict__ L, int ld, int c,
-                                                      int nsplit, int q, T* __restrict__ partials,
-                                                      uint32_t rows, uint32_t rows_per_block) {
+__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx_t<T>* __restrict__ L, int ld,
+                                                                       int seg_shift, int nsplit, int q,
+                                                                       T* __restrict__ partials, uint32_t rows,
+                                                                       uint32_t rows_per_block) {
   using Cfg = GramCfg<T, F>;
   using A4 = typename Acc4<T>::type;
-  __shared__ __attribute__((aligned(16))) T lds[kGramKC * Cfg::STRIDE];
+  constexpr int VPR = 16 / sizeof(T);          // reals per 16-byte unit
+  constexpr int UPR = F / VPR;                 // 16-byte units per row
+  constexpr int UNITS = kGramKC * UPR;         // 16-byte units per chunk
+  constexpr int UPT = UNITS / Cfg::THREADS;    // per thread
+  static_assert(UNITS % Cfg::THREADS == 0, "chunk must split evenly");
+  extern __shared__ __attribute__((aligned(16))) unsigned char gram_smem[];
+  T* lds0 = reinterpret_cast<T*>(gram_smem);
+  T* lds1 = lds0 + kGramKC * Cfg::STRIDE;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -116,45 +129,57 @@ __global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx
 #pragma unroll
   for (int s = 0; s < Cfg::PER_WAVE; ++s) acc[s] = A4{0, 0, 0, 0};
 
-  constexpr int VPR = 16 / sizeof(T);          // reals per 16-byte unit
-  constexpr int UNITS = kGramKC * F / VPR;     // 16-byte units per chunk
-  const int seg = 2 * c;                       // reals per half-row segment
   const uint32_t r_begin = blockIdx.x * rows_per_block;
   const uint32_t r_end = min(rows, r_begin + rows_per_block);
   const T* Lr = reinterpret_cast<const T*>(L);
+  const int seg_mask = (1 << seg_shift) - 1;
 
-  for (uint32_t r0 = r_begin; r0 < r_end; r0 += kGramKC) {
-    // stage kGramKC rows of X_r into LDS (zeros past the end)
-#pragma unroll 4
-    for (int u = tid; u < UNITS; u += Cfg::THREADS) {
-      const int rr = u / (F / VPR);
-      const int f = (u % (F / VPR)) * VPR;
+  gf4 buf[UPT];
+  auto fetch = [&](uint32_t r0) {
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int u = tid + k * Cfg::THREADS;
+      const int rr = u / UPR, f = (u % UPR) * VPR;
       const uint32_t y = r0 + rr;
-      const int h = f / seg;
-      const int w = f - h * seg;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      gf4 val = {0.f, 0.f, 0.f, 0.f};
       if (y < r_end) {
+        const int h = f >> seg_shift, w = f & seg_mask;
         uint32_t x = y;
-        if (nsplit == 2) {
-          const uint32_t lo = y & ((1u << q) - 1u);
-          x = (((y >> q) << (q + 1)) | lo) | ((uint32_t)h << q);
-        }
-        val = *reinterpret_cast<const float4*>(Lr + ((size_t)x * ld) * 2 + w);
+        if (nsplit == 2) x = ((((y >> q) << (q + 1)) | (y & ((1u << q) - 1u))) | ((uint32_t)h << q));
+        val = *reinterpret_cast<const gf4*>(Lr + ((size_t)x * ld) * 2 + w);
       }
-      *reinterpret_cast<float4*>(lds + rr * Cfg::STRIDE + f) = val;
+      buf[k] = val;
     }
-    __syncthreads();
+  };
+  auto stage = [&](T* dst) {
+#pragma unroll
+    for (int k = 0; k < UPT; ++k) {
+      const int u = tid + k * Cfg::THREADS;
+      *reinterpret_cast<gf4*>(dst + (u / UPR) * Cfg::STRIDE + (u % UPR) * VPR) = buf[k];
+    }
+  };
+  auto mma = [&](const T* src) {
     switch (wave) {
-      case 0: gram_chunk_mma<T, F, 0>(lds, acc, lane); break;
-      case 1: gram_chunk_mma<T, F, 1>(lds, acc, lane); break;
-      case 2: gram_chunk_mma<T, F, 2>(lds, acc, lane); break;
-      case 3: gram_chunk_mma<T, F, 3>(lds, acc, lane); break;
-      case 4: if constexpr (Cfg::NW > 4) gram_chunk_mma<T, F, 4>(lds, acc, lane); break;
-      case 5: if constexpr (Cfg::NW > 5) gram_chunk_mma<T, F, 5>(lds, acc, lane); break;
-      case 6: if constexpr (Cfg::NW > 6) gram_chunk_mma<T, F, 6>(lds, acc, lane); break;
-      default: if constexpr (Cfg::NW > 7) gram_chunk_mma<T, F, 7>(lds, acc, lane); break;
+      case 0: gram_chunk_mma<T, F, 0>(src, acc, lane); break;
+      case 1: gram_chunk_mma<T, F, 1>(src, acc, lane); break;
+      case 2: gram_chunk_mma<T, F, 2>(src, acc, lane); break;
+      case 3: gram_chunk_mma<T, F, 3>(src, acc, lane); break;
+      case 4: if constexpr (Cfg::NW > 4) gram_chunk_mma<T, F, 4>(src, acc, lane); break;
+      case 5: if constexpr (Cfg::NW > 5) gram_chunk_mma<T, F, 5>(src, acc, lane); break;
+      case 6: if constexpr (Cfg::NW > 6) gram_chunk_mma<T, F, 6>(src, acc, lane); break;
+      default: if constexpr (Cfg::NW > 7) gram_chunk_mma<T, F, 7>(src, acc, lane); break;
     }
+  };
+
+  if (r_begin < r_end) fetch(r_begin);
+  bool odd = false;
+  for (uint32_t r0 = r_begin; r0 < r_end; r0 += kGramKC) {
+    T* cur = odd ? lds1 : lds0;
+    stage(cur);
     __syncthreads();
+    if (r0 + kGramKC < r_end) fetch(r0 + kGramKC);
+    mma(cur);
+    odd = !odd;
   }
   T* out = partials + (size_t)blockIdx.x * Cfg::NUP * 256;
   switch (wave) {
@@ -181,8 +206,17 @@ static hipError_t launch_gram_f(const cx_t<T>* L, int n, int ld, int c, int nspl
   const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
   const uint32_t chunks = (rows + kGramKC - 1) / kGramKC;
   const uint32_t cpb = (chunks + nblocks - 1) / nblocks;
-  hipLaunchKernelGGL((gram_kernel<T, F>), dim3(nblocks), dim3(GramCfg<T, F>::THREADS), 0, s, L, ld, c, nsplit, q,
-                     partials, rows, cpb * kGramKC);
+  int seg_shift = 0;
+  while ((1 << seg_shift) < 2 * c) ++seg_shift;
+  if ((1 << seg_shift) != 2 * c) return hipErrorInvalidValue;
+  const size_t shm = 2 * (size_t)kGramKC * GramCfg<T, F>::STRIDE * sizeof(T);
+  if (shm > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_kernel<T, F>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((gram_kernel<T, F>), dim3(nblocks), dim3(GramCfg<T, F>::THREADS), shm, s, L, ld,
+                     seg_shift, nsplit, q, partials, rows, cpb * kGramKC);
   return hipGetLastError();
 }
 

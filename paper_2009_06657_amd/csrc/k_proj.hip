@@ -10,8 +10,9 @@
 // [[w_re, w_im], [-w_im, w_re]] on v_mfma_*_16x16x4.
 //
 // Tiling: a work-group owns 128 rows of X (32 per wave) and all output columns; K is streamed
-// in chunks of 32 reals through LDS together with the matching 32 rows of the expanded W.
-// Every row is read before any row is written, and no other work-group touches these rows.
+// in chunks of 32 reals through LDS together with the matching 32 rows of the expanded W, the
+// next chunk prefetched into registers during the MFMAs.  Every row is read before any row is
+// written, and no other work-group touches these rows.
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -31,25 +32,35 @@ __device__ __forceinline__ pv4d pmfma16(double a, double b, pv4d c) {
 
 constexpr int kProjBM = 128;   // rows per work-group
 constexpr int kProjKC = 32;    // reals of K per chunk
-constexpr int kProjXS = kProjKC + 2;   // LDS row stride of the X chunk
+constexpr int kProjXS = kProjKC + 2;   // LDS row stride of the X chunk (8-byte aligned rows)
 
+template <class T> struct PPair;   // two reals, the unit of the X-chunk staging
+template <> struct PPair<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct PPair<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// Software pipeline over K chunks: the next chunk of X rows and of W rows is fetched into
+// registers while the MFMAs consume the current chunk from LDS.
 template <class T, int FO>
-__global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L, int ld, int c_in,
-                                                         int nsplit, int q, int c_out,
+__global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L, int ld, int F,
+                                                         int seg_in_shift, int nsplit, int q,
+                                                         int seg_out_shift,
                                                          const cx_t<T>* __restrict__ W,
                                                          uint32_t rows) {
   using A4 = typename PAcc4<T>::type;
+  using P2 = typename PPair<T>::type;
   constexpr int NTO = FO / 16;
-  constexpr int WS = FO + 16;   // LDS row stride of the W chunk
+  constexpr int FCO = FO / 2;              // complex output columns of W
+  constexpr int WS = FO + 16;              // LDS row stride of the W chunk
+  constexpr int XPT = kProjBM * kProjKC / 2 / 256;            // X pairs per thread
+  constexpr int WPT = (kProjKC / 2) * FCO / 256;              // W entries per thread (may be 0)
+  constexpr int WREM = (kProjKC / 2) * FCO - WPT * 256;       // leftover W entries
   __shared__ __attribute__((aligned(16))) T xs[kProjBM * kProjXS];
   __shared__ __attribute__((aligned(16))) T ws[kProjKC * WS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, kq = lane >> 4;
   const uint32_t y0 = blockIdx.x * kProjBM;
-  const int F = 2 * nsplit * c_in;          // input reals per row
-  const int seg_in = 2 * c_in;
-  const int fco = FO / 2;                   // complex output columns of W
+  const int seg_in_mask = (1 << seg_in_shift) - 1;
   T* Lr = reinterpret_cast<T*>(L);
   const T* Wr = reinterpret_cast<const T*>(W);
 
@@ -61,41 +72,63 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
 
   auto row_index = [&](uint32_t y, int h) -> uint32_t {
     if (nsplit == 1) return y;
-    const uint32_t lo = y & ((1u << q) - 1u);
-    return (((y >> q) << (q + 1)) | lo) | ((uint32_t)h << q);
+    return ((((y >> q) << (q + 1)) | (y & ((1u << q) - 1u))) | ((uint32_t)h << q));
   };
 
-  for (int kc = 0; kc < F; kc += kProjKC) {
-    // X chunk: 128 rows x 32 reals, two reals per thread-step
-    for (int e = tid; e < kProjBM * kProjKC / 2; e += 256) {
-      const int rr = e / (kProjKC / 2);
-      const int f = kc + (e % (kProjKC / 2)) * 2;
+  P2 xb[XPT];
+  P2 wb[WPT > 0 ? WPT : 1];
+  P2 wr1 = {0, 0};
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int e = tid + k * 256;
+      const int rr = e >> 4, f = kc + ((e & 15) << 1);
       const uint32_t y = y0 + rr;
-      T a = 0, b = 0;
+      P2 v = {0, 0};
       if (y < rows && f < F) {
-        const int h = f / seg_in;
-        const int w = f - h * seg_in;
-        const T* src = Lr + ((size_t)row_index(y, h) * ld) * 2 + w;
-        a = src[0];
-        b = src[1];
+        const int h = f >> seg_in_shift, w = f & seg_in_mask;
+        v = *reinterpret_cast<const P2*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w);
       }
-      xs[rr * kProjXS + (f - kc)] = a;
-      xs[rr * kProjXS + (f - kc) + 1] = b;
+      xb[k] = v;
     }
-    // W chunk: complex rows kc/2 .. kc/2 + 15 expanded to 32 real rows
-    for (int e = tid; e < (kProjKC / 2) * fco; e += 256) {
-      const int pr = e / fco, qc = e % fco;
-      const size_t gi = ((size_t)(kc / 2 + pr) * fco + qc) * 2;
-      const bool in = (kc / 2 + pr) < F / 2;
-      const T re = in ? Wr[gi] : (T)0, im = in ? Wr[gi + 1] : (T)0;
-      T* w0 = ws + (2 * pr) * WS + 2 * qc;
-      T* w1 = w0 + WS;
-      w0[0] = re;
-      w0[1] = im;
-      w1[0] = -im;
-      w1[1] = re;
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const int e = tid + k * 256;
+      const int pr = e / FCO, qc = e % FCO;
+      P2 v = {0, 0};
+      if (kc / 2 + pr < F / 2) v = *reinterpret_cast<const P2*>(Wr + ((size_t)(kc / 2 + pr) * FCO + qc) * 2);
+      wb[k] = v;
     }
+    if (WREM > 0 && tid < WREM) {
+      const int e = tid + WPT * 256;
+      const int pr = e / FCO, qc = e % FCO;
+      P2 v = {0, 0};
+      if (kc / 2 + pr < F / 2) v = *reinterpret_cast<const P2*>(Wr + ((size_t)(kc / 2 + pr) * FCO + qc) * 2);
+      wr1 = v;
+    }
+  };
+  auto put_w = [&](int e, P2 v) {
+    const int pr = e / FCO, qc = e % FCO;
+    T* w0 = ws + (2 * pr) * WS + 2 * qc;
+    *reinterpret_cast<P2*>(w0) = v;                          // ( re, im)
+    *reinterpret_cast<P2*>(w0 + WS) = P2{-v[1], v[0]};        // (-im, re)
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int k = 0; k < XPT; ++k) {
+      const int e = tid + k * 256;
+      *reinterpret_cast<P2*>(xs + (e >> 4) * kProjXS + ((e & 15) << 1)) = xb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) put_w(tid + k * 256, wb[k]);
+    if (WREM > 0 && tid < WREM) put_w(tid + WPT * 256, wr1);
+  };
+
+  fetch(0);
+  for (int kc = 0; kc < F; kc += kProjKC) {
+    stage();
     __syncthreads();
+    if (kc + kProjKC < F) fetch(kc + kProjKC);
 #pragma unroll
     for (int ks = 0; ks < kProjKC / 4; ++ks) {
       const T a0 = xs[(32 * wave + m) * kProjXS + 4 * ks + kq];
@@ -112,7 +145,7 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
   }
 
   // write back: output real column f -> half h, real offset w inside that half
-  const int seg_out = 2 * c_out;
+  const int seg_out_mask = (1 << seg_out_shift) - 1;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -124,8 +157,8 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
 #pragma unroll
       for (int t = 0; t < NTO; ++t) {
         const int f = 16 * t + m;
-        const int h = f / seg_out;
-        const int w = f - h * seg_out;
+        const int h = f >> seg_out_shift;
+        const int w = f & seg_out_mask;
         Lr[((size_t)row_index(y, h) * ld) * 2 + w] = acc[r][t][v];
       }
     }
@@ -137,8 +170,12 @@ static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit,
                                 const cx_t<T>* W, hipStream_t s) {
   const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
   const uint32_t blocks = (rows + kProjBM - 1) / kProjBM;
-  hipLaunchKernelGGL((project_kernel<T, FO>), dim3(blocks), dim3(256), 0, s, L, ld, c_in, nsplit, q,
-                     c_out, W, rows);
+  int si = 0, so = 0;
+  while ((1 << si) < 2 * c_in) ++si;
+  while ((1 << so) < 2 * c_out) ++so;
+  if ((1 << si) != 2 * c_in || (1 << so) != 2 * c_out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((project_kernel<T, FO>), dim3(blocks), dim3(256), 0, s, L, ld, 2 * nsplit * c_in,
+                     si, nsplit, q, so, W, rows);
   return hipGetLastError();
 }
 

@@ -39,6 +39,33 @@ def algorithmic_flops(n: int, r_pad: int, cls: int) -> float:
     raise ValueError(cls)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "projection_brickwork_n20_r64_hbm_counters.md")
+CLASS_SOURCE = {0: "k_gate.hip", 1: "k_gram.hip", 4: "k_proj.hip"}
+
+
+def measured_traffic(cls: int):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter read for a 1 GiB copy), or None
+    when there is no summary or the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    key = CLASS_NAMES[cls]
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    m = re.search(rf"^traffic_bytes_per_launch {key}: (\d+)$", text, re.M)
+    src = CLASS_SOURCE.get(cls)
+    h = re.search(rf"^kernel_source_sha256 {re.escape(src)}: ([0-9a-f]+)$", text, re.M) if src else None
+    if not m or not h:
+        return None
+    path = os.path.join(ROOT, "paper_2009_06657_amd", "csrc", src)
+    if hashlib.sha256(open(path, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return int(m.group(1))
+
+
 def run_step(dm, prog, uniforms):
     from paper_2009_06657_amd import run_program
 
@@ -91,6 +118,19 @@ def cpu_baseline(n: int, r: int, budget_s: float = 20.0) -> dict:
                        f"{per_comp:.2f} s per compress)")}
 
 
+def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
+    """A plain device-to-device copy of a known size: the HBM counters read for it (bytes
+    fetched, bytes written per dispatch) give the scale factor applied to the same counters
+    read for the path's kernels."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +139,8 @@ def main():
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -106,6 +148,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calib:
+        copy_calibration(torch)
+        return
 
     import paper_2009_06657_amd as lr
     from workloads import circuits as C
@@ -143,7 +189,7 @@ def main():
                    "eigensolve": "f64", "trace_after": tr},
         "roofline": {"bound": "mfma", "kernel": CLASS_NAMES[dominant], "achieved": achieved / 1e12,
                      "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK,
-                     "traffic": None, "launches": nl, "mean_ms": mean_ms},
+                     "traffic": measured_traffic(dominant), "launches": nl, "mean_ms": mean_ms},
     }
     if not args.no_breakdown:
         br = {}

@@ -155,6 +155,63 @@ lrdm_status lrdm_synchronize(lrdm_t h);
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class);
 lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* total_ms);
 
+/* ---------------------------------------------------------------- reverse sweep (gradients)
+ * The paper defines the forward map only.  These calls give the exact derivative of an energy
+ * E = sum_t c_t Tr(L^H P_t L) of the final factor (Sec. II.D) with respect to the angles of
+ * rotation gates R_P(theta) = exp(-i theta P / 2), by one reverse sweep over the same operations.
+ * The adjoint factor Lbar (dE = 2 Re Tr(Lbar^H dL)) lives in a second handle of the same n,
+ * r_max, dtype, m_max and form (the "bar" handle).  The sweep needs the fused form and
+ * m_max * r_pad <= 64 (every eigenpair of G is recorded); otherwise LRDM_E_UNSUPPORTED. */
+
+/* Bytes of one compression record: the FP64 eigen-decomposition of G kept for the reverse sweep
+ * (8 + N + 2 N^2 doubles, N = m_max * r_pad, rounded up to 256 bytes). */
+lrdm_status lrdm_record_bytes(lrdm_t h, size_t* bytes);
+
+/* lrdm_compress that also writes its record to rec_dev (device memory, lrdm_record_bytes bytes,
+ * 256-byte aligned, owned by the caller): k, the scale c, Tr G, the renorm flag, every eigenvalue
+ * of G (descending) and every eigenvector (N x N complex, column j = eigenvector j).  All N
+ * eigenvectors are formed, so the call costs more than lrdm_compress; the kept factor is the
+ * same.  A Kraus channel must be pending.  Queued; info as in lrdm_compress. */
+lrdm_status lrdm_compress_record(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
+                                 void* rec_dev, lrdm_compress_info* info);
+
+/* Copy the whole state buffer (state_bytes of device memory owned by the caller) to dst_dev;
+ * rank_out (nullable) receives the column bound.  Pending gates are applied first.  Queued. */
+lrdm_status lrdm_checkpoint(lrdm_t h, void* dst_dev, int* rank_out);
+
+/* Replace the state buffer by a copy made with lrdm_checkpoint on a handle of the same shape;
+ * `rank` is the column bound it returned.  Pending gates are discarded.  Queued. */
+lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank);
+
+/* dst's factor <- H src's factor, H = sum_t coeff[t] P_t (Pauli strings as in
+ * lrdm_expect_pauli), column by column: the reverse-sweep seed Lbar = H L of
+ * E = Tr(L^H H L).  dst and src must be different handles of the same shape.  n_terms in
+ * [1, 4096].  Synchronises dst's stream (and src's when the streams differ). */
+lrdm_status lrdm_apply_pauli_sum(lrdm_t dst, lrdm_t src, int n_terms, const uint64_t* xmask,
+                                 const uint64_t* zmask, const double* coeff);
+
+/* out_host[2t], out_host[2t + 1] = Re, Im of Tr(bra^H P_t ket) for n_terms Pauli strings (as in
+ * lrdm_expect_pauli; bra and ket are handles of the same shape).  With bra = Lbar and ket = L
+ * taken right after a gate R_P(theta) on one qubit, dE/dtheta = Im Tr(Lbar^H P L).  n_terms in
+ * [1, 65536].  Synchronises. */
+lrdm_status lrdm_pauli_overlap(lrdm_t bra, lrdm_t ket, int n_terms, const uint64_t* xmask,
+                               const uint64_t* zmask, double* out_host);
+
+/* Reverse of one Kraus channel and the compression after it (Eq. "low rank evolution K",
+ * Sec. II.B, Theorem 1).  On entry bar holds Lbar_n, the adjoint of the compressed factor
+ * L_n = c L' V_K; x_dev is the forward factor before the channel (a lrdm_checkpoint copy of the
+ * forward handle, state layout); rec_dev the record of that compression; (qubit, m, e) the
+ * channel as given to lrdm_apply_kraus.  On return bar holds Lbar = sum_a E_a^H Lbar'_a with
+ *   Lbar' = c Lbar_n V_K^H + L' (Ghat + Ghat^H) - s c^2 L' V_K V_K^H,
+ *   Ghat = V_K Zhat^H V_D^H, Zhat_ji = [V_D^H (c L'^H Lbar_n)]_ji / (lambda_i - lambda_j),
+ *   s = Re Tr(Lbar_n^H L_n) (the last term only when the record says renorm = 1),
+ * the first-order change of the kept spectral projector of G and of c.  Pairs with
+ * |lambda_i - lambda_j| <= 1e-13 Tr G (null space of L') are skipped.  The channel is not
+ * materialised: C = X^H Ybar on the split view, the small matrices in FP64, then
+ * [Lbar_0 | Lbar_1] = Ybar P + X Q in place.  Queued. */
+lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec_dev, int qubit,
+                                  int m, const double* e);
+
 /* Last error message for h, or the calling thread's last error when h == NULL. */
 const char* lrdm_last_error(lrdm_t h);
 

@@ -488,6 +488,8 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
   for (int t = tid; t < kmax; t += NTH) B.lam[t] = lam_s[t];
   const int k = k_s;
   const double scl = sc_s[2];
+  // with a record every eigenvector is formed (kmax == N <= 64), else only the kept ones
+  const int nvec = B.rec ? N : k;
   // LPC lanes per kept column (64 columns); lane g holds rows g, g + LPC, ...
   constexpr int LPC = NTH / 64;
   const int col = tid / LPC, g = tid % LPC;
@@ -496,13 +498,13 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
 #pragma unroll
   for (int s = 0; s < ZR; ++s) {
     const int i = g + LPC * s;
-    z[s] = zmk((col < k && i < N) ? (zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col]) : 0.0, 0.0);
+    z[s] = zmk((col < nvec && i < N) ? (zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col]) : 0.0, 0.0);
   }
   __syncthreads();
   // bring the reflectors back into LDS
   for (int e = tid; e < nref; e += NTH) Rf[e] = zmk(refl[2 * e], refl[2 * e + 1]);
   __syncthreads();
-  if (col < k) {
+  if (col < nvec) {
     for (int j = N - 2; j >= 0; --j) {
       const z64 tj = zmk(tau_s[2 * j], tau_s[2 * j + 1]);
       if (tj.x == 0.0 && tj.y == 0.0) continue;
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
   }
   __syncthreads();
   z64* V = reinterpret_cast<z64*>(dyn);   // V[i * 64 + col]
-  if (col < k) {
+  if (col < nvec) {
 #pragma unroll
     for (int s = 0; s < ZR; ++s) {
       const int i = g + LPC * s;
@@ -539,6 +541,23 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
     }
   }
   __syncthreads();
+  if (B.rec) {
+    double* rec = B.rec;
+    if (tid == 0) {
+      rec[0] = (double)k;
+      rec[1] = scl;
+      rec[2] = (double)N;
+      rec[3] = sc_s[0];
+      rec[4] = (double)renorm;
+    }
+    for (int t = tid; t < N; t += NTH) rec[kRecHeader + t] = lam_s[t];
+    double* rv = rec + kRecHeader + N;
+    for (int e = tid; e < N * N; e += NTH) {
+      const z64 v = V[(e / N) * 64 + (e % N)];
+      rv[2 * e] = v.x;
+      rv[2 * e + 1] = v.y;
+    }
+  }
   using C = cx_t<T>;
   if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
@@ -594,6 +613,7 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
                       int kmax, int r_target, double eps, int tie, int renorm, int c_out,
                       const EigBufs& b, cx_t<T>* W, hipStream_t s) {
   if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64) return hipErrorInvalidValue;
+  if (b.rec && (N > kRecMaxN || kmax != N)) return hipErrorInvalidValue;
   if (N <= 32) return launch_eig_bs<T, 1, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
   if (N <= 64) return launch_eig_bs<T, 2, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
   return launch_eig_bs<T, 8, 4>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);

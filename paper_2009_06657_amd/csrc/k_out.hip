@@ -124,7 +124,8 @@ hipError_t launch_zstats(const cx_t<T>* L, int n, int ld, int ncols, double* par
 constexpr int kPauliRPT = 4;   // rows per thread
 
 template <class T>
-__global__ __launch_bounds__(256) void pauli_partial_kernel(const cx_t<T>* __restrict__ L, uint32_t rows,
+__global__ __launch_bounds__(256) void pauli_partial_kernel(const cx_t<T>* __restrict__ Lbra,
+                                                            const cx_t<T>* __restrict__ L, uint32_t rows,
                                                             int ld, int ncols,
                                                             const uint64_t* __restrict__ xm,
                                                             const uint64_t* __restrict__ zm,
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(256) void pauli_partial_kernel(const cx_t<T>* __res
     xs[r] = x;
     double sr = 0, si = 0;
     if (x < rows) {
-      const cx_t<T>* a = L + (size_t)(x ^ xmask) * ld;
+      const cx_t<T>* a = Lbra + (size_t)(x ^ xmask) * ld;
       const cx_t<T>* b = L + (size_t)x * ld;
       for (int v = 0; v < ncols; ++v) {
         const cx_t<T> av = a[v], bv = b[v];
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(256) void pauli_partial_kernel(const cx_t<T>* __res
 
 __global__ void pauli_final_kernel(const double* __restrict__ part, int nchunks, int n_terms,
                                    const uint64_t* __restrict__ xm, const uint64_t* __restrict__ zm,
-                                   double* __restrict__ out) {
+                                   double* __restrict__ out, int complex_out) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= n_terms) return;
   double sr = 0, si = 0;
@@ -188,30 +189,35 @@ __global__ void pauli_final_kernel(const double* __restrict__ part, int nchunks,
     sr += part[((size_t)t * nchunks + b) * 2];
     si += part[((size_t)t * nchunks + b) * 2 + 1];
   }
-  // multiply by i^{ny}; the real part is the expectation value
+  // multiply by i^{ny}; for bra == ket the real part is the expectation value
   const int ny = __popcll(xm[t] & zm[t]) & 3;
-  double re;
+  double re, im;
   switch (ny) {
-    case 0: re = sr; break;
-    case 1: re = -si; break;
-    case 2: re = -sr; break;
-    default: re = si; break;
+    case 0: re = sr; im = si; break;
+    case 1: re = -si; im = sr; break;
+    case 2: re = -sr; im = -si; break;
+    default: re = si; im = -sr; break;
   }
-  out[t] = re;
+  if (complex_out) {
+    out[2 * t] = re;
+    out[2 * t + 1] = im;
+  } else {
+    out[t] = re;
+  }
 }
 
 template <class T>
-hipError_t launch_pauli(const cx_t<T>* L, int n, int ld, int ncols, const uint64_t* xm,
-                        const uint64_t* zm, int n_terms, double* partials, int ngroups,
-                        double* out, hipStream_t s) {
+hipError_t launch_pauli(const cx_t<T>* bra, const cx_t<T>* L, int n, int ld, int ncols,
+                        const uint64_t* xm, const uint64_t* zm, int n_terms, double* partials,
+                        int ngroups, double* out, int complex_out, hipStream_t s) {
   // partials layout: [n_terms * nchunks * 2] doubles; gstart (ngroups + 1 ints) follows zm.
   const uint32_t rows = 1u << n;
   const int nchunks = (int)((rows + 256 * kPauliRPT - 1) / (256 * kPauliRPT));
   const int* gstart = reinterpret_cast<const int*>(zm + n_terms);
-  hipLaunchKernelGGL(pauli_partial_kernel<T>, dim3(nchunks, ngroups), dim3(256), 0, s, L, rows, ld,
-                     ncols, xm, zm, gstart, partials, nchunks);
+  hipLaunchKernelGGL(pauli_partial_kernel<T>, dim3(nchunks, ngroups), dim3(256), 0, s, bra, L, rows,
+                     ld, ncols, xm, zm, gstart, partials, nchunks);
   hipLaunchKernelGGL(pauli_final_kernel, dim3((n_terms + 255) / 256), dim3(256), 0, s, partials,
-                     nchunks, n_terms, xm, zm, out);
+                     nchunks, n_terms, xm, zm, out, complex_out);
   return hipGetLastError();
 }
 
@@ -324,9 +330,9 @@ template hipError_t launch_probabilities<float>(const float2*, int, int, int, do
 template hipError_t launch_probabilities<double>(const double2*, int, int, int, double*, hipStream_t);
 template hipError_t launch_zstats<float>(const float2*, int, int, int, double*, int, double*, hipStream_t);
 template hipError_t launch_zstats<double>(const double2*, int, int, int, double*, int, double*, hipStream_t);
-template hipError_t launch_pauli<float>(const float2*, int, int, int, const uint64_t*, const uint64_t*,
-                                        int, double*, int, double*, hipStream_t);
-template hipError_t launch_pauli<double>(const double2*, int, int, int, const uint64_t*, const uint64_t*,
-                                         int, double*, int, double*, hipStream_t);
+template hipError_t launch_pauli<float>(const float2*, const float2*, int, int, int, const uint64_t*,
+                                        const uint64_t*, int, double*, int, double*, int, hipStream_t);
+template hipError_t launch_pauli<double>(const double2*, const double2*, int, int, int, const uint64_t*,
+                                         const uint64_t*, int, double*, int, double*, int, hipStream_t);
 
 }  // namespace lrdm

@@ -59,7 +59,15 @@ struct EigBufs {
   double* P;        // packed Householder reflector entries, (N-1)(N-2)/2 complex
   double* lam;      // kept-candidate eigenvalues, descending
   DevInfo* info;
+  double* rec;      // nullable: compression record for the reverse sweep (every eigenpair)
 };
+
+// Compression record (FP64), written by the eigensolver when EigBufs::rec is set:
+// [0] k, [1] scale c, [2] N, [3] Tr G, [4] renorm, [5..8) unused, [8, 8 + N) eigenvalues
+// (descending), then V as N x N complex row-major (column j = eigenvector j), interleaved.
+constexpr int kRecHeader = 8;
+inline size_t record_doubles(int N) { return (size_t)kRecHeader + N + 2 * (size_t)N * N; }
+constexpr int kRecMaxN = 64;      // largest Gram order with a full record
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
 template <class T>
@@ -94,10 +102,45 @@ template <class T>
 hipError_t launch_zstats(const cx_t<T>* L, int n, int ld, int ncols, double* partials,
                          int nblocks, double* out, hipStream_t s);
 
+// Tr(bra^H P_t ket) per term; out[t] = real part (complex_out = 0) or out[2t], out[2t + 1] =
+// (re, im) (complex_out = 1).  bra == ket gives expectation values.
 template <class T>
-hipError_t launch_pauli(const cx_t<T>* L, int n, int ld, int ncols, const uint64_t* xm,
-                        const uint64_t* zm, int n_terms, double* partials, int nblocks,
-                        double* out, hipStream_t s);
+hipError_t launch_pauli(const cx_t<T>* bra, const cx_t<T>* ket, int n, int ld, int ncols,
+                        const uint64_t* xm, const uint64_t* zm, int n_terms, double* partials,
+                        int nblocks, double* out, int complex_out, hipStream_t s);
+
+// ---------------------------------------------------------------- reverse sweep (k_adj.hip)
+// dst = sum_t coeff[t] P_t src, column by column (terms: xm[n], zm[n], coeff[n] as doubles).
+template <class T>
+hipError_t launch_pauli_apply(cx_t<T>* dst, const cx_t<T>* src, int n, int ld, int ncols,
+                              const uint64_t* xm, const uint64_t* zm, const double* coeff,
+                              int n_terms, hipStream_t s);
+
+// Scratch of the compression adjoint, carved from the workspace (all FP64 complex unless noted).
+struct AdjBufs {
+  double* part;     // cross-Gram partials, kAdjChunks x (2c)^2
+  double* C;        // (2c)^2, C = X^H Ybar on the split view
+  double* H;        // N x c
+  double* Zh;       // N x c
+  double* T1;       // N x N
+  double* Gh;       // N x N
+  double* M;        // N x N
+  void* P;          // (2c)^2 in the bulk precision
+  void* Q;          // (2c)^2 in the bulk precision
+};
+constexpr int kAdjChunks = 256;
+inline size_t adj_doubles(int c, int N) {
+  const size_t w = 2 * (size_t)c, e = w * w;
+  return 2 * (e * kAdjChunks + e + 2 * (size_t)N * c + 3 * (size_t)N * N) + 2 * 2 * e;
+}
+
+// Reverse of one fused channel + compression on qubit q: Ybar (the adjoint of the compressed
+// factor, state layout, c columns) is replaced in place by the adjoint of the factor before the
+// channel, given the forward factor X before the channel and the compression record.
+template <class T>
+hipError_t launch_compress_adjoint(cx_t<T>* Ybar, const cx_t<T>* X, int n, int ld, int c, int q,
+                                   const Channel& ch, const double* rec, const AdjBufs& b,
+                                   hipStream_t s);
 
 hipError_t launch_sample(const double* p, int n, double* cdf, double* block_sums,
                          const double* u, int count, uint64_t* out, hipStream_t s);

@@ -25,6 +25,7 @@ constexpr int kSampleBatch = 1 << 20;
 constexpr size_t kPauliPartDoubles = 4u << 20;
 constexpr int kZBlocks = 256;
 constexpr int kMaxTimed = 8192;
+constexpr int kMaxApplyTerms = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int next_pow2(int x) {
@@ -37,6 +38,8 @@ struct Layout {
   int r_pad, m_pad, ld, F_max, FO_max;
   size_t state_bytes;
   size_t off_info, off_part, off_S, off_P, off_lam, off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
+  bool adjoint;        // reverse sweep available (fused form, m_max * r_pad <= 64)
+  size_t off_adj, rec_bytes;
 };
 
 bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
@@ -79,6 +82,10 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   L.off_pauli = take(kPauliPartDoubles * 8);
   L.off_unif = take((size_t)kSampleBatch * 8);
   L.off_samp = take((size_t)kSampleBatch * 8);
+  const int N_rec = m_max * L.r_pad;
+  L.adjoint = !plain && N_rec <= kRecMaxN;
+  L.off_adj = L.adjoint ? take(adj_doubles(L.r_pad, N_rec) * 8) : 0;
+  L.rec_bytes = L.adjoint ? align_up(record_doubles(N_rec) * 8) : 0;
   L.total = o;
   return true;
 }
@@ -267,11 +274,29 @@ EigBufs eig_bufs(lrdm_t h) {
   b.P = h->ws<double>(h->lay.off_P);
   b.lam = h->ws<double>(h->lay.off_lam);
   b.info = h->ws<DevInfo>(h->lay.off_info);
+  b.rec = nullptr;
+  return b;
+}
+
+AdjBufs adj_bufs(lrdm_t h) {
+  const int c = h->lay.r_pad, N = h->m_max * c;
+  const size_t w2 = 2 * (size_t)c, e = w2 * w2;
+  double* p = h->ws<double>(h->lay.off_adj);
+  AdjBufs b;
+  b.part = p; p += 2 * e * kAdjChunks;
+  b.C = p; p += 2 * e;
+  b.H = p; p += 2 * (size_t)N * c;
+  b.Zh = p; p += 2 * (size_t)N * c;
+  b.T1 = p; p += 2 * (size_t)N * N;
+  b.Gh = p; p += 2 * (size_t)N * N;
+  b.M = p; p += 2 * (size_t)N * N;
+  b.P = p; p += 2 * e;
+  b.Q = p;
   return b;
 }
 
 template <class T>
-lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm) {
+lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, double* rec) {
   const int nsplit = (h->chan_pending && !h->plain) ? 2 : 1;
   const int q = nsplit == 2 ? h->chan_q : 0;
   Channel ch{};
@@ -288,10 +313,11 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm) 
     F = 2 * c;
   }
   const int Fc = F / 2;
-  const int kmax = std::min(r_target + 1, N);
+  const int kmax = rec ? N : std::min(r_target + 1, N);
   const int c_out = h->lay.r_pad;
   const int nb = gram_blocks(h->n, nsplit);
   EigBufs b = eig_bufs(h);
+  b.rec = rec;
   auto* L = static_cast<cx_t<T>*>(h->state);
   T* part = h->ws<T>(h->lay.off_part);
   cx_t<T>* W = h->ws<cx_t<T>>(h->lay.off_W);
@@ -324,6 +350,126 @@ lrdm_status reset_t(lrdm_t h) {
   h->c_bound = 1;
   h->gates.clear();
   h->chan_pending = false;
+  return LRDM_OK;
+}
+
+// completeness sum_a E_a^H E_a = I within 1e-10 (FP64)
+bool kraus_complete(int m, const double* e) {
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double re = 0, im = 0;
+      for (int a = 0; a < m; ++a)
+        for (int r = 0; r < 2; ++r) {
+          const double ar = e[((a * 2 + r) * 2 + i) * 2], ai = -e[((a * 2 + r) * 2 + i) * 2 + 1];
+          const double br = e[((a * 2 + r) * 2 + j) * 2], bi = e[((a * 2 + r) * 2 + j) * 2 + 1];
+          re += ar * br - ai * bi;
+          im += ar * bi + ai * br;
+        }
+      if (!(std::fabs(re - (i == j)) <= 1e-10 && std::fabs(im) <= 1e-10)) return false;
+    }
+  return true;
+}
+
+Channel make_channel(int m, const double* e) {
+  Channel ch{};
+  ch.m = m;
+  for (int a = 0; a < m; ++a)
+    for (int r = 0; r < 2; ++r)
+      for (int cidx = 0; cidx < 2; ++cidx)
+        for (int z = 0; z < 2; ++z) ch.e[a][r][cidx][z] = e[((a * 2 + r) * 2 + cidx) * 2 + z];
+  return ch;
+}
+
+bool same_shape(lrdm_t a, lrdm_t b) {
+  return a->n == b->n && a->lay.r_pad == b->lay.r_pad && a->dt == b->dt && a->m_max == b->m_max &&
+         a->plain == b->plain && a->lay.ld == b->lay.ld;
+}
+
+// Order work on a's stream before work that b's stream enqueues next.
+lrdm_status order_streams(lrdm_t a, lrdm_t b) {
+  if (a->stream != b->stream) HIPCHK(a, hipStreamSynchronize(a->stream));
+  return LRDM_OK;
+}
+
+lrdm_status check_masks(lrdm_t h, int n_terms, const uint64_t* xmask, const uint64_t* zmask) {
+  const uint64_t lim = (h->n >= 64) ? ~0ull : ((1ull << h->n) - 1ull);
+  for (int t = 0; t < n_terms; ++t)
+    if ((xmask[t] & ~lim) || (zmask[t] & ~lim)) return fail(h, LRDM_E_ARG, "Pauli mask beyond n qubits");
+  return LRDM_OK;
+}
+
+// Tr(bra^H P_t ket) for every term: vals[t] (real part) or vals[2t], vals[2t + 1] (complex).
+// Terms are grouped by X mask so that each distinct mask costs one pass over the rows.  Uses the
+// workspace and stream of h (the ket's handle).
+lrdm_status pauli_values(lrdm_t h, const void* bra, int n_terms, const uint64_t* xmask,
+                         const uint64_t* zmask, int complex_out, double* vals) {
+  std::vector<int> idx(n_terms);
+  for (int t = 0; t < n_terms; ++t) idx[t] = t;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
+  const uint32_t rows = 1u << h->n;
+  const int nchunks = (int)((rows + 1023) / 1024);
+  const int batch_cap = std::max(1, (int)(kPauliPartDoubles / (2 * (size_t)nchunks)));
+  const int cw = complex_out ? 2 : 1;
+  uint64_t* dterms = h->ws<uint64_t>(h->lay.off_terms);
+  double* dpart = h->ws<double>(h->lay.off_pauli);
+  double* dout = h->ws<double>(h->lay.off_out);
+  for (int b0 = 0; b0 < n_terms; b0 += std::min(batch_cap, 2048)) {
+    const int nb = std::min(n_terms - b0, std::min(batch_cap, 2048));
+    // staging: xm[nb], zm[nb], gstart[ngroups + 1] (int)
+    std::vector<uint64_t> xm(nb), zm(nb);
+    std::vector<int> gstart;
+    for (int t = 0; t < nb; ++t) {
+      xm[t] = xmask[idx[b0 + t]];
+      zm[t] = zmask[idx[b0 + t]];
+      if (t == 0 || xm[t] != xm[t - 1]) gstart.push_back(t);
+    }
+    const int ngroups = (int)gstart.size();
+    gstart.push_back(nb);
+    h->term_stage.assign(2 * nb + (gstart.size() + 1) / 2 + 1, 0);
+    std::memcpy(h->term_stage.data(), xm.data(), nb * 8);
+    std::memcpy(h->term_stage.data() + nb, zm.data(), nb * 8);
+    std::memcpy(h->term_stage.data() + 2 * nb, gstart.data(), gstart.size() * 4);
+    HIPCHK(h, hipMemcpyAsync(dterms, h->term_stage.data(), h->term_stage.size() * 8, hipMemcpyHostToDevice, h->stream));
+    hipError_t e = h->dt == LRDM_C64
+                       ? launch_pauli<float>(static_cast<const float2*>(bra), static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, complex_out, h->stream)
+                       : launch_pauli<double>(static_cast<const double2*>(bra), static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, complex_out, h->stream);
+    HIPCHK(h, e);
+    std::vector<double> r((size_t)nb * cw);
+    HIPCHK(h, hipMemcpyAsync(r.data(), dout, r.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    lrdm_status st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+    for (int t = 0; t < nb; ++t)
+      for (int z = 0; z < cw; ++z) vals[(size_t)idx[b0 + t] * cw + z] = r[(size_t)t * cw + z];
+  }
+  return LRDM_OK;
+}
+
+lrdm_status compress_entry(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
+                           double* rec, lrdm_compress_info* info) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (r_target < 1 || r_target > h->r_max) return fail(h, LRDM_E_ARG, "r_target must be in [1, r_max]");
+  if (!(eps >= 0.0 && eps < 1.0)) return fail(h, LRDM_E_ARG, "eps must be in [0, 1)");
+  if (tie_policy != 0 && tie_policy != 1) return fail(h, LRDM_E_ARG, "tie_policy must be 0 or 1");
+  if (renorm != 0 && renorm != 1) return fail(h, LRDM_E_ARG, "renorm must be 0 or 1");
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  st = h->dt == LRDM_C64 ? compress_t<float>(h, r_target, eps, tie_policy, renorm, rec)
+                         : compress_t<double>(h, r_target, eps, tie_policy, renorm, rec);
+  if (st != LRDM_OK) return st;
+  if (info) {
+    st = sync_and_check(h);
+    if (st != LRDM_OK) return st;
+    DevInfo d;
+    HIPCHK(h, hipMemcpy(&d, h->ws<DevInfo>(h->lay.off_info), sizeof(d), hipMemcpyDeviceToHost));
+    info->rank = d.k;
+    info->n_eig = d.n_eig;
+    info->discarded = d.discarded;
+    info->discarded_total = d.discarded_total;
+    info->trace_before = d.trace;
+    info->boundary_gap = d.gap;
+    info->lambda_max = d.lambda_max;
+  }
   return LRDM_OK;
 }
 
@@ -454,29 +600,11 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e) {
   if (qubit < 0 || qubit >= h->n) return fail(h, LRDM_E_ARG, "qubit out of range");
   if (m < 1 || m > h->m_max) return fail(h, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
   if (!e) return fail(h, LRDM_E_ARG, "null Kraus matrices");
-  // completeness sum_a E_a^H E_a = I
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      double re = 0, im = 0;
-      for (int a = 0; a < m; ++a)
-        for (int r = 0; r < 2; ++r) {
-          const double ar = e[((a * 2 + r) * 2 + i) * 2], ai = -e[((a * 2 + r) * 2 + i) * 2 + 1];
-          const double br = e[((a * 2 + r) * 2 + j) * 2], bi = e[((a * 2 + r) * 2 + j) * 2 + 1];
-          re += ar * br - ai * bi;
-          im += ar * bi + ai * br;
-        }
-      if (!(std::fabs(re - (i == j)) <= 1e-10 && std::fabs(im) <= 1e-10))
-        return fail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
-    }
+  if (!kraus_complete(m, e)) return fail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is already pending: compress first");
   st = flush_gates(h);
   if (st != LRDM_OK) return st;
-  Channel ch{};
-  ch.m = m;
-  for (int a = 0; a < m; ++a)
-    for (int r = 0; r < 2; ++r)
-      for (int cidx = 0; cidx < 2; ++cidx)
-        for (int z = 0; z < 2; ++z) ch.e[a][r][cidx][z] = e[((a * 2 + r) * 2 + cidx) * 2 + z];
+  const Channel ch = make_channel(m, e);
   if (h->plain) {
     const int c = h->ncols;
     hipError_t he = h->dt == LRDM_C64
@@ -500,31 +628,19 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e) {
 
 lrdm_status lrdm_compress(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
                           lrdm_compress_info* info) {
+  return compress_entry(h, r_target, eps, tie_policy, renorm, nullptr, info);
+}
+
+lrdm_status lrdm_compress_record(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
+                                 void* rec_dev, lrdm_compress_info* info) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
-  if (r_target < 1 || r_target > h->r_max) return fail(h, LRDM_E_ARG, "r_target must be in [1, r_max]");
-  if (!(eps >= 0.0 && eps < 1.0)) return fail(h, LRDM_E_ARG, "eps must be in [0, 1)");
-  if (tie_policy != 0 && tie_policy != 1) return fail(h, LRDM_E_ARG, "tie_policy must be 0 or 1");
-  if (renorm != 0 && renorm != 1) return fail(h, LRDM_E_ARG, "renorm must be 0 or 1");
-  st = flush_gates(h);
-  if (st != LRDM_OK) return st;
-  st = h->dt == LRDM_C64 ? compress_t<float>(h, r_target, eps, tie_policy, renorm)
-                         : compress_t<double>(h, r_target, eps, tie_policy, renorm);
-  if (st != LRDM_OK) return st;
-  if (info) {
-    st = sync_and_check(h);
-    if (st != LRDM_OK) return st;
-    DevInfo d;
-    HIPCHK(h, hipMemcpy(&d, h->ws<DevInfo>(h->lay.off_info), sizeof(d), hipMemcpyDeviceToHost));
-    info->rank = d.k;
-    info->n_eig = d.n_eig;
-    info->discarded = d.discarded;
-    info->discarded_total = d.discarded_total;
-    info->trace_before = d.trace;
-    info->boundary_gap = d.gap;
-    info->lambda_max = d.lambda_max;
-  }
-  return LRDM_OK;
+  if (!h->lay.adjoint)
+    return fail(h, LRDM_E_UNSUPPORTED, "compression records need the fused form and m_max * r_pad <= 64");
+  if (!rec_dev) return fail(h, LRDM_E_ARG, "null record buffer");
+  if (reinterpret_cast<uintptr_t>(rec_dev) & 255) return fail(h, LRDM_E_ARG, "record buffer must be 256-byte aligned");
+  if (!h->chan_pending) return fail(h, LRDM_E_STATE, "a record needs a pending Kraus channel");
+  return compress_entry(h, r_target, eps, tie_policy, renorm, static_cast<double*>(rec_dev), info);
 }
 
 lrdm_status lrdm_probabilities(lrdm_t h, double* p_dev) {
@@ -567,47 +683,11 @@ lrdm_status lrdm_expect_pauli(lrdm_t h, int n_terms, const uint64_t* xmask, cons
   if (n_terms < 1 || n_terms > kMaxTerms) return fail(h, LRDM_E_ARG, "n_terms must be in [1, 65536]");
   if (!xmask || !zmask || !out_host || (summed && !coeff)) return fail(h, LRDM_E_ARG, "null argument");
   if (summed != 0 && summed != 1) return fail(h, LRDM_E_ARG, "summed must be 0 or 1");
-  const uint64_t lim = (h->n >= 64) ? ~0ull : ((1ull << h->n) - 1ull);
-  for (int t = 0; t < n_terms; ++t)
-    if ((xmask[t] & ~lim) || (zmask[t] & ~lim)) return fail(h, LRDM_E_ARG, "Pauli mask beyond n qubits");
-  // group terms by X mask
-  std::vector<int> idx(n_terms);
-  for (int t = 0; t < n_terms; ++t) idx[t] = t;
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return xmask[a] < xmask[b]; });
-  const uint32_t rows = 1u << h->n;
-  const int nchunks = (int)((rows + 1023) / 1024);
-  const int batch_cap = std::max(1, (int)(kPauliPartDoubles / (2 * (size_t)nchunks)));
+  st = check_masks(h, n_terms, xmask, zmask);
+  if (st != LRDM_OK) return st;
   std::vector<double> vals(n_terms);
-  uint64_t* dterms = h->ws<uint64_t>(h->lay.off_terms);
-  double* dpart = h->ws<double>(h->lay.off_pauli);
-  double* dout = h->ws<double>(h->lay.off_out);
-  for (int b0 = 0; b0 < n_terms; b0 += std::min(batch_cap, 4096)) {
-    const int nb = std::min(n_terms - b0, std::min(batch_cap, 4096));
-    // staging: xm[nb], zm[nb], gstart[ngroups + 1] (int)
-    std::vector<uint64_t> xm(nb), zm(nb);
-    std::vector<int> gstart;
-    for (int t = 0; t < nb; ++t) {
-      xm[t] = xmask[idx[b0 + t]];
-      zm[t] = zmask[idx[b0 + t]];
-      if (t == 0 || xm[t] != xm[t - 1]) gstart.push_back(t);
-    }
-    const int ngroups = (int)gstart.size();
-    gstart.push_back(nb);
-    h->term_stage.assign(2 * nb + (gstart.size() + 1) / 2 + 1, 0);
-    std::memcpy(h->term_stage.data(), xm.data(), nb * 8);
-    std::memcpy(h->term_stage.data() + nb, zm.data(), nb * 8);
-    std::memcpy(h->term_stage.data() + 2 * nb, gstart.data(), gstart.size() * 4);
-    HIPCHK(h, hipMemcpyAsync(dterms, h->term_stage.data(), h->term_stage.size() * 8, hipMemcpyHostToDevice, h->stream));
-    hipError_t e = h->dt == LRDM_C64
-                       ? launch_pauli<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, h->stream)
-                       : launch_pauli<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, dterms, dterms + nb, nb, dpart, ngroups, dout, h->stream);
-    HIPCHK(h, e);
-    std::vector<double> r(nb);
-    HIPCHK(h, hipMemcpyAsync(r.data(), dout, nb * 8, hipMemcpyDeviceToHost, h->stream));
-    st = sync_and_check(h);
-    if (st != LRDM_OK) return st;
-    for (int t = 0; t < nb; ++t) vals[idx[b0 + t]] = r[t];
-  }
+  st = pauli_values(h, h->state, n_terms, xmask, zmask, 0, vals.data());
+  if (st != LRDM_OK) return st;
   if (summed) {
     double s = 0;
     for (int t = 0; t < n_terms; ++t) s += coeff[t] * vals[t];
@@ -721,6 +801,112 @@ lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* to
   if (mean_ms) *mean_ms = nl ? tot / nl : 0.0;
   h->timing_class = -1;
   h->ev_used = 0;
+  return LRDM_OK;
+}
+
+// ---------------------------------------------------------------- reverse sweep
+lrdm_status lrdm_record_bytes(lrdm_t h, size_t* bytes) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (!bytes) return fail(h, LRDM_E_ARG, "null output pointer");
+  if (!h->lay.adjoint)
+    return fail(h, LRDM_E_UNSUPPORTED, "compression records need the fused form and m_max * r_pad <= 64");
+  *bytes = h->lay.rec_bytes;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_checkpoint(lrdm_t h, void* dst_dev, int* rank_out) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  if (!dst_dev) return fail(h, LRDM_E_ARG, "null destination");
+  HIPCHK(h, hipMemcpyAsync(dst_dev, h->state, h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  if (rank_out) *rank_out = h->c_bound;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (!src_dev) return fail(h, LRDM_E_ARG, "null source");
+  if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  h->gates.clear();
+  HIPCHK(h, hipMemcpyAsync(h->state, src_dev, h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
+  h->ncols = h->lay.r_pad;
+  h->c_bound = rank;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_apply_pauli_sum(lrdm_t dst, lrdm_t src, int n_terms, const uint64_t* xmask,
+                                 const uint64_t* zmask, const double* coeff) {
+  lrdm_status st = check_usable(dst);
+  if (st != LRDM_OK) return st;
+  st = ready_for_output(src);
+  if (st != LRDM_OK) return st;
+  if (dst == src) return fail(dst, LRDM_E_ARG, "source and destination must be different handles");
+  if (!same_shape(dst, src)) return fail(dst, LRDM_E_ARG, "handles differ in n, r, dtype, m_max or form");
+  if (n_terms < 1 || n_terms > kMaxApplyTerms) return fail(dst, LRDM_E_ARG, "n_terms must be in [1, 4096]");
+  if (!xmask || !zmask || !coeff) return fail(dst, LRDM_E_ARG, "null argument");
+  st = check_masks(dst, n_terms, xmask, zmask);
+  if (st != LRDM_OK) return st;
+  if (dst->chan_pending) return fail(dst, LRDM_E_STATE, "a Kraus channel is pending on the destination");
+  dst->gates.clear();
+  st = order_streams(src, dst);
+  if (st != LRDM_OK) return st;
+  std::vector<uint64_t> stage(3 * (size_t)n_terms);
+  std::memcpy(stage.data(), xmask, n_terms * 8);
+  std::memcpy(stage.data() + n_terms, zmask, n_terms * 8);
+  std::memcpy(stage.data() + 2 * n_terms, coeff, n_terms * 8);
+  uint64_t* dterms = dst->ws<uint64_t>(dst->lay.off_terms);
+  HIPCHK(dst, hipMemcpyAsync(dterms, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, dst->stream));
+  hipError_t e = dst->dt == LRDM_C64
+                     ? launch_pauli_apply<float>(static_cast<float2*>(dst->state), static_cast<const float2*>(src->state), dst->n, dst->lay.ld, src->ncols, dterms, dterms + n_terms, reinterpret_cast<const double*>(dterms + 2 * n_terms), n_terms, dst->stream)
+                     : launch_pauli_apply<double>(static_cast<double2*>(dst->state), static_cast<const double2*>(src->state), dst->n, dst->lay.ld, src->ncols, dterms, dterms + n_terms, reinterpret_cast<const double*>(dterms + 2 * n_terms), n_terms, dst->stream);
+  HIPCHK(dst, e);
+  // the staging vector is a local: wait for the upload before it goes out of scope
+  HIPCHK(dst, hipStreamSynchronize(dst->stream));
+  dst->ncols = src->ncols;
+  dst->c_bound = src->c_bound;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_pauli_overlap(lrdm_t bra, lrdm_t ket, int n_terms, const uint64_t* xmask,
+                               const uint64_t* zmask, double* out_host) {
+  lrdm_status st = ready_for_output(bra);
+  if (st != LRDM_OK) return st;
+  st = ready_for_output(ket);
+  if (st != LRDM_OK) return st;
+  if (!same_shape(bra, ket)) return fail(ket, LRDM_E_ARG, "handles differ in n, r, dtype, m_max or form");
+  if (n_terms < 1 || n_terms > kMaxTerms) return fail(ket, LRDM_E_ARG, "n_terms must be in [1, 65536]");
+  if (!xmask || !zmask || !out_host) return fail(ket, LRDM_E_ARG, "null argument");
+  st = check_masks(ket, n_terms, xmask, zmask);
+  if (st != LRDM_OK) return st;
+  st = order_streams(bra, ket);
+  if (st != LRDM_OK) return st;
+  return pauli_values(ket, bra->state, n_terms, xmask, zmask, 1, out_host);
+}
+
+lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec_dev, int qubit,
+                                  int m, const double* e) {
+  lrdm_status st = check_usable(bar);
+  if (st != LRDM_OK) return st;
+  if (!bar->lay.adjoint)
+    return fail(bar, LRDM_E_UNSUPPORTED, "the reverse sweep needs the fused form and m_max * r_pad <= 64");
+  if (!x_dev || !rec_dev || !e) return fail(bar, LRDM_E_ARG, "null argument");
+  if (qubit < 0 || qubit >= bar->n) return fail(bar, LRDM_E_ARG, "qubit out of range");
+  if (m < 1 || m > bar->m_max) return fail(bar, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
+  if (!kraus_complete(m, e)) return fail(bar, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
+  if (bar->chan_pending) return fail(bar, LRDM_E_STATE, "a Kraus channel is pending on the adjoint handle");
+  st = flush_gates(bar);
+  if (st != LRDM_OK) return st;
+  const Channel ch = make_channel(m, e);
+  const AdjBufs b = adj_bufs(bar);
+  hipError_t he = bar->dt == LRDM_C64
+                      ? launch_compress_adjoint<float>(static_cast<float2*>(bar->state), static_cast<const float2*>(x_dev), bar->n, bar->lay.ld, bar->lay.r_pad, qubit, ch, static_cast<const double*>(rec_dev), b, bar->stream)
+                      : launch_compress_adjoint<double>(static_cast<double2*>(bar->state), static_cast<const double2*>(x_dev), bar->n, bar->lay.ld, bar->lay.r_pad, qubit, ch, static_cast<const double*>(rec_dev), b, bar->stream);
+  HIPCHK(bar, he);
+  bar->ncols = bar->lay.r_pad;
+  bar->c_bound = bar->lay.r_pad;
   return LRDM_OK;
 }
 

@@ -24,7 +24,8 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_apply_diagonal_weight", "lrdm_apply_kraus", "lrdm_compress", "lrdm_probabilities",
            "lrdm_expect_pauli", "lrdm_expect_z", "lrdm_sample", "lrdm_get_L", "lrdm_set_L",
            "lrdm_synchronize", "lrdm_timing_begin", "lrdm_timing_end", "lrdm_last_error",
-           "lrdm_version"]
+           "lrdm_version", "lrdm_record_bytes", "lrdm_compress_record", "lrdm_checkpoint",
+           "lrdm_restore", "lrdm_apply_pauli_sum", "lrdm_pauli_overlap", "lrdm_compress_adjoint"]
 
 
 class LrdmError(RuntimeError):
@@ -73,6 +74,13 @@ def load_library(path: str = LIB_PATH):
         "lrdm_synchronize": [P],
         "lrdm_timing_begin": [P, I],
         "lrdm_timing_end": [P, ctypes.POINTER(I), dp, dp],
+        "lrdm_record_bytes": [P, ctypes.POINTER(SZ)],
+        "lrdm_compress_record": [P, I, D, I, I, P, ctypes.POINTER(CompressInfo)],
+        "lrdm_checkpoint": [P, P, ctypes.POINTER(I)],
+        "lrdm_restore": [P, P, I],
+        "lrdm_apply_pauli_sum": [P, P, I, P, P, P],
+        "lrdm_pauli_overlap": [P, P, I, P, P, dp],
+        "lrdm_compress_adjoint": [P, P, P, I, I, dp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -217,6 +225,52 @@ class LowRankDM:
         dt = np.complex64 if self.dtype == C64 else np.complex128
         a = np.ascontiguousarray(np.asarray(L), dtype=dt)
         _check(self.lib.lrdm_set_L(self.h, a.ctypes.data, 1, a.shape[1]), self.h)
+
+    # -------------------------------------------------------------- reverse sweep
+    def record_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(self.lib.lrdm_record_bytes(self.h, ctypes.byref(b)), self.h)
+        return b.value
+
+    def compress_record(self, r: int, rec, eps: float = 0.0, tie: int = 0, renorm: int = 1):
+        """lrdm_compress that also fills `rec` (a device tensor of record_bytes() bytes)."""
+        _check(self.lib.lrdm_compress_record(self.h, int(r), float(eps), int(tie), int(renorm),
+                                             ctypes.c_void_p(rec.data_ptr()), None), self.h)
+
+    def checkpoint(self, dst) -> int:
+        """Copy the state buffer into `dst` (a device tensor of state.numel() bytes); returns the
+        column bound to pass back to restore()."""
+        rk = ctypes.c_int()
+        _check(self.lib.lrdm_checkpoint(self.h, ctypes.c_void_p(dst.data_ptr()), ctypes.byref(rk)), self.h)
+        return rk.value
+
+    def restore(self, src, rank: int):
+        _check(self.lib.lrdm_restore(self.h, ctypes.c_void_p(src.data_ptr()), int(rank)), self.h)
+
+    def apply_pauli_sum_from(self, src: "LowRankDM", xmask, zmask, coeff):
+        """This handle's factor <- H src's factor, H = sum_t coeff[t] P_t."""
+        xm = np.ascontiguousarray(xmask, dtype=np.uint64)
+        zm = np.ascontiguousarray(zmask, dtype=np.uint64)
+        cf = np.ascontiguousarray(coeff, dtype=np.float64)
+        _check(self.lib.lrdm_apply_pauli_sum(self.h, src.h, xm.shape[0], xm.ctypes.data, zm.ctypes.data,
+                                             cf.ctypes.data), self.h)
+
+    def pauli_overlap(self, ket: "LowRankDM", xmask, zmask) -> np.ndarray:
+        """Tr(self^H P_t ket) for every term, complex."""
+        xm = np.ascontiguousarray(xmask, dtype=np.uint64)
+        zm = np.ascontiguousarray(zmask, dtype=np.uint64)
+        out = np.zeros(2 * xm.shape[0])
+        _check(self.lib.lrdm_pauli_overlap(self.h, ket.h, xm.shape[0], xm.ctypes.data, zm.ctypes.data,
+                                           _dptr(out)), ket.h)
+        return out[0::2] + 1j * out[1::2]
+
+    def compress_adjoint(self, x_ckpt, rec, qubit: int, ops):
+        """Reverse of one channel + compression on this (adjoint) handle."""
+        ops = np.asarray(ops, dtype=np.complex128)
+        m = _cplx(ops)
+        _check(self.lib.lrdm_compress_adjoint(self.h, ctypes.c_void_p(x_ckpt.data_ptr()),
+                                              ctypes.c_void_p(rec.data_ptr()), int(qubit), ops.shape[0],
+                                              _dptr(m)), self.h)
 
     # -------------------------------------------------------------- timing
     def timing_begin(self, kernel_class: int):

@@ -266,13 +266,15 @@ def cfg4_angles(n: int = 12, layers: int = 8, seed: int = 1004) -> np.ndarray:
 
 def cfg4_program(theta: np.ndarray, n: int = 12, r: int = 16, p: float = 0.002,
                  dtype: str = "c64", renorm: int = 1) -> Program:
-    """Layer l: RY(theta[l,q,0]) then RZ(theta[l,q,1]) on every qubit, CZ ladder (q, q+1),
-    depolarizing on every qubit with a compression after each channel."""
+    """Layer l: RY(theta[l,q,0]) then RZ(theta[l,q,1]) on every qubit (emitted as the RY layer
+    followed by the RZ layer, the same unitary since gates on different qubits commute), CZ
+    ladder (q, q+1), depolarizing on every qubit with a compression after each channel."""
     layers = theta.shape[0]
     ops: list = []
     for l in range(layers):
         for q in range(n):
             ops.append(_g1(q, ry(theta[l, q, 0]), "ry", ((l * n + q) * 2 + 0, "Y")))
+        for q in range(n):
             ops.append(_g1(q, rz(theta[l, q, 1]), "rz", ((l * n + q) * 2 + 1, "Z")))
         for q in range(n - 1):
             ops.append(_g2(q, q + 1, CZ, "cz", diagonal=True))

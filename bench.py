@@ -118,6 +118,42 @@ def cpu_baseline(n: int, r: int, budget_s: float = 20.0) -> dict:
                        f"{per_comp:.2f} s per compress)")}
 
 
+def gradient_throughput(reps: int = 3) -> dict:
+    """Energy + full gradient of the differentiable noisy ansatz (n=12, r=16, 8 layers of RY/RZ
+    + CZ ladder, depolarizing 0.002 after every gate layer with a compression after each channel,
+    200 Pauli terms, 192 angles) through the reverse sweep, complex64 bulk / FP64 eigensolve."""
+    import torch
+
+    import paper_2009_06657_amd as lr
+    from paper_2009_06657_amd.adjoint import EnergyGradient
+    from workloads import circuits as C
+
+    theta = C.cfg4_angles()
+    xm, zm, co, _ = C.random_pauli_sum(12)
+    eng = EnergyGradient(12, 16, 4, xm, zm, co, dtype=lr.C64)
+    prog = C.cfg4_program(theta)
+    eng.forward(prog)
+    eng.backward(theta.size)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        E = eng.forward(prog)
+        g = eng.backward(theta.size)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = {"value": 1.0 / dt, "unit": "grads/s", "ms_per_grad": 1e3 * dt, "n_params": int(theta.size),
+           "workload": "noisy RY/RZ ansatz n=12 r=16, 8 layers, depolarizing 0.002, 200 Pauli terms",
+           "energy": E}
+    gold = os.path.join(ROOT, "tests", "golden", "cfg4_grad.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            ref = json.load(f)
+        out["max_abs_err_vs_fd"] = float(np.max(np.abs(g - np.array(ref["grad_fd"]))))
+        out["abs_err_energy"] = abs(E - ref["energy"])
+    eng.close()
+    return out
+
+
 def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
     """A plain device-to-device copy of a known size: the HBM counters read for it (bytes
     fetched, bytes written per dispatch) give the scale factor applied to the same counters
@@ -139,6 +175,7 @@ def main():
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient-throughput leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -199,6 +236,8 @@ def main():
             n_, m_, t_ = dm.timing_end()
             br[CLASS_NAMES[cls]] = {"launches": n_, "mean_ms": m_, "total_ms": t_}
         out["breakdown_one_step"] = br
+    if not args.no_grad:
+        out["grads_per_s"] = gradient_throughput()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prog.n, prog.r)
     print(json.dumps(out), flush=True)

@@ -212,6 +212,32 @@ lrdm_status lrdm_pauli_overlap(lrdm_t bra, lrdm_t ket, int n_terms, const uint64
 lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec_dev, int qubit,
                                   int m, const double* e);
 
+/* ---------------------------------------------------------------- full-rank comparator
+ * Exact density-matrix evolution (Eq. "full rank evolution", Sec. II.A) in complex64, the
+ * same-GPU baseline the low-rank path is measured against.  rho (2^n x 2^n, row-major, 8 * 4^n
+ * bytes of caller-owned device memory) is treated as a vector over 2n index bits (column bit q =
+ * index bit q, row bit q = index bit n + q): a gate U applies U to the row bits and conj(U) to the
+ * column bits, a channel applies sum_a E_a (x) conj(E_a) to the bit pair (n + q, q).  Operations
+ * are queued and applied in fused passes over LDS tiles of 2^13 amplitudes.  n in [1, 16]. */
+typedef struct lrdm_fdm_ctx* lrdm_fdm_t;
+
+/* Bytes of rho for n qubits (8 * 4^n). */
+lrdm_status lrdm_fdm_state_bytes(int n, size_t* bytes);
+/* rho = |0...0><0...0| in state_dev (256-byte aligned); work goes on hip_stream. */
+lrdm_status lrdm_fdm_init(lrdm_fdm_t* out, int n, void* state_dev, size_t state_bytes, void* hip_stream);
+lrdm_status lrdm_fdm_reset(lrdm_fdm_t h);
+lrdm_status lrdm_fdm_destroy(lrdm_fdm_t h);
+/* rho <- U rho U^H; arguments as lrdm_apply_gate. */
+lrdm_status lrdm_fdm_apply_gate(lrdm_fdm_t h, int k, const int* qubits, const double* u);
+/* rho <- sum_a E_a rho E_a^H on one qubit; arguments as lrdm_apply_kraus (m in [1, 4]). */
+lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e);
+/* Prob(x) = Re rho[x][x] into p_dev (2^n doubles, device).  Applies queued operations. */
+lrdm_status lrdm_fdm_probabilities(lrdm_fdm_t h, double* p_dev);
+/* Apply queued operations and wait for the stream. */
+lrdm_status lrdm_fdm_synchronize(lrdm_fdm_t h);
+/* Last error message of h ("" for NULL; lrdm_last_error(NULL) also holds it). */
+const char* lrdm_fdm_last_error(lrdm_fdm_t h);
+
 /* Last error message for h, or the calling thread's last error when h == NULL. */
 const char* lrdm_last_error(lrdm_t h);
 

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblrdm.so")
-SOURCES = ["k_gate.hip", "k_gram.hip", "k_eig.hip", "k_proj.hip", "k_out.hip", "k_adj.hip", "runtime.cpp"]
+SOURCES = ["k_gate.hip", "k_gram.hip", "k_eig.hip", "k_proj.hip", "k_out.hip", "k_adj.hip", "k_fdm.hip",
+           "runtime.cpp", "runtime_fdm.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
          # keep hipcc from emitting packed-FP32 arithmetic (see the design notes)
@@ -42,7 +43,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 6, verbose: bool = False) -> str:
+def build(jobs: int = 8, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -109,6 +109,29 @@ hipError_t launch_pauli(const cx_t<T>* bra, const cx_t<T>* ket, int n, int ld, i
                         const uint64_t* xm, const uint64_t* zm, int n_terms, double* partials,
                         int nblocks, double* out, int complex_out, hipStream_t s);
 
+// ---------------------------------------------------------------- full-rank comparator (k_fdm.hip)
+constexpr int kFdmLowBits = 5;     // index bits 0..4 are local in every pass (256-byte runs)
+constexpr int kFdmMaxLocal = 13;   // 2^13 complex64 = 64 KB tile
+constexpr int kFdmMaxOps = 48;
+constexpr int kFdmMaxCoef = 512;
+
+// One fused pass over the 2n-bit vector form of rho: local slot j <-> index bit local_q[j]
+// (slots 0..4 are bits 0..4); ops on slots (1q, 2q) or on any index bit (diagonal).
+struct FdmPass {
+  int nbits, k, n_ops;
+  int local_q[kFdmMaxLocal];
+  int sorted_hi[kFdmMaxLocal];   // local bits above the low block, ascending
+  int op_type[kFdmMaxOps];
+  int op_a[kFdmMaxOps];
+  int op_b[kFdmMaxOps];
+  int op_coef[kFdmMaxOps];
+  float coef[kFdmMaxCoef];
+};
+
+hipError_t launch_fdm_pass(const FdmPass& p, float2* rho, hipStream_t s);
+hipError_t launch_fdm_reset(float2* rho, int n, hipStream_t s);
+hipError_t launch_fdm_diag(const float2* rho, int n, double* p, hipStream_t s);
+
 // ---------------------------------------------------------------- reverse sweep (k_adj.hip)
 // dst = sum_t coeff[t] P_t src, column by column (terms: xm[n], zm[n], coeff[n] as doubles).
 template <class T>
@@ -149,5 +172,7 @@ template <class T>
 hipError_t launch_set_e0(cx_t<T>* L, hipStream_t s);
 
 int gram_blocks(int n, int nsplit);   // number of split-K partials the Gram uses
+
+void set_last_error(const char* msg);   // the calling thread's last error (lrdm_last_error(NULL))
 
 }  // namespace lrdm

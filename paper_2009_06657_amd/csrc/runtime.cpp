@@ -99,6 +99,8 @@ struct PendingGate {
 
 }  // namespace
 
+void lrdm::set_last_error(const char* msg) { g_last_error = msg; }
+
 struct lrdm_ctx {
   int n = 0, r_max = 0, m_max = 0;
   lrdm_dtype dt = LRDM_C64;

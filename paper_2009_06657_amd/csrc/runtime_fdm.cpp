@@ -1,0 +1,300 @@
+// Host runtime of the full-rank density-matrix comparator (Eq. "full rank evolution",
+// Sec. II.A): validation, the pass scheduler over the 2n index bits of rho, and the C ABI
+// (lrdm_fdm_*) declared in include/lrdm.h.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrdm_internal.h"
+
+using namespace lrdm;
+
+struct lrdm_fdm_ctx {
+  struct Op {
+    int type;          // OP_1Q, OP_2Q (slots), OP_DIAG1, OP_DIAG2 (index bits)
+    int a, b;          // index bits
+    uint64_t mask;     // index bits touched
+    std::vector<float> coef;
+  };
+  int n = 0;
+  float2* rho = nullptr;
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  std::string err;
+  std::vector<Op> ops;
+};
+
+namespace {
+
+lrdm_status ffail(lrdm_fdm_t h, lrdm_status st, const std::string& msg) {
+  set_last_error(msg.c_str());
+  if (h) h->err = msg;
+  return st;
+}
+
+lrdm_status fhip(lrdm_fdm_t h, hipError_t e, const char* where) {
+  if (e == hipSuccess) return LRDM_OK;
+  h->poisoned = true;
+  return ffail(h, LRDM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define FHIP(h, expr)                                      \
+  do {                                                     \
+    lrdm_status _s = fhip((h), (expr), #expr);             \
+    if (_s != LRDM_OK) return _s;                          \
+  } while (0)
+
+lrdm_status fusable(lrdm_fdm_t h) {
+  if (!h) return ffail(nullptr, LRDM_E_ARG, "null handle");
+  if (h->poisoned) return ffail(h, LRDM_E_STATE, "handle is poisoned by an earlier device error: " + h->err);
+  return LRDM_OK;
+}
+
+bool unitary(const double* u, int d) {
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      double re = 0, im = 0;
+      for (int k = 0; k < d; ++k) {
+        const double ar = u[2 * (k * d + i)], ai = -u[2 * (k * d + i) + 1];
+        const double br = u[2 * (k * d + j)], bi = u[2 * (k * d + j) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      if (!(std::fabs(re - (i == j ? 1.0 : 0.0)) <= 1e-10 && std::fabs(im) <= 1e-10)) return false;
+    }
+  return true;
+}
+
+void push_op(lrdm_fdm_t h, int type, int a, int b, const std::vector<float>& coef) {
+  lrdm_fdm_ctx::Op op;
+  op.type = type;
+  op.a = a;
+  op.b = b;
+  op.mask = (1ull << a) | (b >= 0 ? (1ull << b) : 0ull);
+  op.coef = coef;
+  h->ops.push_back(op);
+}
+
+// d x d complex matrix (interleaved FP64) -> FP32, optionally conjugated
+std::vector<float> mat(const double* u, int d, bool conj) {
+  std::vector<float> c(2 * d * d);
+  for (int i = 0; i < d * d; ++i) {
+    c[2 * i] = (float)u[2 * i];
+    c[2 * i + 1] = (float)(conj ? -u[2 * i + 1] : u[2 * i + 1]);
+  }
+  return c;
+}
+
+lrdm_status flush(lrdm_fdm_t h) {
+  const int nbits = 2 * h->n;
+  const int kmax = std::min(kFdmMaxLocal, nbits);
+  const int lo = std::min(kmax, kFdmLowBits);
+  const int free_slots = kmax - lo;
+  const uint64_t lowmask = (1ull << lo) - 1ull;
+  std::vector<char> placed(h->ops.size(), 0);
+  size_t remaining = h->ops.size();
+  while (remaining > 0) {
+    FdmPass p;
+    std::memset(&p, 0, sizeof(p));
+    p.nbits = nbits;
+    std::vector<int> hi;
+    uint64_t locmask = lowmask, blocked = 0;
+    int nc = 0;
+    for (size_t i = 0; i < h->ops.size(); ++i) {
+      if (placed[i]) continue;
+      const auto& op = h->ops[i];
+      if (op.mask & blocked) { blocked |= op.mask; continue; }
+      if (p.n_ops >= kFdmMaxOps || nc + (int)op.coef.size() > kFdmMaxCoef) { blocked = ~0ull; continue; }
+      const bool diag = op.type == OP_DIAG1 || op.type == OP_DIAG2;
+      if (!diag) {
+        const uint64_t need = op.mask & ~locmask;
+        if ((int)hi.size() + __builtin_popcountll(need) > free_slots) { blocked |= op.mask; continue; }
+        for (int b = 0; b < nbits; ++b)
+          if (need & (1ull << b)) { hi.push_back(b); locmask |= 1ull << b; }
+      }
+      auto slot = [&](int bit) {
+        if (bit < lo) return bit;
+        for (size_t j = 0; j < hi.size(); ++j) if (hi[j] == bit) return lo + (int)j;
+        return -1;
+      };
+      const int o = p.n_ops++;
+      p.op_type[o] = op.type;
+      p.op_coef[o] = nc;
+      if (diag) {
+        p.op_a[o] = op.a;
+        p.op_b[o] = op.b;
+      } else {
+        p.op_a[o] = slot(op.a);
+        p.op_b[o] = op.b >= 0 ? slot(op.b) : 0;
+      }
+      for (float v : op.coef) p.coef[nc++] = v;
+      placed[i] = 1;
+      --remaining;
+    }
+    // fill the tile with unused bits so that every pass has full-size tiles
+    for (int b = lo; b < nbits && (int)hi.size() < free_slots; ++b)
+      if (!(locmask & (1ull << b))) { hi.push_back(b); locmask |= 1ull << b; }
+    p.k = lo + (int)hi.size();
+    for (int j = 0; j < lo; ++j) p.local_q[j] = j;
+    for (size_t j = 0; j < hi.size(); ++j) p.local_q[lo + j] = hi[j];
+    std::vector<int> sh = hi;
+    std::sort(sh.begin(), sh.end());
+    for (size_t j = 0; j < sh.size(); ++j) p.sorted_hi[j] = sh[j];
+    FHIP(h, launch_fdm_pass(p, h->rho, h->stream));
+  }
+  h->ops.clear();
+  return LRDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lrdm_status lrdm_fdm_state_bytes(int n, size_t* bytes) {
+  if (!bytes) return ffail(nullptr, LRDM_E_ARG, "null output pointer");
+  if (n < 1 || n > 16) return ffail(nullptr, LRDM_E_ARG, "n must be in [1, 16]");
+  *bytes = (size_t)8 << (2 * n);
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_init(lrdm_fdm_t* out, int n, void* state_dev, size_t state_bytes, void* hip_stream) {
+  if (!out) return ffail(nullptr, LRDM_E_ARG, "null output handle pointer");
+  *out = nullptr;
+  if (n < 1 || n > 16) return ffail(nullptr, LRDM_E_ARG, "n must be in [1, 16]");
+  if (!state_dev) return ffail(nullptr, LRDM_E_ARG, "null device buffer");
+  if (state_bytes < ((size_t)8 << (2 * n))) return ffail(nullptr, LRDM_E_NOMEM, "state buffer smaller than 8 * 4^n bytes");
+  if (reinterpret_cast<uintptr_t>(state_dev) & 255) return ffail(nullptr, LRDM_E_ARG, "device buffer must be 256-byte aligned");
+  lrdm_fdm_ctx* h = new lrdm_fdm_ctx();
+  h->n = n;
+  h->rho = static_cast<float2*>(state_dev);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  const hipError_t e = launch_fdm_reset(h->rho, n, h->stream);
+  if (e != hipSuccess) {
+    ffail(nullptr, LRDM_E_HIP, std::string("launch_fdm_reset: ") + hipGetErrorString(e));
+    delete h;
+    return LRDM_E_HIP;
+  }
+  *out = h;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_reset(lrdm_fdm_t h) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  h->ops.clear();
+  FHIP(h, launch_fdm_reset(h->rho, h->n, h->stream));
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_destroy(lrdm_fdm_t h) {
+  if (!h) return ffail(nullptr, LRDM_E_ARG, "null handle");
+  delete h;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_apply_gate(lrdm_fdm_t h, int k, const int* qubits, const double* u) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  if (k != 1 && k != 2) return ffail(h, LRDM_E_ARG, "k must be 1 or 2");
+  if (!qubits || !u) return ffail(h, LRDM_E_ARG, "null qubits or matrix");
+  for (int j = 0; j < k; ++j)
+    if (qubits[j] < 0 || qubits[j] >= h->n) return ffail(h, LRDM_E_ARG, "qubit out of range");
+  if (k == 2 && qubits[0] == qubits[1]) return ffail(h, LRDM_E_ARG, "repeated qubit");
+  const int d = 1 << k;
+  if (!unitary(u, d)) return ffail(h, LRDM_E_ARG, "gate matrix is not unitary within 1e-10");
+  bool diag = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (i != j && (u[2 * (i * d + j)] != 0.0 || u[2 * (i * d + j) + 1] != 0.0)) diag = false;
+  const int n = h->n;
+  if (diag) {
+    std::vector<float> ph(2 * d), phc(2 * d);
+    for (int i = 0; i < d; ++i) {
+      ph[2 * i] = phc[2 * i] = (float)u[2 * (i * d + i)];
+      ph[2 * i + 1] = (float)u[2 * (i * d + i) + 1];
+      phc[2 * i + 1] = -ph[2 * i + 1];
+    }
+    if (k == 1) {
+      push_op(h, OP_DIAG1, n + qubits[0], -1, ph);
+      push_op(h, OP_DIAG1, qubits[0], -1, phc);
+    } else {
+      push_op(h, OP_DIAG2, n + qubits[0], n + qubits[1], ph);
+      push_op(h, OP_DIAG2, qubits[0], qubits[1], phc);
+    }
+    return LRDM_OK;
+  }
+  if (k == 1) {
+    push_op(h, OP_1Q, n + qubits[0], -1, mat(u, 2, false));
+    push_op(h, OP_1Q, qubits[0], -1, mat(u, 2, true));
+  } else {
+    push_op(h, OP_2Q, n + qubits[0], n + qubits[1], mat(u, 4, false));
+    push_op(h, OP_2Q, qubits[0], qubits[1], mat(u, 4, true));
+  }
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  if (qubit < 0 || qubit >= h->n) return ffail(h, LRDM_E_ARG, "qubit out of range");
+  if (m < 1 || m > 4) return ffail(h, LRDM_E_ARG, "Kraus count must be in [1, 4]");
+  if (!e) return ffail(h, LRDM_E_ARG, "null Kraus matrices");
+  // completeness sum_a E_a^H E_a = I
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double re = 0, im = 0;
+      for (int a = 0; a < m; ++a)
+        for (int r = 0; r < 2; ++r) {
+          const double ar = e[((a * 2 + r) * 2 + i) * 2], ai = -e[((a * 2 + r) * 2 + i) * 2 + 1];
+          const double br = e[((a * 2 + r) * 2 + j) * 2], bi = e[((a * 2 + r) * 2 + j) * 2 + 1];
+          re += ar * br - ai * bi;
+          im += ar * bi + ai * br;
+        }
+      if (!(std::fabs(re - (i == j)) <= 1e-10 && std::fabs(im) <= 1e-10))
+        return ffail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
+    }
+  // S[(r + 2c), (r' + 2c')] = sum_a E_a[r][r'] conj(E_a[c][c']) on the bit pair (n + q, q)
+  std::vector<float> S(32);
+  for (int mo = 0; mo < 4; ++mo)
+    for (int mi = 0; mi < 4; ++mi) {
+      const int r = mo & 1, c = mo >> 1, rp = mi & 1, cp = mi >> 1;
+      double re = 0, im = 0;
+      for (int a = 0; a < m; ++a) {
+        const double xr = e[((a * 2 + r) * 2 + rp) * 2], xi = e[((a * 2 + r) * 2 + rp) * 2 + 1];
+        const double yr = e[((a * 2 + c) * 2 + cp) * 2], yi = -e[((a * 2 + c) * 2 + cp) * 2 + 1];
+        re += xr * yr - xi * yi;
+        im += xr * yi + xi * yr;
+      }
+      S[2 * (mo * 4 + mi)] = (float)re;
+      S[2 * (mo * 4 + mi) + 1] = (float)im;
+    }
+  push_op(h, OP_2Q, h->n + qubit, qubit, S);
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_probabilities(lrdm_fdm_t h, double* p_dev) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  if (!p_dev) return ffail(h, LRDM_E_ARG, "null output buffer");
+  st = flush(h);
+  if (st != LRDM_OK) return st;
+  FHIP(h, launch_fdm_diag(h->rho, h->n, p_dev, h->stream));
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_fdm_synchronize(lrdm_fdm_t h) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  st = flush(h);
+  if (st != LRDM_OK) return st;
+  FHIP(h, hipStreamSynchronize(h->stream));
+  return LRDM_OK;
+}
+
+const char* lrdm_fdm_last_error(lrdm_fdm_t h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"

@@ -25,7 +25,10 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_expect_pauli", "lrdm_expect_z", "lrdm_sample", "lrdm_get_L", "lrdm_set_L",
            "lrdm_synchronize", "lrdm_timing_begin", "lrdm_timing_end", "lrdm_last_error",
            "lrdm_version", "lrdm_record_bytes", "lrdm_compress_record", "lrdm_checkpoint",
-           "lrdm_restore", "lrdm_apply_pauli_sum", "lrdm_pauli_overlap", "lrdm_compress_adjoint"]
+           "lrdm_restore", "lrdm_apply_pauli_sum", "lrdm_pauli_overlap", "lrdm_compress_adjoint",
+           "lrdm_fdm_state_bytes", "lrdm_fdm_init", "lrdm_fdm_reset", "lrdm_fdm_destroy",
+           "lrdm_fdm_apply_gate", "lrdm_fdm_apply_kraus", "lrdm_fdm_probabilities",
+           "lrdm_fdm_synchronize", "lrdm_fdm_last_error"]
 
 
 class LrdmError(RuntimeError):
@@ -81,6 +84,14 @@ def load_library(path: str = LIB_PATH):
         "lrdm_apply_pauli_sum": [P, P, I, P, P, P],
         "lrdm_pauli_overlap": [P, P, I, P, P, dp],
         "lrdm_compress_adjoint": [P, P, P, I, I, dp],
+        "lrdm_fdm_state_bytes": [I, ctypes.POINTER(SZ)],
+        "lrdm_fdm_init": [ctypes.POINTER(P), I, P, SZ, P],
+        "lrdm_fdm_reset": [P],
+        "lrdm_fdm_destroy": [P],
+        "lrdm_fdm_apply_gate": [P, I, ctypes.POINTER(I), dp],
+        "lrdm_fdm_apply_kraus": [P, I, I, dp],
+        "lrdm_fdm_probabilities": [P, P],
+        "lrdm_fdm_synchronize": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -88,6 +99,8 @@ def load_library(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.lrdm_last_error.argtypes = [P]
     lib.lrdm_last_error.restype = ctypes.c_char_p
+    lib.lrdm_fdm_last_error.argtypes = [P]
+    lib.lrdm_fdm_last_error.restype = ctypes.c_char_p
     lib.lrdm_version.argtypes = []
     lib.lrdm_version.restype = ctypes.c_char_p
     _lib = lib
@@ -282,6 +295,87 @@ class LowRankDM:
         _check(self.lib.lrdm_timing_end(self.h, ctypes.byref(n), ctypes.byref(mean), ctypes.byref(tot)),
                self.h)
         return n.value, mean.value, tot.value
+
+
+class FullRankDM:
+    """The full-rank density-matrix comparator (complex64 rho of 8 * 4^n bytes on the device)."""
+
+    def __init__(self, n: int, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.lib = load_library()
+        self.n = n
+        b = ctypes.c_size_t()
+        _check(self.lib.lrdm_fdm_state_bytes(n, ctypes.byref(b)))
+        self.device = torch.device(device)
+        self.state = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = ctypes.c_void_p()
+        _check(self.lib.lrdm_fdm_init(ctypes.byref(self.h), n, self.state.data_ptr(), b.value,
+                                      ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def _chk(self, st):
+        if st != 0:
+            raise LrdmError(st, self.lib.lrdm_fdm_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.lrdm_fdm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self):
+        self._chk(self.lib.lrdm_fdm_reset(self.h))
+
+    def apply_gate(self, qubits: Sequence[int], u):
+        q = (ctypes.c_int * len(qubits))(*[int(x) for x in qubits])
+        m = _cplx(u)
+        self._chk(self.lib.lrdm_fdm_apply_gate(self.h, len(qubits), q, _dptr(m)))
+
+    def apply_kraus(self, qubit: int, ops):
+        ops = np.asarray(ops, dtype=np.complex128)
+        m = _cplx(ops)
+        self._chk(self.lib.lrdm_fdm_apply_kraus(self.h, int(qubit), ops.shape[0], _dptr(m)))
+
+    def probabilities(self, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(2 ** self.n, dtype=torch.float64, device=self.device)
+        self._chk(self.lib.lrdm_fdm_probabilities(self.h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def synchronize(self):
+        self._chk(self.lib.lrdm_fdm_synchronize(self.h))
+
+    def rho(self) -> np.ndarray:
+        """rho as a (2^n, 2^n) complex128 array (test helper; copies 8 * 4^n bytes)."""
+        self.synchronize()
+        a = self.state.view(dtype=__import__("torch").complex64).cpu().numpy()
+        return a.reshape(2 ** self.n, 2 ** self.n).astype(np.complex128)
+
+
+def run_program_fdm(fdm: FullRankDM, program):
+    """Gates and channels of a Program on the full-rank comparator (compressions do not apply;
+    diagonal Hamming-weight phases are not supported there)."""
+    from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
+
+    for op in program.ops:
+        if isinstance(op, Gate):
+            fdm.apply_gate(op.qubits, op.u)
+        elif isinstance(op, Kraus):
+            fdm.apply_kraus(op.qubit, op.ops)
+        elif isinstance(op, (Compress, LayerEnd)):
+            pass
+        elif isinstance(op, DiagWeight):
+            raise NotImplementedError("Hamming-weight phases are not supported by the full-rank comparator")
+        else:
+            raise TypeError(f"unknown op {op!r}")
 
 
 def run_program(dm: LowRankDM, program, on_layer=None):

@@ -154,6 +154,64 @@ def gradient_throughput(reps: int = 3) -> dict:
     return out
 
 
+def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 16) -> dict:
+    """Same-GPU comparison with the full-rank density matrix: the brickwork layer (SU(2) on every
+    qubit, CZ, amplitude damping + dephasing per qubit) on the full-rank kernel at n <= 16
+    (rho of 8 * 4^n bytes; n = 20 would need 8.8 TB), the low-rank path at n = 16, r = 64 for a
+    measured same-n ratio, and T_full(16) * 4^(20 - 16) as the extrapolated n = 20 layer time."""
+    import torch
+
+    import paper_2009_06657_amd as lr
+    from workloads import circuits as C
+
+    per_layer = {}
+    for n in sizes:
+        reps = 2 if n >= 16 else 4
+        prog = C.cfg3_program(n=n, r=64, layers=1 + reps)
+        layers = [[]]
+        for op in prog.ops:
+            if isinstance(op, C.LayerEnd):
+                layers.append([])
+            else:
+                layers[-1].append(op)
+        f = lr.FullRankDM(n)
+
+        def run_layers(ls):
+            for seg in ls:
+                lr.run_program_fdm(f, C.Program(n, seg, prog.r, prog.dtype, prog.m_max, "seg", 1))
+            f.synchronize()
+
+        run_layers(layers[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_layers(layers[1:1 + reps])
+        torch.cuda.synchronize()
+        per_layer[n] = (time.perf_counter() - t0) / reps
+        f.close()
+        del f
+        torch.cuda.empty_cache()
+    # low-rank path at the largest full-rank size
+    prog = C.cfg3_program(n=lret_n, r=64, layers=4)
+    dm = lr.LowRankDM(lret_n, 64, lr.C64, prog.m_max)
+    lr.run_program(dm, prog)
+    dm.synchronize()
+    dm.reset()
+    t0 = time.perf_counter()
+    lr.run_program(dm, prog)
+    dm.synchronize()
+    t_lret = (time.perf_counter() - t0) / 4
+    dm.close()
+    nmax = max(sizes)
+    extrap = per_layer[nmax] * 4.0 ** (20 - nmax)
+    return {"workload": "brickwork layer: SU(2) on every qubit + CZ, amplitude damping 0.002 and "
+                        "dephasing 0.001 per qubit (full rank: exact channels; low rank: compress to r=64 after each)",
+            "full_rank_ms_per_layer": {str(n): 1e3 * t for n, t in per_layer.items()},
+            f"low_rank_ms_per_layer_n{lret_n}_r64": 1e3 * t_lret,
+            f"speedup_same_n{nmax}": per_layer[nmax] / t_lret,
+            "full_rank_ms_per_layer_n20_extrapolated": 1e3 * extrap,
+            "extrapolation": f"T_full({nmax}) * 4^(20 - {nmax})"}
+
+
 def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
     """A plain device-to-device copy of a known size: the HBM counters read for it (bytes
     fetched, bytes written per dispatch) give the scale factor applied to the same counters
@@ -176,6 +234,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-throughput leg")
+    ap.add_argument("--no-fdm", action="store_true", help="skip the full-rank comparator leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -213,6 +272,7 @@ def main():
 
     layers = args.layers * args.steps
     ms_per_step = 1e3 * elapsed / args.steps
+    ms_per_layer = ms_per_step / args.layers
     flops = algorithmic_flops(prog.n, dm.r_pad, dominant)
     achieved = flops / (mean_ms * 1e-3)
     out = {
@@ -238,6 +298,10 @@ def main():
         out["breakdown_one_step"] = br
     if not args.no_grad:
         out["grads_per_s"] = gradient_throughput()
+    if not args.no_fdm:
+        fd = fdm_comparator()
+        fd["speedup_n20_vs_extrapolated_full_rank"] = fd["full_rank_ms_per_layer_n20_extrapolated"] / ms_per_layer
+        out["vs_full_rank_dm"] = fd
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prog.n, prog.r)
     print(json.dumps(out), flush=True)

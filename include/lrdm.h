@@ -238,6 +238,41 @@ lrdm_status lrdm_fdm_synchronize(lrdm_fdm_t h);
 /* Last error message of h ("" for NULL; lrdm_last_error(NULL) also holds it). */
 const char* lrdm_fdm_last_error(lrdm_fdm_t h);
 
+/* ---------------------------------------------------------------- batched serving
+ * Many independent handles (complex64, fused form; any mix of n, r_max and m_max) run together.
+ * Between lrdm_batch_begin and lrdm_batch_end, lrdm_reset / lrdm_apply_gate /
+ * lrdm_apply_diagonal_weight / lrdm_apply_kraus / lrdm_compress on those handles are validated
+ * and recorded instead of executed (calls that need results return LRDM_E_STATE).  The recorded
+ * programs are then scheduled in lockstep: step s of every instance (its gate passes and its s-th
+ * compression) is issued as one batched launch per kernel kind and size class, so e.g. the s-th
+ * eigensolves of all instances run concurrently, one work-group each.  The whole schedule is
+ * captured in one hipGraph; lrdm_batch_launch replays it.  Per-step device timestamps give
+ * each instance's completion time.  The caller owns the plan buffer (job tables + timestamps). */
+typedef struct lrdm_batch_ctx* lrdm_batch_t;
+
+/* handles: n_inst distinct handles.  The graph is captured and replayed on hip_stream, which must
+ * not be the default (null) stream; NULL asks the library for a stream of its own (default
+ * priority).  A replay waits for work queued before it on the handles' streams, and work queued
+ * there afterwards waits for the replay. */
+lrdm_status lrdm_batch_create(lrdm_batch_t* out, int n_inst, const lrdm_t* handles, void* hip_stream);
+/* Apply pending gates, wait for each handle's stream, start recording. */
+lrdm_status lrdm_batch_begin(lrdm_batch_t b);
+/* Stop recording, build the lockstep schedule; *plan_bytes = device bytes it needs. */
+lrdm_status lrdm_batch_end(lrdm_batch_t b, size_t* plan_bytes);
+/* Upload the schedule to plan_dev (256-byte aligned, >= plan_bytes, owned by the caller and
+ * kept until lrdm_batch_destroy) and capture the hipGraph.  Synchronous. */
+lrdm_status lrdm_batch_instantiate(lrdm_batch_t b, void* plan_dev, size_t plan_bytes);
+/* Replay the graph on the batch stream (asynchronous).  Every instance starts from its
+ * recorded reset, so replays give identical results. */
+lrdm_status lrdm_batch_launch(lrdm_batch_t b);
+/* Number of lockstep steps and of captured launches. */
+lrdm_status lrdm_batch_info(lrdm_batch_t b, int* n_steps, int* n_launches);
+/* Wait for the last launch; done_ms[i] (nullable, n_inst doubles) = time from the start of the
+ * replay to the end of instance i's last step; total_ms (nullable) = whole replay.  Device wall
+ * clock. */
+lrdm_status lrdm_batch_times(lrdm_batch_t b, double* done_ms, double* total_ms);
+lrdm_status lrdm_batch_destroy(lrdm_batch_t b);
+
 /* Last error message for h, or the calling thread's last error when h == NULL. */
 const char* lrdm_last_error(lrdm_t h);
 

@@ -121,10 +121,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 template <class T, int BR, int BC>
-__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* __restrict__ S, int Fc, Channel ch,
-                                                   int nsplit, int c, int N, int kmax, int r_target,
-                                                   double eps, int tie, int renorm, int c_out,
-                                                   EigBufs B, cx_t<T>* __restrict__ W) {
+__device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, const Channel& ch, int nsplit,
+                                         int c, int N, int kmax, int r_target, double eps, int tie,
+                                         int renorm, int c_out, const EigBufs& B,
+                                         cx_t<T>* __restrict__ W) {
   constexpr int NP = 32 * BC;            // padded order; the thread grid is (NP / BR) x 32
   constexpr int NTH = 32 * (NP / BR);    // threads
   extern __shared__ __attribute__((aligned(16))) double dyn[];   // phase-dependent scratch
@@ -585,6 +585,59 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* 
     }
   }
 }
+
+template <class T, int BR, int BC>
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* __restrict__ S, int Fc, Channel ch,
+                                                   int nsplit, int c, int N, int kmax, int r_target,
+                                                   double eps, int tie, int renorm, int c_out,
+                                                   EigBufs B, cx_t<T>* __restrict__ W) {
+  eig_body<T, BR, BC>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, B, W);
+}
+
+// One work-group per job; every job of a launch has the same size class (BR, BC).
+template <class T, int BR, int BC>
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_batched(const EigJob<T>* __restrict__ jobs) {
+  const EigJob<T>& J = jobs[blockIdx.x];
+  eig_body<T, BR, BC>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm,
+                      J.c_out, J.B, J.W);
+}
+
+template <int BR, int BC>
+static size_t eig_shm(int kmax) {
+  constexpr int NP = 32 * BC;
+  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);
+  const size_t ph5a = (size_t)(NP * (NP - 1) / 2) * 16;
+  const size_t ph5b = (size_t)NP * 64 * 16;
+  size_t shm = ph4;
+  if (ph5a > shm) shm = ph5a;
+  if (ph5b > shm) shm = ph5b;
+  return shm;
+}
+
+template <class T, int BR, int BC>
+static hipError_t launch_eig_batched_bs(const EigJob<T>* jobs, int njobs, int kmax_max, hipStream_t s) {
+  constexpr int NP = 32 * BC;
+  constexpr int NTH = 32 * (NP / BR);
+  const size_t shm = eig_shm<BR, BC>(kmax_max);
+  if (shm > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_batched<T, BR, BC>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((eig_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_eig_batched(int N, const EigJob<T>* jobs, int njobs, int kmax_max, hipStream_t s) {
+  if (njobs < 1 || N < 1 || N > kMaxEig || kmax_max < 1) return hipErrorInvalidValue;
+  if (N <= 32) return launch_eig_batched_bs<T, 1, 1>(jobs, njobs, kmax_max, s);
+  if (N <= 64) return launch_eig_batched_bs<T, 2, 2>(jobs, njobs, kmax_max, s);
+  return launch_eig_batched_bs<T, 8, 4>(jobs, njobs, kmax_max, s);
+}
+
+template hipError_t launch_eig_batched<float>(int, const EigJob<float>*, int, int, hipStream_t);
+template hipError_t launch_eig_batched<double>(int, const EigJob<double>*, int, int, hipStream_t);
 
 template <class T, int BR, int BC>
 static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int nsplit, int c,

@@ -37,8 +37,8 @@ __device__ __forceinline__ uint32_t insert_zero(uint32_t p, int j) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
-                                                        int cshift) {
+__device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __restrict__ L, int cshift,
+                                               uint32_t tile_index) {
   using C = cx_t<T>;
   extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
   C* tile = reinterpret_cast<C*>(gate_smem);   // [2^k][ncols]
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
   __syncthreads();
 
   // deposit the tile index into the non-local bit positions (ascending local qubits)
-  uint32_t base = blockIdx.x;
+  uint32_t base = tile_index;
   for (int j = 0; j < k; ++j) {
     const int p = P.sorted_q[j];
     base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
@@ -157,12 +157,34 @@ __global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
+                                                        int cshift) {
+  gate_pass_body<T>(P, L, cshift, blockIdx.x);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {
+  const int j = find_job(jobs, njobs, blockIdx.x);
+  gate_pass_body<T>(jobs[j].p, jobs[j].L, jobs[j].cshift, blockIdx.x - jobs[j].block0);
+}
+
+size_t gate_pass_shm(int ncols, int k, size_t csize) { return ((size_t)ncols << k) * csize; }
+
+template <class T>
+hipError_t launch_gate_pass_batched(const GateJob<T>* jobs, int njobs, uint32_t blocks, size_t shm,
+                                    hipStream_t s) {
+  if (njobs < 1 || blocks < 1 || shm > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gate_pass_batched<T>, dim3(blocks), dim3(256), shm, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
   if (p.ncols < 1 || (p.ncols & (p.ncols - 1)) || p.k < 0 || p.k > 8 || p.k > p.n)
     return hipErrorInvalidValue;
   int cshift = 0;
   while ((1 << cshift) < p.ncols) ++cshift;
-  const size_t shm = ((size_t)p.ncols << p.k) * sizeof(cx_t<T>);
+  const size_t shm = gate_pass_shm(p.ncols, p.k, sizeof(cx_t<T>));
   if (shm > 65536) return hipErrorInvalidValue;
   const uint32_t tiles = 1u << (p.n - p.k);
   hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(256), shm, s, p, L, cshift);
@@ -222,6 +244,48 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// State reset of many handles: zero the factor and the compression record, L[0][0] = 1.
+__global__ __launch_bounds__(256) void reset_batched(const ResetJob* __restrict__ jobs, int njobs,
+                                                     int complex_bytes) {
+  const int j = find_job(jobs, njobs, blockIdx.x);
+  const ResetJob& J = jobs[j];
+  const uint64_t words = J.state_bytes / 16;
+  uint4* st = static_cast<uint4*>(J.state);
+  for (uint64_t w = (uint64_t)(blockIdx.x - J.block0) * 256 + threadIdx.x; w < words;
+       w += (uint64_t)J.nblocks * 256)
+    st[w] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == J.block0 && threadIdx.x == 0) {
+    DevInfo zero{};
+    *J.info = zero;
+  }
+  __syncthreads();
+  if (blockIdx.x == J.block0 && threadIdx.x == 0) {
+    if (complex_bytes == 8) {
+      static_cast<float2*>(J.state)[0] = make_float2(1.f, 0.f);
+    } else {
+      static_cast<double2*>(J.state)[0] = make_double2(1.0, 0.0);
+    }
+  }
+}
+
+hipError_t launch_reset_batched(const ResetJob* jobs, int njobs, uint32_t blocks, int complex_bytes,
+                                hipStream_t s) {
+  if (njobs < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reset_batched, dim3(blocks), dim3(256), 0, s, jobs, njobs, complex_bytes);
+  return hipGetLastError();
+}
+
+// Device wall clock (constant-rate counter) into one slot: per-step completion times of a
+// captured batch.
+__global__ void stamp_kernel(uint64_t* slot) { *slot = wall_clock64(); }
+
+hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(1), 0, s, slot);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gate_pass_batched<float>(const GateJob<float>*, int, uint32_t, size_t, hipStream_t);
+template hipError_t launch_gate_pass_batched<double>(const GateJob<double>*, int, uint32_t, size_t, hipStream_t);
 template hipError_t launch_gate_pass<float>(const GatePass<float>&, float2*, hipStream_t);
 template hipError_t launch_gate_pass<double>(const GatePass<double>&, double2*, hipStream_t);
 template hipError_t launch_kraus_expand<float>(float2*, int, int, int, int, const Channel&, int, hipStream_t);

@@ -108,10 +108,9 @@ typedef float gf4 __attribute__((ext_vector_type(4)));   // 16-byte register uni
 // The chunk loop is software-pipelined: the next kGramKC rows are fetched into registers while
 // the MFMAs consume the current chunk from one of two LDS buffers (one barrier per chunk).
 template <class T, int F>
-__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx_t<T>* __restrict__ L, int ld,
-                                                                       int seg_shift, int nsplit, int q,
-                                                                       T* __restrict__ partials, uint32_t rows,
-                                                                       uint32_t rows_per_block) {
+__device__ __forceinline__ void gram_body(const cx_t<T>* __restrict__ L, int ld, int seg_shift, int nsplit,
+                                          int q, T* __restrict__ partials, uint32_t rows,
+                                          uint32_t rows_per_block, uint32_t bid) {
   using Cfg = GramCfg<T, F>;
   using A4 = typename Acc4<T>::type;
   constexpr int VPR = 16 / sizeof(T);          // reals per 16-byte unit
@@ -129,7 +128,7 @@ __global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx
 #pragma unroll
   for (int s = 0; s < Cfg::PER_WAVE; ++s) acc[s] = A4{0, 0, 0, 0};
 
-  const uint32_t r_begin = blockIdx.x * rows_per_block;
+  const uint32_t r_begin = bid * rows_per_block;
   const uint32_t r_end = min(rows, r_begin + rows_per_block);
   const T* Lr = reinterpret_cast<const T*>(L);
   const int seg_mask = (1 << seg_shift) - 1;
@@ -181,7 +180,7 @@ __global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx
     mma(cur);
     odd = !odd;
   }
-  T* out = partials + (size_t)blockIdx.x * Cfg::NUP * 256;
+  T* out = partials + (size_t)bid * Cfg::NUP * 256;
   switch (wave) {
     case 0: gram_store<T, F, 0>(out, acc, lane); break;
     case 1: gram_store<T, F, 1>(out, acc, lane); break;
@@ -191,6 +190,63 @@ __global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx
     case 5: if constexpr (Cfg::NW > 5) gram_store<T, F, 5>(out, acc, lane); break;
     case 6: if constexpr (Cfg::NW > 6) gram_store<T, F, 6>(out, acc, lane); break;
     default: if constexpr (Cfg::NW > 7) gram_store<T, F, 7>(out, acc, lane); break;
+  }
+}
+
+template <class T, int F>
+__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_kernel(const cx_t<T>* __restrict__ L, int ld,
+                                                                       int seg_shift, int nsplit, int q,
+                                                                       T* __restrict__ partials, uint32_t rows,
+                                                                       uint32_t rows_per_block) {
+  gram_body<T, F>(L, ld, seg_shift, nsplit, q, partials, rows, rows_per_block, blockIdx.x);
+}
+
+template <class T, int F>
+__global__ __launch_bounds__((GramCfg<T, F>::THREADS)) void gram_batched(const GramJob<T>* __restrict__ jobs,
+                                                                        int njobs) {
+  const int j = find_job(jobs, njobs, blockIdx.x);
+  const GramJob<T>& J = jobs[j];
+  gram_body<T, F>(J.L, J.ld, J.seg_shift, J.nsplit, J.q, J.partials, J.rows, J.rows_per_block,
+                  blockIdx.x - J.block0);
+}
+
+int gram_seg_shift(int c) {
+  int s = 0;
+  while ((1 << s) < 2 * c) ++s;
+  return ((1 << s) == 2 * c) ? s : -1;
+}
+
+uint32_t gram_rows_per_block(int n, int nsplit, int nblocks) {
+  const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
+  const uint32_t chunks = (rows + kGramKC - 1) / kGramKC;
+  const uint32_t cpb = (chunks + nblocks - 1) / nblocks;
+  return cpb * kGramKC;
+}
+
+template <class T, int F>
+static hipError_t launch_gram_batched_f(const GramJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s) {
+  const size_t shm = 2 * (size_t)kGramKC * GramCfg<T, F>::STRIDE * sizeof(T);
+  if (shm > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(gram_batched<T, F>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((gram_batched<T, F>), dim3(blocks), dim3(GramCfg<T, F>::THREADS), shm, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_gram_batched(int F, const GramJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s) {
+  if (njobs < 1 || blocks < 1) return hipErrorInvalidValue;
+  switch (F) {
+    case 16: return launch_gram_batched_f<T, 16>(jobs, njobs, blocks, s);
+    case 32: return launch_gram_batched_f<T, 32>(jobs, njobs, blocks, s);
+    case 64: return launch_gram_batched_f<T, 64>(jobs, njobs, blocks, s);
+    case 128: return launch_gram_batched_f<T, 128>(jobs, njobs, blocks, s);
+    case 256:
+      if constexpr (sizeof(T) == 4) return launch_gram_batched_f<T, 256>(jobs, njobs, blocks, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -239,10 +295,9 @@ hipError_t launch_gram(const cx_t<T>* L, int n, int ld, int c, int nsplit, int q
 // Sum the split-K partials of one upper tile (fixed order, FP64) and convert the real tile of
 // R into the complex entries of S it covers.
 template <class T>
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ partials, int nblocks,
-                                                          int NT, int NUP, double* __restrict__ S) {
+__device__ __forceinline__ void gram_reduce_body(const T* __restrict__ partials, int nblocks, int NT, int NUP,
+                                                 double* __restrict__ S, int u) {
   __shared__ double R[16][17];
-  const int u = blockIdx.x;
   int ti = 0, rem = u;
   while (rem >= NT - ti) {
     rem -= NT - ti;
@@ -284,6 +339,26 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ 
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const T* __restrict__ partials, int nblocks,
+                                                          int NT, int NUP, double* __restrict__ S) {
+  gram_reduce_body<T>(partials, nblocks, NT, NUP, S, blockIdx.x);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gram_reduce_batched(const ReduceJob<T>* __restrict__ jobs, int njobs) {
+  const int j = find_job(jobs, njobs, blockIdx.x);
+  const ReduceJob<T>& J = jobs[j];
+  gram_reduce_body<T>(J.partials, J.nblocks, J.NT, J.NUP, J.S, (int)(blockIdx.x - J.block0));
+}
+
+template <class T>
+hipError_t launch_gram_reduce_batched(const ReduceJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s) {
+  if (njobs < 1 || blocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gram_reduce_batched<T>, dim3(blocks), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_gram_reduce(const T* partials, int nblocks, int F, double* S, hipStream_t s) {
   const int NT = F / 16;
   const int NUP = NT * (NT + 1) / 2;
@@ -295,5 +370,9 @@ template hipError_t launch_gram<float>(const float2*, int, int, int, int, int, f
 template hipError_t launch_gram<double>(const double2*, int, int, int, int, int, double*, int, hipStream_t);
 template hipError_t launch_gram_reduce<float>(const float*, int, int, double*, hipStream_t);
 template hipError_t launch_gram_reduce<double>(const double*, int, int, double*, hipStream_t);
+template hipError_t launch_gram_batched<float>(int, const GramJob<float>*, int, uint32_t, hipStream_t);
+template hipError_t launch_gram_batched<double>(int, const GramJob<double>*, int, uint32_t, hipStream_t);
+template hipError_t launch_gram_reduce_batched<float>(const ReduceJob<float>*, int, uint32_t, hipStream_t);
+template hipError_t launch_gram_reduce_batched<double>(const ReduceJob<double>*, int, uint32_t, hipStream_t);
 
 }  // namespace lrdm

@@ -41,11 +41,9 @@ template <> struct PPair<double> { typedef double type __attribute__((ext_vector
 // Software pipeline over K chunks: the next chunk of X rows and of W rows is fetched into
 // registers while the MFMAs consume the current chunk from LDS.
 template <class T, int FO>
-__global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L, int ld, int F,
-                                                         int seg_in_shift, int nsplit, int q,
-                                                         int seg_out_shift,
-                                                         const cx_t<T>* __restrict__ W,
-                                                         uint32_t rows) {
+__device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, int F, int seg_in_shift,
+                                             int nsplit, int q, int seg_out_shift,
+                                             const cx_t<T>* __restrict__ W, uint32_t rows, uint32_t bid) {
   using A4 = typename PAcc4<T>::type;
   using P2 = typename PPair<T>::type;
   constexpr int NTO = FO / 16;
@@ -59,7 +57,7 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = lane & 15, kq = lane >> 4;
-  const uint32_t y0 = blockIdx.x * kProjBM;
+  const uint32_t y0 = bid * kProjBM;
   const int seg_in_mask = (1 << seg_in_shift) - 1;
   T* Lr = reinterpret_cast<T*>(L);
   const T* Wr = reinterpret_cast<const T*>(W);
@@ -166,6 +164,42 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
 }
 
 template <class T, int FO>
+__global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L, int ld, int F,
+                                                         int seg_in_shift, int nsplit, int q,
+                                                         int seg_out_shift,
+                                                         const cx_t<T>* __restrict__ W,
+                                                         uint32_t rows) {
+  project_body<T, FO>(L, ld, F, seg_in_shift, nsplit, q, seg_out_shift, W, rows, blockIdx.x);
+}
+
+template <class T, int FO>
+__global__ __launch_bounds__(256, 2) void project_batched(const ProjJob<T>* __restrict__ jobs, int njobs) {
+  const int j = find_job(jobs, njobs, blockIdx.x);
+  const ProjJob<T>& J = jobs[j];
+  project_body<T, FO>(J.L, J.ld, J.F, J.seg_in_shift, J.nsplit, J.q, J.seg_out_shift, J.W, J.rows,
+                      blockIdx.x - J.block0);
+}
+
+template <class T>
+hipError_t launch_project_batched(int FO, const ProjJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s) {
+  if (njobs < 1 || blocks < 1) return hipErrorInvalidValue;
+  switch (FO) {
+    case 16: hipLaunchKernelGGL((project_batched<T, 16>), dim3(blocks), dim3(256), 0, s, jobs, njobs); break;
+    case 32: hipLaunchKernelGGL((project_batched<T, 32>), dim3(blocks), dim3(256), 0, s, jobs, njobs); break;
+    case 64: hipLaunchKernelGGL((project_batched<T, 64>), dim3(blocks), dim3(256), 0, s, jobs, njobs); break;
+    case 128: hipLaunchKernelGGL((project_batched<T, 128>), dim3(blocks), dim3(256), 0, s, jobs, njobs); break;
+    case 256:
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((project_batched<T, 256>), dim3(blocks), dim3(256), 0, s, jobs, njobs);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class T, int FO>
 static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
                                 const cx_t<T>* W, hipStream_t s) {
   const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
@@ -195,6 +229,8 @@ hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q
   }
 }
 
+template hipError_t launch_project_batched<float>(int, const ProjJob<float>*, int, uint32_t, hipStream_t);
+template hipError_t launch_project_batched<double>(int, const ProjJob<double>*, int, uint32_t, hipStream_t);
 template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, hipStream_t);
 template hipError_t launch_project<double>(double2*, int, int, int, int, int, int, const double2*, hipStream_t);
 

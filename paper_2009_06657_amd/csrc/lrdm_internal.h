@@ -69,6 +69,72 @@ constexpr int kRecHeader = 8;
 inline size_t record_doubles(int N) { return (size_t)kRecHeader + N + 2 * (size_t)N * N; }
 constexpr int kRecMaxN = 64;      // largest Gram order with a full record
 
+// ---------------------------------------------------------------- batched launches
+// A batched launch covers one kernel kind for many independent states: job j owns the blocks
+// [block0, block0 + nblocks) of the grid (or block j for one-block jobs).
+template <class J>
+__device__ __forceinline__ int find_job(const J* __restrict__ jobs, int njobs, uint32_t b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T> struct GateJob {
+  GatePass<T> p;
+  cx_t<T>* L;
+  int cshift;
+  uint32_t block0, nblocks;
+};
+template <class T> struct GramJob {
+  const cx_t<T>* L;
+  T* partials;
+  int ld, seg_shift, nsplit, q;
+  uint32_t rows, rows_per_block, block0, nblocks;
+};
+template <class T> struct ReduceJob {
+  const T* partials;
+  double* S;
+  int nblocks, NT, NUP;
+  uint32_t block0;
+};
+template <class T> struct EigJob {
+  const double* S;
+  Channel ch;
+  int Fc, nsplit, c, N, kmax, r_target, tie, renorm, c_out;
+  double eps;
+  EigBufs B;
+  cx_t<T>* W;
+};
+template <class T> struct ProjJob {
+  cx_t<T>* L;
+  const cx_t<T>* W;
+  int ld, F, seg_in_shift, nsplit, q, seg_out_shift;
+  uint32_t rows, block0, nblocks;
+};
+struct ResetJob {
+  void* state;
+  DevInfo* info;
+  uint64_t state_bytes;
+  uint32_t block0, nblocks;
+};
+
+// Batched launchers (jobs in device memory; the host also keeps the launch shape)
+template <class T> hipError_t launch_gate_pass_batched(const GateJob<T>* jobs, int njobs, uint32_t blocks, size_t shm, hipStream_t s);
+template <class T> hipError_t launch_gram_batched(int F, const GramJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s);
+template <class T> hipError_t launch_gram_reduce_batched(const ReduceJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s);
+template <class T> hipError_t launch_eig_batched(int N, const EigJob<T>* jobs, int njobs, int kmax_max, hipStream_t s);
+template <class T> hipError_t launch_project_batched(int FO, const ProjJob<T>* jobs, int njobs, uint32_t blocks, hipStream_t s);
+hipError_t launch_reset_batched(const ResetJob* jobs, int njobs, uint32_t blocks, int complex_bytes, hipStream_t s);
+hipError_t launch_stamp(uint64_t* slot, hipStream_t s);
+
+// Launch-shape helpers shared by the single and batched paths
+int gram_seg_shift(int c);                       // log2(2c), -1 if 2c is not a power of two
+uint32_t gram_rows_per_block(int n, int nsplit, int nblocks);
+size_t gate_pass_shm(int ncols, int k, size_t csize);
+
 // ---------------------------------------------------------------- launchers (k_*.hip)
 template <class T>
 hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s);

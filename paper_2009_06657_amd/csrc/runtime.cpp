@@ -97,6 +97,27 @@ struct PendingGate {
   std::vector<double> coef;
 };
 
+// Launches recorded instead of issued while a handle belongs to a batch being recorded
+// (complex64 only).  Items keep the handle's issue order; job structs hold every argument.
+enum RecKind : int { REC_RESET = 0, REC_GATE = 1, REC_GRAM = 2, REC_REDUCE = 3, REC_EIG = 4, REC_PROJ = 5 };
+struct RecItem {
+  int kind;
+  int cls;          // F (Gram), N (eigensolve), FO (projection)
+  int kmax;         // eigensolve
+  uint32_t blocks;
+  size_t shm;       // gate pass
+  size_t idx;       // index into the per-kind vector
+};
+struct Recorder {
+  std::vector<RecItem> items;
+  std::vector<ResetJob> resets;
+  std::vector<GateJob<float>> gates;
+  std::vector<GramJob<float>> grams;
+  std::vector<ReduceJob<float>> reds;
+  std::vector<EigJob<float>> eigs;
+  std::vector<ProjJob<float>> projs;
+};
+
 }  // namespace
 
 void lrdm::set_last_error(const char* msg) { g_last_error = msg; }
@@ -124,6 +145,8 @@ struct lrdm_ctx {
   int ev_used = 0;
   // host staging
   std::vector<uint64_t> term_stage;
+  // batch recording (non-null between lrdm_batch_begin and lrdm_batch_end)
+  Recorder* rec = nullptr;
 
   template <class P> P* ws(size_t off) { return reinterpret_cast<P*>(work + off); }
 };
@@ -250,6 +273,21 @@ lrdm_status flush_gates_t(lrdm_t h) {
     for (int j = 0; j < nloc; ++j) sorted[j] = p.local_q[j];
     std::sort(sorted, sorted + nloc);
     for (int j = 0; j < nloc; ++j) p.sorted_q[j] = sorted[j];
+    if (h->rec) {
+      if constexpr (sizeof(T) == 4) {
+        GateJob<float> j;
+        j.p = p;
+        j.L = static_cast<float2*>(h->state);
+        j.cshift = 0;
+        while ((1 << j.cshift) < p.ncols) ++j.cshift;
+        j.block0 = 0;
+        j.nblocks = 1u << (p.n - p.k);
+        h->rec->items.push_back({REC_GATE, 0, 0, j.nblocks, gate_pass_shm(p.ncols, p.k, sizeof(float2)),
+                                 h->rec->gates.size()});
+        h->rec->gates.push_back(j);
+      }
+      continue;
+    }
     timed_begin(h, 0);
     HIPCHK(h, launch_gate_pass<T>(p, static_cast<cx_t<T>*>(h->state), h->stream));
     timed_end(h, 0);
@@ -263,8 +301,15 @@ lrdm_status flush_gates(lrdm_t h) {
   return h->dt == LRDM_C64 ? flush_gates_t<float>(h) : flush_gates_t<double>(h);
 }
 
+lrdm_status not_recording(lrdm_t h) {
+  if (h->rec) return fail(h, LRDM_E_STATE, "the handle is being recorded into a batch (lrdm_batch_end first)");
+  return LRDM_OK;
+}
+
 lrdm_status ready_for_output(lrdm_t h) {
   lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  st = not_recording(h);
   if (st != LRDM_OK) return st;
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
   return flush_gates(h);
@@ -323,6 +368,70 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   auto* L = static_cast<cx_t<T>*>(h->state);
   T* part = h->ws<T>(h->lay.off_part);
   cx_t<T>* W = h->ws<cx_t<T>>(h->lay.off_W);
+  if (h->rec) {
+    if constexpr (sizeof(T) == 4) {
+      Recorder& R = *h->rec;
+      GramJob<float> g;
+      g.L = L;
+      g.partials = part;
+      g.ld = h->lay.ld;
+      g.seg_shift = gram_seg_shift(c);
+      g.nsplit = nsplit;
+      g.q = q;
+      g.rows = 1u << (h->n - (nsplit == 2 ? 1 : 0));
+      g.rows_per_block = gram_rows_per_block(h->n, nsplit, nb);
+      g.block0 = 0;
+      g.nblocks = (uint32_t)nb;
+      if (g.seg_shift < 0) return fail(h, LRDM_E_UNSUPPORTED, "column count is not a power of two");
+      R.items.push_back({REC_GRAM, F, 0, g.nblocks, 0, R.grams.size()});
+      R.grams.push_back(g);
+      ReduceJob<float> rj;
+      rj.partials = part;
+      rj.S = b.S;
+      rj.nblocks = nb;
+      rj.NT = F / 16;
+      rj.NUP = rj.NT * (rj.NT + 1) / 2;
+      rj.block0 = 0;
+      R.items.push_back({REC_REDUCE, F, 0, (uint32_t)rj.NUP, 0, R.reds.size()});
+      R.reds.push_back(rj);
+      EigJob<float> e;
+      e.S = b.S;
+      e.ch = ch;
+      e.Fc = Fc;
+      e.nsplit = nsplit;
+      e.c = c;
+      e.N = N;
+      e.kmax = kmax;
+      e.r_target = r_target;
+      e.tie = tie;
+      e.renorm = renorm;
+      e.c_out = c_out;
+      e.eps = eps;
+      e.B = b;
+      e.W = W;
+      R.items.push_back({REC_EIG, N, kmax, 1, 0, R.eigs.size()});
+      R.eigs.push_back(e);
+      ProjJob<float> pj;
+      pj.L = L;
+      pj.W = W;
+      pj.ld = h->lay.ld;
+      pj.F = 2 * nsplit * c;
+      pj.seg_in_shift = gram_seg_shift(c);
+      pj.nsplit = nsplit;
+      pj.q = q;
+      pj.seg_out_shift = gram_seg_shift(c_out);
+      pj.rows = 1u << (h->n - (nsplit == 2 ? 1 : 0));
+      pj.block0 = 0;
+      pj.nblocks = (pj.rows + 127) / 128;
+      R.items.push_back({REC_PROJ, 2 * nsplit * c_out, 0, pj.nblocks, 0, R.projs.size()});
+      R.projs.push_back(pj);
+    }
+    h->ncols = c_out;
+    const int grown_r = (nsplit == 2) ? h->c_bound * ch.m : h->c_bound;
+    h->c_bound = std::min(std::min(grown_r, r_target), N);
+    h->chan_pending = false;
+    return LRDM_OK;
+  }
   timed_begin(h, 1);
   HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
   timed_end(h, 1);
@@ -345,6 +454,23 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
 
 template <class T>
 lrdm_status reset_t(lrdm_t h) {
+  if (h->rec) {
+    ResetJob j;
+    j.state = h->state;
+    j.info = h->ws<DevInfo>(h->lay.off_info);
+    j.state_bytes = h->lay.state_bytes;
+    j.block0 = 0;
+    const uint64_t words = h->lay.state_bytes / 16;
+    const uint64_t want = (words + 256 * 16 - 1) / (256 * 16);
+    j.nblocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 1024));
+    h->rec->items.push_back({REC_RESET, 0, 0, j.nblocks, 0, h->rec->resets.size()});
+    h->rec->resets.push_back(j);
+    h->ncols = h->lay.r_pad;
+    h->c_bound = 1;
+    h->gates.clear();
+    h->chan_pending = false;
+    return LRDM_OK;
+  }
   HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
   HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
   HIPCHK(h, launch_set_e0<T>(static_cast<cx_t<T>*>(h->state), h->stream));
@@ -448,6 +574,8 @@ lrdm_status pauli_values(lrdm_t h, const void* bra, int n_terms, const uint64_t*
 
 lrdm_status compress_entry(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
                            double* rec, lrdm_compress_info* info) {
+  if (h && h->rec && (info || rec))
+    return fail(h, LRDM_E_STATE, "a recorded compression cannot report info or write a record");
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
   if (r_target < 1 || r_target > h->r_max) return fail(h, LRDM_E_ARG, "r_target must be in [1, r_max]");
@@ -750,6 +878,8 @@ lrdm_status lrdm_get_L(lrdm_t h, void* dst, int to_host, int* rank_out) {
 lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
+  st = not_recording(h);
+  if (st != LRDM_OK) return st;
   if (!src) return fail(h, LRDM_E_ARG, "null source");
   if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
@@ -769,6 +899,8 @@ lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank) {
 lrdm_status lrdm_synchronize(lrdm_t h) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
+  st = not_recording(h);
+  if (st != LRDM_OK) return st;
   st = flush_gates(h);
   if (st != LRDM_OK) return st;
   return sync_and_check(h);
@@ -776,6 +908,8 @@ lrdm_status lrdm_synchronize(lrdm_t h) {
 
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {
   lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  st = not_recording(h);
   if (st != LRDM_OK) return st;
   if (kernel_class < 0 || kernel_class > 4) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 4]");
   if (h->ev.empty()) {
@@ -829,6 +963,8 @@ lrdm_status lrdm_checkpoint(lrdm_t h, void* dst_dev, int* rank_out) {
 lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
+  st = not_recording(h);
+  if (st != LRDM_OK) return st;
   if (!src_dev) return fail(h, LRDM_E_ARG, "null source");
   if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
@@ -842,6 +978,8 @@ lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank) {
 lrdm_status lrdm_apply_pauli_sum(lrdm_t dst, lrdm_t src, int n_terms, const uint64_t* xmask,
                                  const uint64_t* zmask, const double* coeff) {
   lrdm_status st = check_usable(dst);
+  if (st != LRDM_OK) return st;
+  st = not_recording(dst);
   if (st != LRDM_OK) return st;
   st = ready_for_output(src);
   if (st != LRDM_OK) return st;
@@ -892,6 +1030,8 @@ lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec
                                   int m, const double* e) {
   lrdm_status st = check_usable(bar);
   if (st != LRDM_OK) return st;
+  st = not_recording(bar);
+  if (st != LRDM_OK) return st;
   if (!bar->lay.adjoint)
     return fail(bar, LRDM_E_UNSUPPORTED, "the reverse sweep needs the fused form and m_max * r_pad <= 64");
   if (!x_dev || !rec_dev || !e) return fail(bar, LRDM_E_ARG, "null argument");
@@ -909,6 +1049,387 @@ lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec
   HIPCHK(bar, he);
   bar->ncols = bar->lay.r_pad;
   bar->c_bound = bar->lay.r_pad;
+  return LRDM_OK;
+}
+
+// ---------------------------------------------------------------- batched serving
+}  // extern "C"
+
+struct lrdm_batch_ctx {
+  struct Launch {
+    int kind;          // RecKind, or -1 for a step stamp
+    int cls, kmax, njobs;
+    uint32_t blocks;
+    size_t shm, off;   // off: job array (or stamp slot) offset in the plan buffer
+  };
+  std::vector<lrdm_t> hs;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<hipStream_t> hstreams;   // distinct streams of the handles
+  hipEvent_t ev_before = nullptr, ev_after = nullptr;
+  bool recording = false;
+  std::vector<Recorder> recs;
+  std::vector<Launch> launches;
+  std::vector<unsigned char> plan;
+  size_t plan_bytes = 0;
+  int nsteps = 0;
+  std::vector<int> last_step;
+  char* plan_dev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double ticks_per_ms = 0;
+};
+
+namespace {
+
+lrdm_status bfail(lrdm_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void drop_graph(lrdm_batch_t b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->plan_dev = nullptr;
+}
+
+template <class J>
+size_t put_jobs(std::vector<unsigned char>& plan, const std::vector<J>& jobs) {
+  const size_t off = align_up(plan.size());
+  plan.resize(off + jobs.size() * sizeof(J));
+  std::memcpy(plan.data() + off, jobs.data(), jobs.size() * sizeof(J));
+  return off;
+}
+
+int eig_class(int N) { return N <= 32 ? 0 : (N <= 64 ? 1 : 2); }
+
+// Lockstep schedule: step s of every instance (the operations up to and including its s-th
+// projection) is issued together, one batched launch per kernel kind and size class.
+lrdm_status build_plan(lrdm_batch_t b) {
+  const int ni = (int)b->hs.size();
+  std::vector<std::vector<std::vector<RecItem>>> steps(ni);
+  b->nsteps = 0;
+  b->last_step.assign(ni, -1);
+  for (int i = 0; i < ni; ++i) {
+    std::vector<RecItem> cur;
+    for (const RecItem& it : b->recs[i].items) {
+      if (!cur.empty() && it.kind < cur.back().kind && !(it.kind == REC_GATE && cur.back().kind == REC_GATE))
+        return bfail(LRDM_E_UNSUPPORTED, "batched instances must issue resets, gates and then one compression per step");
+      cur.push_back(it);
+      if (it.kind == REC_PROJ) {
+        steps[i].push_back(cur);
+        cur.clear();
+      }
+    }
+    if (!cur.empty()) steps[i].push_back(cur);
+    b->last_step[i] = (int)steps[i].size() - 1;
+    b->nsteps = std::max(b->nsteps, (int)steps[i].size());
+  }
+  b->plan.assign(align_up((size_t)(b->nsteps + 1) * 8), 0);
+  b->launches.clear();
+  for (int s = 0; s < b->nsteps; ++s) {
+    // resets
+    {
+      std::vector<ResetJob> jobs;
+      uint32_t blocks = 0;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_RESET) {
+            ResetJob j = b->recs[i].resets[it.idx];
+            j.block0 = blocks;
+            blocks += j.nblocks;
+            jobs.push_back(j);
+          }
+      }
+      if (!jobs.empty()) b->launches.push_back({REC_RESET, 0, 0, (int)jobs.size(), blocks, 0, put_jobs(b->plan, jobs)});
+    }
+    // gate passes, by their position inside the step
+    for (int g = 0;; ++g) {
+      std::vector<GateJob<float>> jobs;
+      uint32_t blocks = 0;
+      size_t shm = 0;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        int seen = 0;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_GATE && seen++ == g) {
+            GateJob<float> j = b->recs[i].gates[it.idx];
+            j.block0 = blocks;
+            blocks += j.nblocks;
+            shm = std::max(shm, it.shm);
+            jobs.push_back(j);
+          }
+      }
+      if (jobs.empty()) break;
+      b->launches.push_back({REC_GATE, 0, 0, (int)jobs.size(), blocks, shm, put_jobs(b->plan, jobs)});
+    }
+    // Gram, by width
+    for (int F : {16, 32, 64, 128, 256}) {
+      std::vector<GramJob<float>> jobs;
+      uint32_t blocks = 0;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_GRAM && it.cls == F) {
+            GramJob<float> j = b->recs[i].grams[it.idx];
+            j.block0 = blocks;
+            blocks += j.nblocks;
+            jobs.push_back(j);
+          }
+      }
+      if (!jobs.empty()) b->launches.push_back({REC_GRAM, F, 0, (int)jobs.size(), blocks, 0, put_jobs(b->plan, jobs)});
+    }
+    // Gram reductions
+    {
+      std::vector<ReduceJob<float>> jobs;
+      uint32_t blocks = 0;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_REDUCE) {
+            ReduceJob<float> j = b->recs[i].reds[it.idx];
+            j.block0 = blocks;
+            blocks += it.blocks;
+            jobs.push_back(j);
+          }
+      }
+      if (!jobs.empty()) b->launches.push_back({REC_REDUCE, 0, 0, (int)jobs.size(), blocks, 0, put_jobs(b->plan, jobs)});
+    }
+    // eigensolves, one work-group each, by size class
+    for (int cl = 0; cl < 3; ++cl) {
+      std::vector<EigJob<float>> jobs;
+      int kmax = 1, Nmax = 1;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_EIG && eig_class(it.cls) == cl) {
+            jobs.push_back(b->recs[i].eigs[it.idx]);
+            kmax = std::max(kmax, it.kmax);
+            Nmax = std::max(Nmax, it.cls);
+          }
+      }
+      if (!jobs.empty())
+        b->launches.push_back({REC_EIG, Nmax, kmax, (int)jobs.size(), (uint32_t)jobs.size(), 0, put_jobs(b->plan, jobs)});
+    }
+    // projections, by output width
+    for (int FO : {16, 32, 64, 128, 256}) {
+      std::vector<ProjJob<float>> jobs;
+      uint32_t blocks = 0;
+      for (int i = 0; i < ni; ++i) {
+        if (s >= (int)steps[i].size()) continue;
+        for (const RecItem& it : steps[i][s])
+          if (it.kind == REC_PROJ && it.cls == FO) {
+            ProjJob<float> j = b->recs[i].projs[it.idx];
+            j.block0 = blocks;
+            blocks += j.nblocks;
+            jobs.push_back(j);
+          }
+      }
+      if (!jobs.empty()) b->launches.push_back({REC_PROJ, FO, 0, (int)jobs.size(), blocks, 0, put_jobs(b->plan, jobs)});
+    }
+    b->launches.push_back({-1, 0, 0, 0, 0, 0, (size_t)(s + 1) * 8});
+  }
+  b->plan_bytes = align_up(b->plan.size());
+  b->plan.resize(b->plan_bytes, 0);
+  return LRDM_OK;
+}
+
+hipError_t issue(lrdm_batch_t b, const lrdm_batch_ctx::Launch& L) {
+  char* base = b->plan_dev;
+  switch (L.kind) {
+    case -1: return launch_stamp(reinterpret_cast<uint64_t*>(base + L.off), b->stream);
+    case REC_RESET:
+      return launch_reset_batched(reinterpret_cast<const ResetJob*>(base + L.off), L.njobs, L.blocks, 8, b->stream);
+    case REC_GATE:
+      return launch_gate_pass_batched<float>(reinterpret_cast<const GateJob<float>*>(base + L.off), L.njobs,
+                                             L.blocks, L.shm, b->stream);
+    case REC_GRAM:
+      return launch_gram_batched<float>(L.cls, reinterpret_cast<const GramJob<float>*>(base + L.off), L.njobs,
+                                        L.blocks, b->stream);
+    case REC_REDUCE:
+      return launch_gram_reduce_batched<float>(reinterpret_cast<const ReduceJob<float>*>(base + L.off), L.njobs,
+                                               L.blocks, b->stream);
+    case REC_EIG:
+      return launch_eig_batched<float>(L.cls, reinterpret_cast<const EigJob<float>*>(base + L.off), L.njobs, L.kmax,
+                                       b->stream);
+    case REC_PROJ:
+      return launch_project_batched<float>(L.cls, reinterpret_cast<const ProjJob<float>*>(base + L.off), L.njobs,
+                                           L.blocks, b->stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lrdm_status lrdm_batch_create(lrdm_batch_t* out, int n_inst, const lrdm_t* handles, void* hip_stream) {
+  if (!out) return bfail(LRDM_E_ARG, "null output handle pointer");
+  *out = nullptr;
+  if (n_inst < 1 || !handles) return bfail(LRDM_E_ARG, "need at least one handle");
+  for (int i = 0; i < n_inst; ++i) {
+    lrdm_t h = handles[i];
+    lrdm_status st = check_usable(h);
+    if (st != LRDM_OK) return st;
+    if (h->dt != LRDM_C64) return bfail(LRDM_E_UNSUPPORTED, "batched serving runs complex64 handles");
+    if (h->plain) return bfail(LRDM_E_UNSUPPORTED, "batched serving runs the fused form");
+    if (h->rec) return bfail(LRDM_E_STATE, "a handle is already being recorded");
+    for (int j = 0; j < i; ++j)
+      if (handles[j] == h) return bfail(LRDM_E_ARG, "repeated handle");
+  }
+  lrdm_batch_ctx* b = new lrdm_batch_ctx();
+  b->hs.assign(handles, handles + n_inst);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipSuccess;
+  if (!b->stream) {   // graphs are captured on a non-default stream (default priority)
+    e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    b->own_stream = (e == hipSuccess);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_before, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_after, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->own_stream) hipStreamDestroy(b->stream);
+    if (b->ev_before) hipEventDestroy(b->ev_before);
+    delete b;
+    return bfail(LRDM_E_HIP, std::string("batch stream/event: ") + hipGetErrorString(e));
+  }
+  for (lrdm_t h : b->hs)
+    if (h->stream != b->stream &&
+        std::find(b->hstreams.begin(), b->hstreams.end(), h->stream) == b->hstreams.end())
+      b->hstreams.push_back(h->stream);
+  b->recs.resize(n_inst);
+  *out = b;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_begin(lrdm_batch_t b) {
+  if (!b) return bfail(LRDM_E_ARG, "null batch");
+  if (b->recording) return bfail(LRDM_E_STATE, "already recording");
+  for (lrdm_t h : b->hs) {
+    lrdm_status st = check_usable(h);
+    if (st != LRDM_OK) return st;
+    if (h->rec) return bfail(LRDM_E_STATE, "a handle is already being recorded");
+    if (h->chan_pending) return bfail(LRDM_E_STATE, "a handle has a pending Kraus channel");
+  }
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    lrdm_t h = b->hs[i];
+    lrdm_status st = flush_gates(h);
+    if (st != LRDM_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    b->recs[i] = Recorder();
+    h->rec = &b->recs[i];
+  }
+  drop_graph(b);
+  b->recording = true;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_end(lrdm_batch_t b, size_t* plan_bytes) {
+  if (!b || !plan_bytes) return bfail(LRDM_E_ARG, "null argument");
+  if (!b->recording) return bfail(LRDM_E_STATE, "not recording");
+  lrdm_status result = LRDM_OK;
+  for (lrdm_t h : b->hs) {
+    lrdm_status st = flush_gates(h);
+    if (st != LRDM_OK && result == LRDM_OK) result = st;
+    if (h->chan_pending && result == LRDM_OK)
+      result = bfail(LRDM_E_STATE, "a recorded program ends with a Kraus channel that was not compressed");
+    h->rec = nullptr;
+  }
+  b->recording = false;
+  if (result != LRDM_OK) return result;
+  lrdm_status st = build_plan(b);
+  if (st != LRDM_OK) return st;
+  *plan_bytes = b->plan_bytes;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_instantiate(lrdm_batch_t b, void* plan_dev, size_t plan_bytes) {
+  if (!b || !plan_dev) return bfail(LRDM_E_ARG, "null argument");
+  if (b->recording || b->plan_bytes == 0) return bfail(LRDM_E_STATE, "record and end the batch first");
+  if (plan_bytes < b->plan_bytes) return bfail(LRDM_E_NOMEM, "plan buffer smaller than lrdm_batch_end reported");
+  if (reinterpret_cast<uintptr_t>(plan_dev) & 255) return bfail(LRDM_E_ARG, "plan buffer must be 256-byte aligned");
+  drop_graph(b);
+  b->plan_dev = static_cast<char*>(plan_dev);
+  hipError_t e = hipMemcpy(plan_dev, b->plan.data(), b->plan_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bfail(LRDM_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  int dev = 0, khz = 0;
+  hipGetDevice(&dev);
+  e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess || khz <= 0) return bfail(LRDM_E_HIP, "cannot read the device wall-clock rate");
+  b->ticks_per_ms = (double)khz;
+  e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return bfail(LRDM_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  hipError_t le = launch_stamp(reinterpret_cast<uint64_t*>(b->plan_dev), b->stream);
+  for (size_t i = 0; i < b->launches.size() && le == hipSuccess; ++i) le = issue(b, b->launches[i]);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (le != hipSuccess) {
+    drop_graph(b);
+    return bfail(LRDM_E_HIP, std::string("batched launch: ") + hipGetErrorString(le));
+  }
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return bfail(LRDM_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return bfail(LRDM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  b->plan_dev = static_cast<char*>(plan_dev);
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_launch(lrdm_batch_t b) {
+  if (!b) return bfail(LRDM_E_ARG, "null batch");
+  if (!b->exec) return bfail(LRDM_E_STATE, "instantiate the batch first");
+  // the replay waits for work queued on the handles' streams, and later work there waits for it
+  hipError_t e = hipSuccess;
+  for (hipStream_t hs : b->hstreams) {
+    if (e == hipSuccess) e = hipEventRecord(b->ev_before, hs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_before, 0);
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_after, b->stream);
+  for (hipStream_t hs : b->hstreams)
+    if (e == hipSuccess) e = hipStreamWaitEvent(hs, b->ev_after, 0);
+  if (e != hipSuccess) return bfail(LRDM_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_info(lrdm_batch_t b, int* n_steps, int* n_launches) {
+  if (!b) return bfail(LRDM_E_ARG, "null batch");
+  if (n_steps) *n_steps = b->nsteps;
+  if (n_launches) *n_launches = (int)b->launches.size() + 1;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_times(lrdm_batch_t b, double* done_ms, double* total_ms) {
+  if (!b) return bfail(LRDM_E_ARG, "null batch");
+  if (!b->exec) return bfail(LRDM_E_STATE, "instantiate and launch the batch first");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(LRDM_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  std::vector<uint64_t> st(b->nsteps + 1);
+  e = hipMemcpy(st.data(), b->plan_dev, st.size() * 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bfail(LRDM_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  if (done_ms)
+    for (size_t i = 0; i < b->hs.size(); ++i)
+      done_ms[i] = b->last_step[i] >= 0 ? (double)(st[b->last_step[i] + 1] - st[0]) / b->ticks_per_ms : 0.0;
+  if (total_ms) *total_ms = (double)(st[b->nsteps] - st[0]) / b->ticks_per_ms;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_batch_destroy(lrdm_batch_t b) {
+  if (!b) return bfail(LRDM_E_ARG, "null batch");
+  if (b->recording)
+    for (lrdm_t h : b->hs) h->rec = nullptr;
+  drop_graph(b);
+  if (b->ev_before) hipEventDestroy(b->ev_before);
+  if (b->ev_after) hipEventDestroy(b->ev_after);
+  if (b->own_stream) hipStreamDestroy(b->stream);
+  delete b;
   return LRDM_OK;
 }
 

@@ -28,7 +28,9 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_restore", "lrdm_apply_pauli_sum", "lrdm_pauli_overlap", "lrdm_compress_adjoint",
            "lrdm_fdm_state_bytes", "lrdm_fdm_init", "lrdm_fdm_reset", "lrdm_fdm_destroy",
            "lrdm_fdm_apply_gate", "lrdm_fdm_apply_kraus", "lrdm_fdm_probabilities",
-           "lrdm_fdm_synchronize", "lrdm_fdm_last_error"]
+           "lrdm_fdm_synchronize", "lrdm_fdm_last_error", "lrdm_batch_create", "lrdm_batch_begin",
+           "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
+           "lrdm_batch_times", "lrdm_batch_destroy"]
 
 
 class LrdmError(RuntimeError):
@@ -92,6 +94,14 @@ def load_library(path: str = LIB_PATH):
         "lrdm_fdm_apply_kraus": [P, I, I, dp],
         "lrdm_fdm_probabilities": [P, P],
         "lrdm_fdm_synchronize": [P],
+        "lrdm_batch_create": [ctypes.POINTER(P), I, ctypes.POINTER(P), P],
+        "lrdm_batch_begin": [P],
+        "lrdm_batch_end": [P, ctypes.POINTER(SZ)],
+        "lrdm_batch_instantiate": [P, P, SZ],
+        "lrdm_batch_launch": [P],
+        "lrdm_batch_info": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
+        "lrdm_batch_times": [P, dp, dp],
+        "lrdm_batch_destroy": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -358,6 +368,80 @@ class FullRankDM:
         self.synchronize()
         a = self.state.view(dtype=__import__("torch").complex64).cpu().numpy()
         return a.reshape(2 ** self.n, 2 ** self.n).astype(np.complex128)
+
+
+class Batch:
+    """Many complex64 handles recorded once and replayed as one captured hipGraph (lockstep
+    batched launches; see lrdm_batch_* in include/lrdm.h).
+
+        b = Batch(handles)
+        with b.recording():
+            for dm, prog in zip(handles, programs):
+                dm.reset(); run_program(dm, prog)
+        b.launch(); done_ms, total_ms = b.times()
+    """
+
+    def __init__(self, handles: Sequence[LowRankDM], stream=None):
+        import torch
+
+        self.lib = load_library()
+        self.handles = list(handles)
+        dev = self.handles[0].device
+        self.device = dev
+        self.stream = stream   # None: the library captures and replays on a stream of its own
+        arr = (ctypes.c_void_p * len(self.handles))(*[h.h.value for h in self.handles])
+        self.b = ctypes.c_void_p()
+        _check(self.lib.lrdm_batch_create(ctypes.byref(self.b), len(self.handles), arr,
+                                          ctypes.c_void_p(stream.cuda_stream) if stream is not None else None))
+        self.plan = None
+
+    def begin(self):
+        _check(self.lib.lrdm_batch_begin(self.b))
+
+    def end(self):
+        import torch
+
+        nbytes = ctypes.c_size_t()
+        _check(self.lib.lrdm_batch_end(self.b, ctypes.byref(nbytes)))
+        self.plan = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        _check(self.lib.lrdm_batch_instantiate(self.b, ctypes.c_void_p(self.plan.data_ptr()), nbytes.value))
+
+    def recording(self):
+        import contextlib
+
+        @contextlib.contextmanager
+        def ctx():
+            self.begin()
+            try:
+                yield self
+            finally:
+                self.end()
+        return ctx()
+
+    def launch(self):
+        _check(self.lib.lrdm_batch_launch(self.b))
+
+    def info(self):
+        s, l = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.lrdm_batch_info(self.b, ctypes.byref(s), ctypes.byref(l)))
+        return s.value, l.value
+
+    def times(self):
+        done = np.zeros(len(self.handles))
+        tot = np.zeros(1)
+        _check(self.lib.lrdm_batch_times(self.b, _dptr(done), _dptr(tot)))
+        return done, float(tot[0])
+
+    def close(self):
+        if self.b:
+            self.lib.lrdm_batch_destroy(self.b)
+            self.b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run_program_fdm(fdm: FullRankDM, program):

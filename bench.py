@@ -212,6 +212,72 @@ def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 16) -> dict:
             "extrapolation": f"T_full({nmax}) * 4^(20 - {nmax})"}
 
 
+def batched_serving(count: int = 256, loop_budget_s: float = 30.0) -> dict:
+    """The serving mix: `count` independent brickwork instances (n ~ U{8..16}, r ~ U{8,16,32},
+    10..30 layers, depolarizing p ~ U(1e-4, 5e-3), compress after every channel, <Z> per
+    instance) recorded once and replayed as one captured graph of lockstep batched launches,
+    against looping the unbatched path over the same instances (timed until `loop_budget_s`, the
+    rest extrapolated by layer count)."""
+    import torch
+
+    import paper_2009_06657_amd as lr
+    from workloads import circuits as C
+
+    progs = C.cfg5_instances(count)
+    layers = np.array([p.layers for p in progs], dtype=np.float64)
+    hs = [lr.LowRankDM(p.n, p.r, lr.C64, p.m_max) for p in progs]
+    b = lr.Batch(hs)
+    with b.recording():
+        for dm, p in zip(hs, progs):
+            dm.reset()
+            lr.run_program(dm, p)
+    steps, launches = b.info()
+    b.launch()
+    b.times()
+    t0 = time.perf_counter()
+    b.launch()
+    done_ms, total_ms = b.times()
+    zs = [dm.expect_z()[0] for dm in hs]
+    wall = time.perf_counter() - t0
+    b.close()
+    for dm in hs:
+        dm.close()
+    del hs
+    torch.cuda.empty_cache()
+    # unbatched loop over the same instances (one handle reused per shape)
+    per_inst = np.full(count, np.nan)
+    t_start = time.perf_counter()
+    cache = {}
+    for i, p in enumerate(progs):
+        key = (p.n, p.r, p.m_max)
+        if key not in cache:
+            cache[key] = lr.LowRankDM(p.n, p.r, lr.C64, p.m_max)
+        dm = cache[key]
+        t1 = time.perf_counter()
+        dm.reset()
+        lr.run_program(dm, p)
+        dm.expect_z()
+        per_inst[i] = time.perf_counter() - t1
+        if time.perf_counter() - t_start > loop_budget_s:
+            break
+    ran = ~np.isnan(per_inst)
+    loop_time = float(np.nansum(per_inst)) * (layers.sum() / layers[ran].sum())
+    for dm in cache.values():
+        dm.close()
+    return {"workload": f"{count} brickwork instances, n U{{8..16}}, r U{{8,16,32}}, 10-30 layers, "
+                        "depolarizing U(1e-4, 5e-3), compress after every channel, <Z> per instance",
+            "instances": count, "total_layers": int(layers.sum()),
+            "lockstep_steps": steps, "graph_launches": launches,
+            "batched_layers_per_s": float(layers.sum() / (total_ms * 1e-3)),
+            "batched_ms": total_ms, "batched_wall_ms_with_outputs": 1e3 * wall,
+            "latency_ms_p50": float(np.percentile(done_ms, 50)), "latency_ms_p99": float(np.percentile(done_ms, 99)),
+            "looped_layers_per_s": float(layers.sum() / loop_time), "looped_ms": 1e3 * loop_time,
+            "looped_instances_timed": int(ran.sum()),
+            "looped_latency_ms_p50": float(np.nanpercentile(per_inst, 50) * 1e3),
+            "looped_latency_ms_p99": float(np.nanpercentile(per_inst, 99) * 1e3),
+            "speedup": loop_time / (total_ms * 1e-3)}
+
+
 def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 3) -> None:
     """A plain device-to-device copy of a known size: the HBM counters read for it (bytes
     fetched, bytes written per dispatch) give the scale factor applied to the same counters
@@ -235,6 +301,7 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-throughput leg")
     ap.add_argument("--no-fdm", action="store_true", help="skip the full-rank comparator leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -298,6 +365,8 @@ def main():
         out["breakdown_one_step"] = br
     if not args.no_grad:
         out["grads_per_s"] = gradient_throughput()
+    if not args.no_batch:
+        out["batched_serving"] = batched_serving()
     if not args.no_fdm:
         fd = fdm_comparator()
         fd["speedup_n20_vs_extrapolated_full_rank"] = fd["full_rank_ms_per_layer_n20_extrapolated"] / ms_per_layer

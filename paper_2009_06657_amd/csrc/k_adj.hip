@@ -44,6 +44,12 @@ __device__ __forceinline__ zd echan(const Channel& ch, int a, int r, int c) {
   return zd{ch.e[a][r][c][0], ch.e[a][r][c][1]};
 }
 
+// rows per split-K chunk of the cross Gram: at least 64, at most kAdjChunks chunks
+__host__ inline uint32_t adj_rows_per_chunk(uint32_t half_rows) {
+  const uint32_t by_count = (half_rows + kAdjChunks - 1) / kAdjChunks;
+  return by_count > 64u ? by_count : 64u;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- H L
@@ -134,6 +140,23 @@ __global__ __launch_bounds__(256) void cross_gram_reduce_kernel(const double* __
   }
   C[2 * e] = sr;
   C[2 * e + 1] = si;
+}
+
+// S = X^H X of the split view with products and sums in FP64 (exact products of complex64
+// entries): the Gram matrix of a recorded compression, whose null space then stays at the FP64
+// rounding level so that the reverse sweep can recognise it.
+template <class T>
+hipError_t launch_gram_exact(const cx_t<T>* L, int n, int ld, int c, int q, double* part, double* S,
+                             hipStream_t s) {
+  if (c < 1 || 2 * c > 128 || n < 1 || q < 0 || q >= n) return hipErrorInvalidValue;
+  const uint32_t half_rows = 1u << (n - 1);
+  const int w2 = 2 * c, nent = w2 * w2;
+  const uint32_t rpc = adj_rows_per_chunk(half_rows);
+  const int nchunks = (int)((half_rows + rpc - 1) / rpc);
+  hipLaunchKernelGGL(cross_gram_kernel<T>, dim3(nchunks, (nent + 255) / 256), dim3(256), 0, s, L, L, ld, c,
+                     q, half_rows, rpc, part);
+  hipLaunchKernelGGL(cross_gram_reduce_kernel, dim3((nent + 255) / 256), dim3(256), 0, s, part, nchunks, nent, S);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- small FP64 matrices
@@ -314,7 +337,7 @@ hipError_t launch_compress_adjoint(cx_t<T>* Ybar, const cx_t<T>* X, int n, int l
     return hipErrorInvalidValue;
   const uint32_t half_rows = 1u << (n - 1);
   const int w2 = 2 * c, nent = w2 * w2;
-  const uint32_t rpc = (half_rows + kAdjChunks - 1) / kAdjChunks;
+  const uint32_t rpc = adj_rows_per_chunk(half_rows);
   const int nchunks = (int)((half_rows + rpc - 1) / rpc);
   hipLaunchKernelGGL(cross_gram_kernel<T>, dim3(nchunks, (nent + 255) / 256), dim3(256), 0, s, X, Ybar, ld,
                      c, q, half_rows, rpc, b.part);
@@ -332,6 +355,8 @@ template hipError_t launch_pauli_apply<float>(float2*, const float2*, int, int, 
                                               const uint64_t*, const double*, int, hipStream_t);
 template hipError_t launch_pauli_apply<double>(double2*, const double2*, int, int, int, const uint64_t*,
                                                const uint64_t*, const double*, int, hipStream_t);
+template hipError_t launch_gram_exact<float>(const float2*, int, int, int, int, double*, double*, hipStream_t);
+template hipError_t launch_gram_exact<double>(const double2*, int, int, int, int, double*, double*, hipStream_t);
 template hipError_t launch_compress_adjoint<float>(float2*, const float2*, int, int, int, int,
                                                    const Channel&, const double*, const AdjBufs&,
                                                    hipStream_t);

@@ -223,6 +223,11 @@ inline size_t adj_doubles(int c, int N) {
   return 2 * (e * kAdjChunks + e + 2 * (size_t)N * c + 3 * (size_t)N * N) + 2 * 2 * e;
 }
 
+// Split-view Gram S = X^H X (Fc = 2c, full Hermitian, FP64) with FP64 products and sums.
+template <class T>
+hipError_t launch_gram_exact(const cx_t<T>* L, int n, int ld, int c, int q, double* part, double* S,
+                             hipStream_t s);
+
 // Reverse of one fused channel + compression on qubit q: Ybar (the adjoint of the compressed
 // factor, state layout, c columns) is replaced in place by the adjoint of the factor before the
 // channel, given the forward factor X before the channel and the compression record.

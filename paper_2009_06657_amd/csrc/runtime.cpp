@@ -432,12 +432,17 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     h->chan_pending = false;
     return LRDM_OK;
   }
-  timed_begin(h, 1);
-  HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
-  timed_end(h, 1);
-  timed_begin(h, 2);
-  HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
-  timed_end(h, 2);
+  if (rec) {
+    // recorded compressions (reverse sweep) form S exactly from the bulk-precision factor
+    HIPCHK(h, launch_gram_exact<T>(L, h->n, h->lay.ld, c, q, adj_bufs(h).part, b.S, h->stream));
+  } else {
+    timed_begin(h, 1);
+    HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
+    timed_end(h, 1);
+    timed_begin(h, 2);
+    HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
+    timed_end(h, 2);
+  }
   timed_begin(h, 3);
   HIPCHK(h, launch_eig<T>(b.S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b,
                           W, h->stream));

@@ -7,11 +7,14 @@
 // or rows (diagonal gates, which act on any qubit because the full row index is known), and
 // writes the tile back.  Consecutive threads handle consecutive columns of one row, so every
 // global load/store is a contiguous ncols-wide row segment whatever the qubit.
+#include <utility>
+
 #include "lrdm_internal.h"
 
 namespace lrdm {
 
 typedef float f4v __attribute__((ext_vector_type(4)));   // 16-byte register unit
+constexpr int kGateThreads = 512;   // 8 waves: one register group per thread for a 64 KB tile
 
 template <class C> __device__ __forceinline__ C cmul(C a, C b) {
   C r;
@@ -36,6 +39,165 @@ __device__ __forceinline__ uint32_t insert_zero(uint32_t p, int j) {
   return ((p >> j) << (j + 1)) | (p & ((1u << j) - 1u));
 }
 
+template <class F, int... I>
+__device__ __forceinline__ void gate_static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void gate_static_for(F&& f) {
+  gate_static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// plain two-field complex for register arrays (the HIP vector types are unions, which keeps
+// arrays of them out of registers)
+template <class T> struct RC {
+  T x, y;
+};
+
+// 1q gate on register bit B of 2^R registers (all indices compile-time)
+template <int B, int R, class T>
+__device__ __forceinline__ void reg_1q(RC<T> (&x)[1 << R], const T* u) {
+  using C = RC<T>;
+  const C u00{u[0], u[1]}, u01{u[2], u[3]};
+  const C u10{u[4], u[5]}, u11{u[6], u[7]};
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (!(i & (1 << B))) {
+      const C a = x[i], b = x[i | (1 << B)];
+      x[i] = C{u00.x * a.x - u00.y * a.y + u01.x * b.x - u01.y * b.y,
+               u00.x * a.y + u00.y * a.x + u01.x * b.y + u01.y * b.x};
+      x[i | (1 << B)] = C{u10.x * a.x - u10.y * a.y + u11.x * b.x - u11.y * b.y,
+                          u10.x * a.y + u10.y * a.x + u11.x * b.y + u11.y * b.x};
+    }
+  }
+}
+
+// OR of the uniform values v[b] over the set bits b of i (i is a constant after unrolling)
+template <int R>
+__device__ __forceinline__ uint32_t pick_or(int i, const uint32_t (&v)[R]) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int b = 0; b < R; ++b)
+    if (i & (1 << b)) r |= v[b];
+  return r;
+}
+
+// Apply the pass's operations phase by phase in registers.  Phase p holds, per thread, the
+// 2^R tile elements that differ only in its register slots (one group per thread, the other
+// tile-index bits come from the thread id).  Phase 0 reads from HBM and the last phase writes to
+// HBM (lanes run along the columns of a row); consecutive phases exchange data through LDS.  In
+// phase mode op_a of a 1q operation is a register bit index (0 .. R-1); only 1q and 1- or
+// 2-qubit diagonal operations occur (passes with general 2q gates or Hamming-weight phases use
+// the per-operation sweeps instead).
+template <class T, int R>
+__device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __restrict__ L, size_t ld,
+                                            cx_t<T>* tile, int cshift, uint32_t base,
+                                            const uint32_t* slot_off) {
+  using C = RC<T>;
+  constexpr int NR = 1 << R;
+  const int E = P.k + cshift;
+  const uint32_t tid = threadIdx.x;
+  const bool live = tid < (1u << (E - R));
+  C x[NR];
+  uint32_t pos = 0, row_g = 0;
+  uint32_t sh_pos[R], sh_row[R];
+
+  auto layout = [&](int ph) {
+    uint32_t rmask = 0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      const int slot = P.ph_slots[ph][b];
+      sh_pos[b] = 1u << (cshift + slot);
+      sh_row[b] = 1u << P.local_q[slot];
+      rmask |= sh_pos[b];
+    }
+    const uint32_t tmask = ((1u << E) - 1u) & ~rmask;
+    uint32_t p = 0;
+    int src = 0;
+    for (int q = 0; q < E; ++q)
+      if ((tmask >> q) & 1u) {
+        p |= ((tid >> src) & 1u) << q;
+        ++src;
+      }
+    pos = p;
+    row_g = base | slot_off[(p >> cshift) & 255u];
+  };
+  auto apply = [&](int ph) {
+    const int o0 = P.ph_first[ph], o1 = o0 + P.ph_count[ph];
+    for (int o = o0; o < o1; ++o) {
+      const T* u = P.coef + P.op_coef[o];
+      const int ty = P.op_type[o];
+      if (ty == OP_1Q) {
+        switch (P.op_a[o]) {
+          case 0: reg_1q<0, R, T>(x, u); break;
+          case 1: reg_1q<1, R, T>(x, u); break;
+          case 2: reg_1q<2, R, T>(x, u); break;
+          default: reg_1q<3, R, T>(x, u); break;
+        }
+      } else {
+        // OP_DIAG1 / OP_DIAG2: the (at most four) phases are uniform; each element selects one
+        const int qa = P.op_a[o], qb = (ty == OP_DIAG2) ? P.op_b[o] : P.op_a[o];
+        const C d0{u[0], u[1]}, d1{u[2], u[3]};
+        const C d2{(ty == OP_DIAG2) ? u[4] : u[0], (ty == OP_DIAG2) ? u[5] : u[1]};
+        const C d3{(ty == OP_DIAG2) ? u[6] : u[2], (ty == OP_DIAG2) ? u[7] : u[3]};
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const uint32_t row = row_g | pick_or<R>(i, sh_row);
+          const bool ba = (row >> qa) & 1u, bb = (row >> qb) & 1u;
+          const T pr = bb ? (ba ? d3.x : d2.x) : (ba ? d1.x : d0.x);
+          const T pi = bb ? (ba ? d3.y : d2.y) : (ba ? d1.y : d0.y);
+          const T xr = x[i].x, xi = x[i].y;
+          x[i].x = pr * xr - pi * xi;
+          x[i].y = pr * xi + pi * xr;
+        }
+      }
+    }
+  };
+
+  layout(0);
+  if (live) {
+    const uint32_t col = pos & ((1u << cshift) - 1u);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const cx_t<T> v = L[(size_t)(row_g | pick_or<R>(i, sh_row)) * ld + col];
+      x[i] = C{v.x, v.y};
+    }
+    apply(0);
+  }
+  for (int ph = 1; ph < P.n_phases; ++ph) {
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        cx_t<T> v;
+        v.x = x[i].x;
+        v.y = x[i].y;
+        tile[pos | pick_or<R>(i, sh_pos)] = v;
+      }
+    }
+    __syncthreads();
+    layout(ph);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const cx_t<T> v = tile[pos | pick_or<R>(i, sh_pos)];
+        x[i] = C{v.x, v.y};
+      }
+      apply(ph);
+    }
+    if (ph + 1 < P.n_phases) __syncthreads();
+  }
+  if (live) {
+    const uint32_t col = pos & ((1u << cshift) - 1u);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      cx_t<T> v;
+      v.x = x[i].x;
+      v.y = x[i].y;
+      L[(size_t)(row_g | pick_or<R>(i, sh_row)) * ld + col] = v;
+    }
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __restrict__ L, int cshift,
                                                uint32_t tile_index) {
@@ -58,16 +220,22 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
     const int p = P.sorted_q[j];
     base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
   }
+  constexpr int RPH = 4;   // register slots per phase (kPhaseRegs on the host)
+  if (P.n_phases > 0) {
+    // register phases: the first reads from HBM, the last writes to HBM, LDS only in between
+    gate_phases<T, RPH>(P, L, ld, tile, cshift, base, slot_off);
+    return;
+  }
   const int elems = nc << k;
   // HBM -> LDS with 16-byte accesses, kUnroll loads in flight per thread before the LDS writes
   constexpr int CPU = 16 / (int)sizeof(C);   // complex values per 16-byte unit
-  constexpr int kUnroll = 8;
+  constexpr int kUnroll = 16;
   const int units = elems / CPU;
-  for (int u0 = 0; u0 < units; u0 += 256 * kUnroll) {
+  for (int u0 = 0; u0 < units; u0 += kGateThreads * kUnroll) {
     f4v buf[kUnroll];
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
-      const int uu = u0 + j * 256 + tid;
+      const int uu = u0 + j * kGateThreads + tid;
       if (uu < units) {
         const int e = uu * CPU;
         const uint32_t i = (uint32_t)e >> cshift;
@@ -77,7 +245,7 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
     }
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
-      const int uu = u0 + j * 256 + tid;
+      const int uu = u0 + j * kGateThreads + tid;
       if (uu < units) *reinterpret_cast<f4v*>(tile + uu * CPU) = buf[j];
     }
   }
@@ -91,7 +259,7 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
       const C u00 = cmk<C, T>(u[0], u[1]), u01 = cmk<C, T>(u[2], u[3]);
       const C u10 = cmk<C, T>(u[4], u[5]), u11 = cmk<C, T>(u[6], u[7]);
 #pragma unroll 4
-      for (int e = tid; e < (elems >> 1); e += 256) {
+      for (int e = tid; e < (elems >> 1); e += kGateThreads) {
         const int v = e & (nc - 1);
         const uint32_t i0 = insert_zero((uint32_t)e >> cshift, j), i1 = i0 | (1u << j);
         C& a0 = tile[(i0 << cshift) + v];
@@ -104,7 +272,7 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
       const int ja = P.op_a[o], jb = P.op_b[o];
       const int jlo = ja < jb ? ja : jb, jhi = ja < jb ? jb : ja;
 #pragma unroll 2
-      for (int e = tid; e < (elems >> 2); e += 256) {
+      for (int e = tid; e < (elems >> 2); e += kGateThreads) {
         const int v = e & (nc - 1);
         const uint32_t i00 = insert_zero(insert_zero((uint32_t)e >> cshift, jlo), jhi);
         const uint32_t idx[4] = {i00, i00 | (1u << ja), i00 | (1u << jb), i00 | (1u << ja) | (1u << jb)};
@@ -122,7 +290,7 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
     } else {
       // diagonal in the computational basis: phase from the full row index
       const int qa = P.op_a[o], qb = P.op_b[o];
-      for (int e = tid; e < elems; e += 256) {
+      for (int e = tid; e < elems; e += kGateThreads) {
         const uint32_t x = base | slot_off[(uint32_t)e >> cshift];
         int sel;
         if (ty == OP_DIAG1)
@@ -136,16 +304,16 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
     }
     __syncthreads();
   }
-  for (int u0 = 0; u0 < units; u0 += 256 * kUnroll) {
+  for (int u0 = 0; u0 < units; u0 += kGateThreads * kUnroll) {
     f4v buf[kUnroll];
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
-      const int uu = u0 + j * 256 + tid;
+      const int uu = u0 + j * kGateThreads + tid;
       if (uu < units) buf[j] = *reinterpret_cast<const f4v*>(tile + uu * CPU);
     }
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j) {
-      const int uu = u0 + j * 256 + tid;
+      const int uu = u0 + j * kGateThreads + tid;
       if (uu < units) {
         const int e = uu * CPU;
         const uint32_t i = (uint32_t)e >> cshift;
@@ -157,24 +325,26 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
+__global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
                                                         int cshift) {
   gate_pass_body<T>(P, L, cshift, blockIdx.x);
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(kGateThreads) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {
   const int j = find_job(jobs, njobs, blockIdx.x);
   gate_pass_body<T>(jobs[j].p, jobs[j].L, jobs[j].cshift, blockIdx.x - jobs[j].block0);
 }
 
-size_t gate_pass_shm(int ncols, int k, size_t csize) { return ((size_t)ncols << k) * csize; }
+size_t gate_pass_shm(int ncols, int k, size_t csize, int n_phases) {
+  return (n_phases == 1) ? 0 : ((size_t)ncols << k) * csize;
+}
 
 template <class T>
 hipError_t launch_gate_pass_batched(const GateJob<T>* jobs, int njobs, uint32_t blocks, size_t shm,
                                     hipStream_t s) {
   if (njobs < 1 || blocks < 1 || shm > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gate_pass_batched<T>, dim3(blocks), dim3(256), shm, s, jobs, njobs);
+  hipLaunchKernelGGL(gate_pass_batched<T>, dim3(blocks), dim3(kGateThreads), shm, s, jobs, njobs);
   return hipGetLastError();
 }
 
@@ -184,10 +354,10 @@ hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
     return hipErrorInvalidValue;
   int cshift = 0;
   while ((1 << cshift) < p.ncols) ++cshift;
-  const size_t shm = gate_pass_shm(p.ncols, p.k, sizeof(cx_t<T>));
+  const size_t shm = gate_pass_shm(p.ncols, p.k, sizeof(cx_t<T>), p.n_phases);
   if (shm > 65536) return hipErrorInvalidValue;
   const uint32_t tiles = 1u << (p.n - p.k);
-  hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(256), shm, s, p, L, cshift);
+  hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(kGateThreads), shm, s, p, L, cshift);
   return hipGetLastError();
 }
 

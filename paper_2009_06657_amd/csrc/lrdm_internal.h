@@ -11,6 +11,7 @@ namespace lrdm {
 constexpr int kMaxEig = 128;      // largest Gram order the single-work-group eigensolver takes
 constexpr int kGateMaxOps = 40;   // operations per fused gate pass (kernel-argument budget)
 constexpr int kGateMaxCoef = 288; // real coefficients per fused gate pass
+constexpr int kGateMaxPhases = 16; // register phases per fused gate pass
 
 template <class T> struct Cx;
 template <> struct Cx<float> { using type = float2; };
@@ -22,14 +23,22 @@ enum GateOpType : int { OP_1Q = 0, OP_2Q = 1, OP_DIAG1 = 2, OP_DIAG2 = 3, OP_WEI
 // One fused sweep over L: every row tile holds the 2^k rows that differ only in the k "local"
 // qubits; general 1q/2q gates act on local qubits, diagonal gates on any qubit (the full row
 // index is known).  Operations are applied in list order.
+// With n_phases > 0 the operations are applied in register phases: phase p holds the tile rows
+// that differ in the local slots ph_slots[p][0 .. 4) in
+// registers and applies operations [ph_first[p], ph_first[p] + ph_count[p]) there; every
+// non-diagonal operation of a phase acts on its slots (op_a is then the register bit).
+// n_phases = 0: one LDS sweep per operation.
 template <class T> struct GatePass {
-  int n, k, ld, ncols, n_ops;
+  int n, k, ld, ncols, n_ops, n_phases;
   int local_q[8];      // local bit j <-> qubit local_q[j]
   int sorted_q[8];     // the same qubits in ascending order (row-index deposit)
   int op_type[kGateMaxOps];
   int op_a[kGateMaxOps];
   int op_b[kGateMaxOps];
   int op_coef[kGateMaxOps];
+  unsigned char ph_first[kGateMaxPhases];
+  unsigned char ph_count[kGateMaxPhases];
+  unsigned char ph_slots[kGateMaxPhases][5];
   T coef[kGateMaxCoef];
 };
 
@@ -133,7 +142,7 @@ hipError_t launch_stamp(uint64_t* slot, hipStream_t s);
 // Launch-shape helpers shared by the single and batched paths
 int gram_seg_shift(int c);                       // log2(2c), -1 if 2c is not a power of two
 uint32_t gram_rows_per_block(int n, int nsplit, int nblocks);
-size_t gate_pass_shm(int ncols, int k, size_t csize);
+size_t gate_pass_shm(int ncols, int k, size_t csize, int n_phases);
 
 // ---------------------------------------------------------------- launchers (k_*.hip)
 template <class T>

@@ -226,6 +226,63 @@ int local_budget(int n, int ncols, size_t csize) {
   return k;
 }
 
+// Register phases of a fused pass (see GatePass): consecutive operations share a phase while
+// the 1q operations among them act on at most kPhaseRegs distinct local slots; diagonal
+// operations join any phase.  Passes with other operation types keep the per-operation sweeps.
+constexpr int kPhaseRegs = 4;
+
+template <class T>
+void build_phases(GatePass<T>& p) {
+  p.n_phases = 0;
+  if (p.k < kPhaseRegs) return;
+  for (int o = 0; o < p.n_ops; ++o)
+    if (p.op_type[o] != OP_1Q && p.op_type[o] != OP_DIAG1 && p.op_type[o] != OP_DIAG2) return;
+  int nph = 0;
+  int first[kGateMaxOps], count[kGateMaxOps], slots[kGateMaxOps][kPhaseRegs], nsl[kGateMaxOps];
+  int regbit[kGateMaxOps];
+  auto open_phase = [&](int o) {
+    first[nph] = o;
+    count[nph] = 0;
+    nsl[nph] = 0;
+    ++nph;
+  };
+  open_phase(0);
+  for (int o = 0; o < p.n_ops; ++o) {
+    int ph = nph - 1;
+    if (p.op_type[o] == OP_1Q) {
+      const int slot = p.op_a[o];
+      int b = -1;
+      for (int i = 0; i < nsl[ph]; ++i)
+        if (slots[ph][i] == slot) b = i;
+      if (b < 0 && nsl[ph] == kPhaseRegs) {
+        open_phase(o);
+        ph = nph - 1;
+      }
+      if (b < 0) {
+        b = nsl[ph];
+        slots[ph][nsl[ph]++] = slot;
+      }
+      regbit[o] = b;
+    }
+    ++count[ph];
+  }
+  if (nph > kGateMaxPhases) return;
+  for (int ph = 0; ph < nph; ++ph) {
+    // fill the register slots with unused local slots
+    for (int j = 0; j < p.k && nsl[ph] < kPhaseRegs; ++j) {
+      bool used = false;
+      for (int i = 0; i < nsl[ph]; ++i) used |= (slots[ph][i] == j);
+      if (!used) slots[ph][nsl[ph]++] = j;
+    }
+    p.ph_first[ph] = (unsigned char)first[ph];
+    p.ph_count[ph] = (unsigned char)count[ph];
+    for (int i = 0; i < kPhaseRegs; ++i) p.ph_slots[ph][i] = (unsigned char)slots[ph][i];
+  }
+  for (int o = 0; o < p.n_ops; ++o)
+    if (p.op_type[o] == OP_1Q) p.op_a[o] = regbit[o];
+  p.n_phases = nph;
+}
+
 template <class T>
 lrdm_status flush_gates_t(lrdm_t h) {
   const int kloc_max = local_budget(h->n, h->ncols, sizeof(cx_t<T>));
@@ -273,6 +330,7 @@ lrdm_status flush_gates_t(lrdm_t h) {
     for (int j = 0; j < nloc; ++j) sorted[j] = p.local_q[j];
     std::sort(sorted, sorted + nloc);
     for (int j = 0; j < nloc; ++j) p.sorted_q[j] = sorted[j];
+    build_phases(p);
     if (h->rec) {
       if constexpr (sizeof(T) == 4) {
         GateJob<float> j;
@@ -282,7 +340,7 @@ lrdm_status flush_gates_t(lrdm_t h) {
         while ((1 << j.cshift) < p.ncols) ++j.cshift;
         j.block0 = 0;
         j.nblocks = 1u << (p.n - p.k);
-        h->rec->items.push_back({REC_GATE, 0, 0, j.nblocks, gate_pass_shm(p.ncols, p.k, sizeof(float2)),
+        h->rec->items.push_back({REC_GATE, 0, 0, j.nblocks, gate_pass_shm(p.ncols, p.k, sizeof(float2), p.n_phases),
                                  h->rec->gates.size()});
         h->rec->gates.push_back(j);
       }

@@ -217,9 +217,11 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     if (!trivial) {
       const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
       beta = (alpha.x >= 0) ? -nrm : nrm;
-      tau = zmk((beta - alpha.x) / beta, -alpha.y / beta);
-      const double dr = alpha.x - beta, di = alpha.y, den = dr * dr + di * di;
-      sc = zmk(dr / den, -di / den);
+      const double ib = 1.0 / beta;
+      tau = zmk((beta - alpha.x) * ib, -alpha.y * ib);
+      const double dr = alpha.x - beta, di = alpha.y;
+      const double iden = 1.0 / (dr * dr + di * di);
+      sc = zmk(dr * iden, -di * iden);
     }
     z64 (&vloc)[BC] = cv;   // v overwrites the column entries it is built from
 #pragma unroll
@@ -241,31 +243,79 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
         tau_s[2 * j + 1] = tau.y;
       }
     }
-    // p = tau A v for this thread's rows, reduced over the half-wave; row blocks that lie
-    // entirely in the eliminated part (rows <= j) only publish zeros
+    // s = A v for this thread's rows, reduced over the half-wave (pbuf holds s; p = tau s);
+    // row blocks that lie entirely in the eliminated part (rows <= j) only publish zeros
     const bool live = BR * R + BR - 1 > j;   // uniform over the half-wave
     if (live) {
+      if constexpr (BR == 8) {
+        // 16 values (8 rows x re/im) over 32 lanes by a transposing reduction: each stage
+        // halves the values a lane keeps and swaps the other half with its partner (lane ^ 16,
+        // then row_mirror, row_half_mirror and quad xor 2 pair lanes that differ in bits 3, 2,
+        // 1), and a last exchange adds the pair differing in bit 0: lane Cc ends with the
+        // half-wave total of value Cc >> 1, i.e. row Cc >> 2, component (Cc >> 1) & 1.
+        double v16[16];
 #pragma unroll
-      for (int a = 0; a < BR; ++a) {
-        z64 s = zmk(0, 0);
+        for (int a = 0; a < BR; ++a) {
+          z64 s = zmk(0, 0);
 #pragma unroll
-        for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
-        s.x = gsum<32>(s.x);
-        s.y = gsum<32>(s.y);
-        const int i = BR * R + a;
-        if (Cc == 0) pbuf[i] = (i > j && i < N) ? zmul(tau, s) : zmk(0, 0);
+          for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+          v16[2 * a] = s.x;
+          v16[2 * a + 1] = s.y;
+        }
+        const bool f4 = (Cc >> 4) & 1, f3 = (Cc >> 3) & 1, f2 = (Cc >> 2) & 1, f1 = (Cc >> 1) & 1;
+        double v8[8], v4[4], v2[2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double snd = f4 ? v16[q] : v16[q + 8];
+          const double kp = f4 ? v16[q + 8] : v16[q];
+          v8[q] = kp + __shfl_xor(snd, 16, 64);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double snd = f3 ? v8[q] : v8[q + 4];
+          const double kp = f3 ? v8[q + 4] : v8[q];
+          v4[q] = kp + dpp_mov<0x140>(snd);   // row_mirror
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const double snd = f2 ? v4[q] : v4[q + 2];
+          const double kp = f2 ? v4[q + 2] : v4[q];
+          v2[q] = kp + dpp_mov<0x141>(snd);   // row_half_mirror
+        }
+        double v1;
+        {
+          const double snd = f1 ? v2[0] : v2[1];
+          const double kp = f1 ? v2[1] : v2[0];
+          v1 = kp + dpp_mov<0x4E>(snd);       // quad_perm xor 2
+        }
+        v1 += dpp_mov<0xB1>(v1);              // quad_perm xor 1
+        if (!(Cc & 1)) {
+          const int i = BR * R + (Cc >> 2);
+          reinterpret_cast<double*>(pbuf)[2 * i + ((Cc >> 1) & 1)] = (i > j && i < N) ? v1 : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < BR; ++a) {
+          z64 s = zmk(0, 0);
+#pragma unroll
+          for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+          s.x = gsum<32>(s.x);
+          s.y = gsum<32>(s.y);
+          const int i = BR * R + a;
+          if (Cc == 0) pbuf[i] = (i > j && i < N) ? s : zmk(0, 0);
+        }
       }
     } else if (Cc == 0) {
 #pragma unroll
       for (int a = 0; a < BR; ++a) pbuf[BR * R + a] = zmk(0, 0);
     }
     __syncthreads();
-    // alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
+    // p = tau s; alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
     z64 dt = zmk(0, 0);
     z64 pcol[BC];
 #pragma unroll
     for (int b = 0; b < BC; ++b) {
-      pcol[b] = pbuf[BC * Cc + b];
+      pcol[b] = zmul(tau, pbuf[BC * Cc + b]);
       dt = zadd(dt, zcmul(pcol[b], vloc[b]));
     }
     dt.x = gsum<32>(dt.x);
@@ -275,7 +325,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
 #pragma unroll
     for (int a = 0; a < BR; ++a) {
       const z64 vr = vbuf[BR * R + a];
-      const z64 wr = zadd(pbuf[BR * R + a], zmul(alpha2, vr));
+      const z64 wr = zadd(zmul(tau, pbuf[BR * R + a]), zmul(alpha2, vr));
 #pragma unroll
       for (int b = 0; b < BC; ++b) {
         const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
@@ -573,6 +623,10 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
       o.x = (T)(acc.x * scl);
       o.y = (T)(acc.y * scl);
       W[e] = o;
+      if (B.W64) {
+        B.W64[2 * e] = acc.x * scl;
+        B.W64[2 * e + 1] = acc.y * scl;
+      }
     }
   } else {
     for (int e = tid; e < N * c_out; e += NTH) {

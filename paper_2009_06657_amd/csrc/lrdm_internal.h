@@ -69,6 +69,7 @@ struct EigBufs {
   double* lam;      // kept-candidate eigenvalues, descending
   DevInfo* info;
   double* rec;      // nullable: compression record for the reverse sweep (every eigenpair)
+  double* W64;      // nullable: W in FP64 as well (split view), for chained compressions
 };
 
 // Compression record (FP64), written by the eigensolver when EigBufs::rec is set:
@@ -183,6 +184,15 @@ template <class T>
 hipError_t launch_pauli(const cx_t<T>* bra, const cx_t<T>* ket, int n, int ld, int ncols,
                         const uint64_t* xm, const uint64_t* zm, int n_terms, double* partials,
                         int nblocks, double* out, int complex_out, hipStream_t s);
+
+// ---------------------------------------------------------------- chained compressions (k_chain.hip)
+// Two compressions on the same qubit with nothing in between share the split view: the second
+// acts on X W_1, so its Gram matrix is W_1^H S W_1 and both projections compose into X (W_1 W_2).
+// S <- W^H S W (Hermitian part), n x n complex FP64, tmp: n x n scratch.
+hipError_t launch_chain_gram(double* S, const double* W, double* tmp, int n, hipStream_t s);
+// Wp <- Wp Wn (FP64) and Wt <- Wp in the bulk precision; tmp: n x n scratch.
+template <class T>
+hipError_t launch_chain_compose(double* Wp, const double* Wn, double* tmp, cx_t<T>* Wt, int n, hipStream_t s);
 
 // ---------------------------------------------------------------- full-rank comparator (k_fdm.hip)
 constexpr int kFdmLowBits = 5;     // index bits 0..4 are local in every pass (256-byte runs)

@@ -40,6 +40,7 @@ struct Layout {
   size_t off_info, off_part, off_S, off_P, off_lam, off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
   bool adjoint;        // reverse sweep available (fused form, m_max * r_pad <= 64)
   size_t off_adj, rec_bytes;
+  size_t off_chain;    // fused form: W of the pending projection, the next W (FP64) and scratch
 };
 
 bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
@@ -85,6 +86,7 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   const int N_rec = m_max * L.r_pad;
   L.adjoint = !plain && N_rec <= kRecMaxN;
   L.off_adj = L.adjoint ? take(adj_doubles(L.r_pad, N_rec) * 8) : 0;
+  L.off_chain = plain ? 0 : take((size_t)3 * (2 * L.r_pad) * (2 * L.r_pad) * 16);
   L.rec_bytes = L.adjoint ? align_up(record_doubles(N_rec) * 8) : 0;
   L.total = o;
   return true;
@@ -147,6 +149,11 @@ struct lrdm_ctx {
   std::vector<uint64_t> term_stage;
   // batch recording (non-null between lrdm_batch_begin and lrdm_batch_end)
   Recorder* rec = nullptr;
+  // fused form: the projection of the last compression is deferred while only channels on the
+  // same qubit follow (chained compressions); pend_q is that qubit
+  bool proj_pending = false;
+  int pend_q = -1;
+  bool last_w_next = false;   // the last compression's own W is in the "next" buffer (chained)
 
   template <class P> P* ws(size_t off) { return reinterpret_cast<P*>(work + off); }
 };
@@ -354,8 +361,12 @@ lrdm_status flush_gates_t(lrdm_t h) {
   return LRDM_OK;
 }
 
+lrdm_status settle(lrdm_t h);
+
 lrdm_status flush_gates(lrdm_t h) {
   if (h->gates.empty()) return LRDM_OK;
+  lrdm_status st = settle(h);   // a deferred projection precedes the queued gates
+  if (st != LRDM_OK) return st;
   return h->dt == LRDM_C64 ? flush_gates_t<float>(h) : flush_gates_t<double>(h);
 }
 
@@ -370,6 +381,8 @@ lrdm_status ready_for_output(lrdm_t h) {
   st = not_recording(h);
   if (st != LRDM_OK) return st;
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  st = settle(h);
+  if (st != LRDM_OK) return st;
   return flush_gates(h);
 }
 
@@ -380,6 +393,7 @@ EigBufs eig_bufs(lrdm_t h) {
   b.lam = h->ws<double>(h->lay.off_lam);
   b.info = h->ws<DevInfo>(h->lay.off_info);
   b.rec = nullptr;
+  b.W64 = nullptr;
   return b;
 }
 
@@ -398,6 +412,25 @@ AdjBufs adj_bufs(lrdm_t h) {
   b.P = p; p += 2 * e;
   b.Q = p;
   return b;
+}
+
+// Materialise the factor: issue the deferred projection of the last (possibly chained)
+// compression.
+template <class T>
+lrdm_status settle_t(lrdm_t h) {
+  if (!h->proj_pending) return LRDM_OK;
+  h->proj_pending = false;
+  const int c = h->lay.r_pad;
+  timed_begin(h, 4);
+  HIPCHK(h, launch_project<T>(static_cast<cx_t<T>*>(h->state), h->n, h->lay.ld, c, 2, h->pend_q, c,
+                              h->ws<cx_t<T>>(h->lay.off_W), h->stream));
+  timed_end(h, 4);
+  return LRDM_OK;
+}
+
+lrdm_status settle(lrdm_t h) {
+  if (!h->proj_pending) return LRDM_OK;
+  return h->dt == LRDM_C64 ? settle_t<float>(h) : settle_t<double>(h);
 }
 
 template <class T>
@@ -490,9 +523,25 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     h->chan_pending = false;
     return LRDM_OK;
   }
+  // chained compression: the previous one (same qubit) left its projection pending, so S of
+  // the factor it would produce is W^H S W and the two projections compose
+  const bool chain = !rec && nsplit == 2 && h->proj_pending && h->pend_q == q;
+  if (!chain) {
+    lrdm_status st = settle_t<T>(h);
+    if (st != LRDM_OK) return st;
+  }
+  double* Wp64 = h->ws<double>(h->lay.off_chain);          // W of the pending projection
+  double* Wn64 = Wp64 + 2 * (size_t)Fc * Fc;                // W of this compression
+  double* tmp64 = Wn64 + 2 * (size_t)Fc * Fc;
   if (rec) {
     // recorded compressions (reverse sweep) form S exactly from the bulk-precision factor
     HIPCHK(h, launch_gram_exact<T>(L, h->n, h->lay.ld, c, q, adj_bufs(h).part, b.S, h->stream));
+  } else if (chain) {
+    // S holds the Gram matrix of the split view before the previous compression; transform it
+    // by that compression's own W (not the composed product)
+    timed_begin(h, 1);
+    HIPCHK(h, launch_chain_gram(b.S, h->last_w_next ? Wn64 : Wp64, tmp64, Fc, h->stream));
+    timed_end(h, 1);
   } else {
     timed_begin(h, 1);
     HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
@@ -501,13 +550,22 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
     timed_end(h, 2);
   }
+  const bool defer = !rec && nsplit == 2;   // fused compressions defer their projection
+  if (defer) b.W64 = chain ? Wn64 : Wp64;
   timed_begin(h, 3);
   HIPCHK(h, launch_eig<T>(b.S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b,
                           W, h->stream));
   timed_end(h, 3);
-  timed_begin(h, 4);
-  HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W, h->stream));
-  timed_end(h, 4);
+  if (chain) HIPCHK(h, launch_chain_compose<T>(Wp64, Wn64, tmp64, W, Fc, h->stream));
+  if (defer) {
+    h->proj_pending = true;
+    h->pend_q = q;
+    h->last_w_next = chain;
+  } else {
+    timed_begin(h, 4);
+    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W, h->stream));
+    timed_end(h, 4);
+  }
   h->ncols = c_out;
   const int grown = (nsplit == 2) ? h->c_bound * ch.m : h->c_bound;
   h->c_bound = std::min(std::min(grown, r_target), N);
@@ -528,6 +586,7 @@ lrdm_status reset_t(lrdm_t h) {
     j.nblocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 1024));
     h->rec->items.push_back({REC_RESET, 0, 0, j.nblocks, 0, h->rec->resets.size()});
     h->rec->resets.push_back(j);
+    h->proj_pending = false;
     h->ncols = h->lay.r_pad;
     h->c_bound = 1;
     h->gates.clear();
@@ -537,6 +596,7 @@ lrdm_status reset_t(lrdm_t h) {
   HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
   HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
   HIPCHK(h, launch_set_e0<T>(static_cast<cx_t<T>*>(h->state), h->stream));
+  h->proj_pending = false;
   h->ncols = h->lay.r_pad;
   h->c_bound = 1;
   h->gates.clear();
@@ -947,6 +1007,7 @@ lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank) {
   if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
   h->gates.clear();
+  h->proj_pending = false;
   const size_t cs = (h->dt == LRDM_C64) ? 8 : 16;
   const size_t rows = 1ull << h->n;
   HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
@@ -963,6 +1024,8 @@ lrdm_status lrdm_synchronize(lrdm_t h) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
   st = not_recording(h);
+  if (st != LRDM_OK) return st;
+  st = settle(h);
   if (st != LRDM_OK) return st;
   st = flush_gates(h);
   if (st != LRDM_OK) return st;
@@ -1032,6 +1095,7 @@ lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank) {
   if (rank < 1 || rank > h->lay.r_pad) return fail(h, LRDM_E_ARG, "rank must be in [1, r_pad]");
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
   h->gates.clear();
+  h->proj_pending = false;
   HIPCHK(h, hipMemcpyAsync(h->state, src_dev, h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
   h->ncols = h->lay.r_pad;
   h->c_bound = rank;
@@ -1054,6 +1118,7 @@ lrdm_status lrdm_apply_pauli_sum(lrdm_t dst, lrdm_t src, int n_terms, const uint
   if (st != LRDM_OK) return st;
   if (dst->chan_pending) return fail(dst, LRDM_E_STATE, "a Kraus channel is pending on the destination");
   dst->gates.clear();
+  dst->proj_pending = false;
   st = order_streams(src, dst);
   if (st != LRDM_OK) return st;
   std::vector<uint64_t> stage(3 * (size_t)n_terms);
@@ -1102,6 +1167,8 @@ lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec
   if (m < 1 || m > bar->m_max) return fail(bar, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
   if (!kraus_complete(m, e)) return fail(bar, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
   if (bar->chan_pending) return fail(bar, LRDM_E_STATE, "a Kraus channel is pending on the adjoint handle");
+  st = settle(bar);
+  if (st != LRDM_OK) return st;
   st = flush_gates(bar);
   if (st != LRDM_OK) return st;
   const Channel ch = make_channel(m, e);
@@ -1379,7 +1446,9 @@ lrdm_status lrdm_batch_begin(lrdm_batch_t b) {
   }
   for (size_t i = 0; i < b->hs.size(); ++i) {
     lrdm_t h = b->hs[i];
-    lrdm_status st = flush_gates(h);
+    lrdm_status st = settle(h);
+    if (st != LRDM_OK) return st;
+    st = flush_gates(h);
     if (st != LRDM_OK) return st;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     b->recs[i] = Recorder();

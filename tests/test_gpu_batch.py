@@ -1,6 +1,8 @@
 """Batched serving (many handles of uneven n and r in one captured hipGraph): every instance
-equals its unbatched run bit for bit (same kernels, tiles and reduction order), and matches the
-FP64 oracle within the complex64 tolerance (1e-5 on <Z_i>)."""
+equals its unbatched run bit for bit when both issue the same launches (same kernels, tiles and
+reduction order), within 1e-6 on Prob and <Z_i> when the unbatched run chains consecutive
+compressions on one qubit (the batch issues every compression separately), and matches the FP64
+oracle within the complex64 tolerance (1e-5 on <Z_i>)."""
 import sys
 
 import numpy as np
@@ -46,13 +48,26 @@ def _mix(count, seed, n_range=(5, 10), depth_range=(2, 4)):
     return progs
 
 
+def _chains(p):
+    """True when the program has two channels on one qubit with nothing but a compression between."""
+    prev = None
+    for op in p.ops:
+        if isinstance(op, C.Kraus):
+            if prev is not None and prev == op.qubit:
+                return True
+            prev = op.qubit
+        elif not isinstance(op, C.Compress):
+            prev = None
+    return False
+
+
 def _run_unbatched(lr, progs):
     out = []
     for p in progs:
         dm = lr.LowRankDM(p.n, p.r, lr.C64, p.m_max)
         lr.run_program(dm, p)
         z, _, tr = dm.expect_z()
-        out.append((dm.get_L(), z, tr))
+        out.append((dm.get_L(), z, tr, dm.probabilities().cpu().numpy()))
         dm.close()
     return out
 
@@ -72,7 +87,7 @@ def _run_batched(lr, progs, replays=1):
         for dm in hs:
             dm.synchronize()
             z, _, tr = dm.expect_z()
-            res.append((dm.get_L(), z, tr))
+            res.append((dm.get_L(), z, tr, dm.probabilities().cpu().numpy()))
         results.append((res, done, total))
     steps, launches = b.info()
     b.close()
@@ -85,22 +100,32 @@ def test_batch_equals_unbatched_bitwise(lr):
     ref = _run_unbatched(lr, progs)
     results, steps, launches = _run_batched(lr, progs, replays=2)
     _say(f"  steps {steps} launches {launches}")
+    nchain = 0
     for rep, (res, done, total) in enumerate(results):
-        for i, ((La, za, ta), (Lb, zb, tb)) in enumerate(zip(ref, res)):
-            assert np.array_equal(La, Lb), f"instance {i} differs (replay {rep})"
-            assert np.array_equal(za, zb)
+        for i, ((La, za, ta, Pa), (Lb, zb, tb, Pb)) in enumerate(zip(ref, res)):
+            if _chains(progs[i]):
+                nchain += 1
+                assert np.max(np.abs(Pa - Pb)) <= 1e-6, f"instance {i} differs (replay {rep})"
+                assert np.max(np.abs(za - zb)) <= 1e-6
+            else:
+                assert np.array_equal(La, Lb), f"instance {i} differs (replay {rep})"
+                assert np.array_equal(za, zb)
         assert total > 0 and np.all(done > 0) and np.all(done <= total + 1e-9)
         # an instance with more compressions never finishes before one with fewer
         ncomp = np.array([p.n_compress() for p in progs])
         order = np.argsort(ncomp, kind="stable")
         assert np.all(np.diff(done[order]) >= -1e-9)
+    assert 0 < nchain < 2 * len(progs)   # both kinds of instance occur
+    # two replays of the graph are identical
+    for (La, za, _, _), (Lb, zb, _, _) in zip(results[0][0], results[1][0]):
+        assert np.array_equal(La, Lb) and np.array_equal(za, zb)
 
 
 def test_batch_matches_oracle(lr):
     progs = _mix(6, 11, n_range=(5, 7), depth_range=(2, 3))
     results, _, _ = _run_batched(lr, progs)
     res = results[0][0]
-    for p, (_, z, tr) in zip(progs, res):
+    for p, (_, z, tr, _) in zip(progs, res):
         L = oracle.run_lret(p)
         P = oracle.probabilities(L)
         zr = oracle.expect_z(P, p.n)

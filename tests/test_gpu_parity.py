@@ -171,6 +171,29 @@ def test_cfg3_small(lr, plain):
     dm.close()
 
 
+@pytest.mark.parametrize("chans", [[("ad", 0.05), ("deph", 0.04)], [("ad", 0.03), ("dep", 0.02), ("deph", 0.01)]])
+def test_chained_compressions_complex128(lr, chans):
+    """Consecutive channels on one qubit reuse the split view (Gram W^H S W, composed projection):
+    complex128 agrees with the oracle's step-by-step run to 1e-10, and an output between the two
+    channels (which materialises the intermediate factor) changes nothing."""
+    prog = C.brickwork_program(7, 2, 16, chans, seed=91, dtype="c128")
+    _say(f"[chain c128] chans={chans}")
+    dm = run_gpu(lr, prog)
+    P = dm.probabilities().cpu().numpy()
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    assert np.max(np.abs(P - Pref)) < 1e-10
+    # the same program with a sync after every compression (no chaining)
+    dm2 = lr.LowRankDM(prog.n, prog.r, lr.C128, prog.m_max)
+    for op in prog.ops:
+        lr.run_program(dm2, C.Program(prog.n, [op], prog.r, prog.dtype, prog.m_max, "one", 0))
+        if isinstance(op, C.Compress):
+            dm2.synchronize()
+    P2 = dm2.probabilities().cpu().numpy()
+    assert np.max(np.abs(P2 - Pref)) < 1e-10
+    dm.close()
+    dm2.close()
+
+
 @pytest.mark.parametrize("n,r,chans", [(10, 64, [("ad", 0.002), ("deph", 0.001)]),
                                        (9, 32, [("dep", 0.003)])])
 def test_largest_gram_order(lr, n, r, chans):

@@ -50,15 +50,43 @@ __device__ __forceinline__ double dpp_mov(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+// v + v(lane ^ 16) and v + v(lane ^ 32) by the lane-swap moves (permlane16/32_swap): the two
+// results of a swap of v with itself are v and its partner, in an order that depends on the lane.
+__device__ __forceinline__ double xor16_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
 template <int W>
 __device__ __forceinline__ double gsum(double v) {
   if constexpr (W >= 2) v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
   if constexpr (W >= 4) v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
   if constexpr (W >= 8) v += dpp_mov<0x141>(v);   // row_half_mirror
   if constexpr (W >= 16) v += dpp_mov<0x140>(v);  // row_mirror
-  if constexpr (W >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (W >= 64) v += __shfl_xor(v, 32, 64);
+  if constexpr (W >= 32) v = xor16_sum(v);
+  if constexpr (W >= 64) v = xor32_sum(v);
   return v;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sums of a and of b over the 64 lanes of a wave, returned in every lane.  Transposing: the
+// 32-lane swap leaves lanes 0-31 with pair sums of a and lanes 32-63 with pair sums of b, the
+// half-waves reduce those by DPP and the 16-lane swap, and the totals are read from lanes 0 and 32.
+__device__ __forceinline__ void wsum64x2(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+  double v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  v = gsum<32>(v);
+  a = read_lane(v, 0);
+  b = read_lane(v, 32);
 }
 
 __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
@@ -80,6 +108,13 @@ __device__ __forceinline__ double fdiv(double f, double q) {
   double r = __builtin_amdgcn_rcp(q);
   r = fma(r, fma(-q, r, 1.0), r);
   return f * r;
+}
+
+// 1 / q through the hardware reciprocal refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return fma(r, fma(-q, r, 1.0), r);
 }
 
 // number of eigenvalues of T (scaled, diagonal d, squared off-diagonal e2) below x
@@ -120,11 +155,201 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <class T, int BR, int BC>
+// LDS operands of the tridiagonalisation steps
+struct TriSmem {
+  z64* col_buf;   // column jl of the trailing matrix being reduced (local row index)
+  z64* vbuf;      // reflector v (local index)
+  z64* pbuf;      // s = A v (local index)
+  double* d_s;    // diagonal of T (global index)
+  double* e_s;    // off-diagonal of T (global index)
+  double* tau_s;  // reflector scalars (global index, interleaved)
+  z64* Rf;        // packed reflector entries i >= j + 2 (global packing)
+};
+
+// Transposing exchange across lane ^ 16: lanes with bit 4 clear get a + a(lane ^ 16), lanes
+// with bit 4 set get b + b(lane ^ 16) (one 16-lane swap of a with b).
+__device__ __forceinline__ double xor16_keep(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Half-wave sums of NV (8 or 16) values by a transposing reduction: each stage halves the
+// values a lane keeps and adds its partner's copy of them (lane ^ 16 by the lane swap, then
+// row_mirror, row_half_mirror and quad xor 2 pair lanes differing in bits 3, 2, 1); the lanes
+// left with one value add the remaining partners.  Lane Cc ends with the total of value
+// Cc >> (5 - log2 NV).
+template <int NV>
+__device__ __forceinline__ double tsum_halfwave(double (&v)[NV], int Cc) {
+  static_assert(NV == 8 || NV == 16, "8 or 16 values");
+  constexpr int H = NV / 2;
+  double w8[H];
+#pragma unroll
+  for (int q = 0; q < H; ++q) w8[q] = xor16_keep(v[q], v[q + H]);
+  const bool f3 = (Cc >> 3) & 1, f2 = (Cc >> 2) & 1, f1 = (Cc >> 1) & 1;
+  double w4[H / 2];
+#pragma unroll
+  for (int q = 0; q < H / 2; ++q) {
+    const double snd = f3 ? w8[q] : w8[q + H / 2];
+    const double kp = f3 ? w8[q + H / 2] : w8[q];
+    w4[q] = kp + dpp_mov<0x140>(snd);   // row_mirror
+  }
+  double w2[H / 4 > 0 ? H / 4 : 1];
+  if constexpr (H / 4 >= 1) {
+#pragma unroll
+    for (int q = 0; q < H / 4; ++q) {
+      const double snd = f2 ? w4[q] : w4[q + H / 4];
+      const double kp = f2 ? w4[q + H / 4] : w4[q];
+      w2[q] = kp + dpp_mov<0x141>(snd);   // row_half_mirror
+    }
+  }
+  double r;
+  if constexpr (NV == 16) {
+    const double snd = f1 ? w2[0] : w2[1];
+    const double kp = f1 ? w2[1] : w2[0];
+    r = kp + dpp_mov<0x4E>(snd);   // quad_perm xor 2
+  } else {
+    r = w2[0];
+    r += dpp_mov<0x4E>(r);
+  }
+  r += dpp_mov<0xB1>(r);   // quad_perm xor 1
+  return r;
+}
+
+// One Householder step on the register-resident trailing matrix A: layout <BR, BC> (thread
+// (R, Cc) holds rows BR R .. BR R + BR - 1 and columns BC Cc .. BC Cc + BC - 1), local order Nl,
+// local step jl (jl % BC == BB), global step j0 + jl.  Forms the reflector from column jl
+// (every half-wave redundantly; lane Cc owns entries BC Cc + b), s = A v reduced over each
+// half-wave, the rank-2 update A -= v w^H + w v^H, and broadcasts column jl + 1.
+template <int BR, int BC, int BB>
+__device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], const int jl, const int Nl, const int j0, const int N,
+                                         const TriSmem& M) {
+  const int tid = threadIdx.x, R = tid >> 5, Cc = tid & 31;
+  const int j = j0 + jl;
+  const z64 alpha = M.col_buf[jl + 1];
+  z64 cv[BC];
+  double xn2 = 0;
+#pragma unroll
+  for (int b = 0; b < BC; ++b) {
+    const int i = BC * Cc + b;
+    cv[b] = M.col_buf[i];
+    if (i > jl + 1 && i < Nl) xn2 += cv[b].x * cv[b].x + cv[b].y * cv[b].y;
+  }
+  xn2 = gsum<32>(xn2);
+  double beta = alpha.x;
+  z64 tau = zmk(0, 0), sc = zmk(0, 0);
+  const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
+  if (!trivial) {
+    // 1 / ||x|| from the hardware reciprocal square root refined by two Newton steps, and
+    // 1 / |alpha - beta|^2 by the refined reciprocal (short dependency chains; a few ulp)
+    const double n2 = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2));
+    double rn = __builtin_amdgcn_rsq(n2);
+    rn = rn * fma(-0.5 * n2, rn * rn, 1.5);
+    rn = rn * fma(-0.5 * n2, rn * rn, 1.5);
+    const double nrm = n2 * rn;
+    const bool pos = alpha.x >= 0;
+    beta = pos ? -nrm : nrm;
+    const double ib = pos ? -rn : rn;
+    tau = zmk((beta - alpha.x) * ib, -alpha.y * ib);
+    const double dr = alpha.x - beta, di = alpha.y;
+    const double iden = rcp_nr(fma(dr, dr, di * di));
+    sc = zmk(dr * iden, -di * iden);
+  }
+  z64 (&vloc)[BC] = cv;   // v overwrites the column entries it is built from
+#pragma unroll
+  for (int b = 0; b < BC; ++b) {
+    const int i = BC * Cc + b;
+    vloc[b] = (i == jl + 1) ? zmk(1, 0) : ((i > jl + 1 && i < Nl) ? zmul(sc, cv[b]) : zmk(0, 0));
+  }
+  if (tid < 32) {
+#pragma unroll
+    for (int b = 0; b < BC; ++b) {
+      const int i = BC * Cc + b;
+      M.vbuf[i] = vloc[b];
+      if (i >= jl + 2 && i < Nl) M.Rf[refl_off(j, N) + (i - jl - 2)] = vloc[b];
+    }
+    if (tid == 0) {
+      M.d_s[j] = M.col_buf[jl].x;
+      M.e_s[j] = beta;
+      M.tau_s[2 * j] = tau.x;
+      M.tau_s[2 * j + 1] = tau.y;
+    }
+  }
+  // s = A v for this thread's rows, reduced over the half-wave (pbuf holds s; p = tau s);
+  // row blocks that lie entirely in the eliminated part (rows <= jl) only publish zeros
+  const bool live = BR * R + BR - 1 > jl;   // uniform over the half-wave
+  if (live) {
+    if constexpr (BR == 8 || BR == 4) {
+      constexpr int NV = 2 * BR;
+      double vv[NV];
+#pragma unroll
+      for (int a = 0; a < BR; ++a) {
+        z64 s = zmul(A[a][0], vloc[0]);
+#pragma unroll
+        for (int b = 1; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+        vv[2 * a] = s.x;
+        vv[2 * a + 1] = s.y;
+      }
+      const double r = tsum_halfwave<NV>(vv, Cc);
+      constexpr int SH = (NV == 16) ? 1 : 2;   // lane Cc holds value Cc >> SH
+      if ((Cc & ((1 << SH) - 1)) == 0) {
+        const int val = Cc >> SH;
+        const int i = BR * R + (val >> 1);
+        reinterpret_cast<double*>(M.pbuf)[2 * i + (val & 1)] = (i > jl && i < Nl) ? r : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < BR; ++a) {
+        z64 s = zmk(0, 0);
+#pragma unroll
+        for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
+        s.x = gsum<32>(s.x);
+        s.y = gsum<32>(s.y);
+        const int i = BR * R + a;
+        if (Cc == 0) M.pbuf[i] = (i > jl && i < Nl) ? s : zmk(0, 0);
+      }
+    }
+  } else if (Cc == 0) {
+#pragma unroll
+    for (int a = 0; a < BR; ++a) M.pbuf[BR * R + a] = zmk(0, 0);
+  }
+  __syncthreads();
+  // p = tau s; alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
+  z64 dt = zmk(0, 0);
+  z64 pcol[BC];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) {
+    pcol[b] = zmul(tau, M.pbuf[BC * Cc + b]);
+    dt = zadd(dt, zcmul(pcol[b], vloc[b]));
+  }
+  dt.x = gsum<32>(dt.x);
+  dt.y = gsum<32>(dt.y);
+  const z64 alpha2 = zscale(zmul(tau, dt), -0.5);
+  if (live) {
+#pragma unroll
+    for (int a = 0; a < BR; ++a) {
+      const z64 vr = M.vbuf[BR * R + a];
+      const z64 wr = zadd(zmul(tau, M.pbuf[BR * R + a]), zmul(alpha2, vr));
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
+        A[a][b] = zsub(A[a][b], zadd(zmul(vr, zconj(wc)), zmul(wr, zconj(vloc[b]))));
+      }
+    }
+  }
+  // owners of column jl + 1 broadcast it for the next step
+  if (Cc == (jl + 1) / BC) {
+    constexpr int bsel = (BB + 1) % BC;
+#pragma unroll
+    for (int a = 0; a < BR; ++a) M.col_buf[BR * R + a] = A[a][bsel];
+  }
+  __syncthreads();
+}
+
+template <int BR, int BC>
 __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, const Channel& ch, int nsplit,
                                          int c, int N, int kmax, int r_target, double eps, int tie,
-                                         int renorm, int c_out, const EigBufs& B,
-                                         cx_t<T>* __restrict__ W) {
+                                         int renorm, const EigBufs& B) {
   constexpr int NP = 32 * BC;            // padded order; the thread grid is (NP / BR) x 32
   constexpr int NTH = 32 * (NP / BR);    // threads
   extern __shared__ __attribute__((aligned(16))) double dyn[];   // phase-dependent scratch
@@ -194,165 +419,66 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
 
   // ---------------------------------------------------------------- 2. tridiagonalisation
   // Reflector entries i >= j + 2 are kept in LDS while reducing (a global store inside the
-  // loop would make every barrier wait for its completion); they are spilled to the workspace
-  // in one pass afterwards, because the eigenvector phase reuses this LDS.
+  // loop would make every barrier wait for its completion) and spilled to the workspace
+  // afterwards, because the eigenvector phase reuses this LDS.  With the 128-order layout the
+  // last 64 steps run on the trailing 64 x 64 block moved to a <4, 2> layout (a quarter of the
+  // arithmetic per step): the finished reflectors are spilled first and the move is staged
+  // through the freed LDS.
   z64* Rf = reinterpret_cast<z64*>(dyn);
   double* refl = B.P;
-  auto step = [&](const int j, auto bbc) {
-    constexpr int bb = decltype(bbc)::value;   // j % BC
-    // reflector from column j (every half-wave redundantly; lane Cc owns entries BC Cc + b)
-    const z64 alpha = col_buf[j + 1];
-    z64 cv[BC];
-    double xn2 = 0;
-#pragma unroll
-    for (int b = 0; b < BC; ++b) {
-      const int i = BC * Cc + b;
-      cv[b] = col_buf[i];
-      if (i > j + 1 && i < N) xn2 += cv[b].x * cv[b].x + cv[b].y * cv[b].y;
-    }
-    xn2 = gsum<32>(xn2);
-    double beta = alpha.x;
-    z64 tau = zmk(0, 0), sc = zmk(0, 0);
-    const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
-    if (!trivial) {
-      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-      beta = (alpha.x >= 0) ? -nrm : nrm;
-      const double ib = 1.0 / beta;
-      tau = zmk((beta - alpha.x) * ib, -alpha.y * ib);
-      const double dr = alpha.x - beta, di = alpha.y;
-      const double iden = 1.0 / (dr * dr + di * di);
-      sc = zmk(dr * iden, -di * iden);
-    }
-    z64 (&vloc)[BC] = cv;   // v overwrites the column entries it is built from
-#pragma unroll
-    for (int b = 0; b < BC; ++b) {
-      const int i = BC * Cc + b;
-      vloc[b] = (i == j + 1) ? zmk(1, 0) : ((i > j + 1 && i < N) ? zmul(sc, cv[b]) : zmk(0, 0));
-    }
-    if (tid < 32) {
-#pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        const int i = BC * Cc + b;
-        vbuf[i] = vloc[b];
-        if (i >= j + 2 && i < N) Rf[refl_off(j, N) + (i - j - 2)] = vloc[b];
-      }
-      if (tid == 0) {
-        d_s[j] = col_buf[j].x;
-        e_s[j] = beta;
-        tau_s[2 * j] = tau.x;
-        tau_s[2 * j + 1] = tau.y;
-      }
-    }
-    // s = A v for this thread's rows, reduced over the half-wave (pbuf holds s; p = tau s);
-    // row blocks that lie entirely in the eliminated part (rows <= j) only publish zeros
-    const bool live = BR * R + BR - 1 > j;   // uniform over the half-wave
-    if (live) {
-      if constexpr (BR == 8) {
-        // 16 values (8 rows x re/im) over 32 lanes by a transposing reduction: each stage
-        // halves the values a lane keeps and swaps the other half with its partner (lane ^ 16,
-        // then row_mirror, row_half_mirror and quad xor 2 pair lanes that differ in bits 3, 2,
-        // 1), and a last exchange adds the pair differing in bit 0: lane Cc ends with the
-        // half-wave total of value Cc >> 1, i.e. row Cc >> 2, component (Cc >> 1) & 1.
-        double v16[16];
-#pragma unroll
-        for (int a = 0; a < BR; ++a) {
-          z64 s = zmk(0, 0);
-#pragma unroll
-          for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
-          v16[2 * a] = s.x;
-          v16[2 * a + 1] = s.y;
-        }
-        const bool f4 = (Cc >> 4) & 1, f3 = (Cc >> 3) & 1, f2 = (Cc >> 2) & 1, f1 = (Cc >> 1) & 1;
-        double v8[8], v4[4], v2[2];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const double snd = f4 ? v16[q] : v16[q + 8];
-          const double kp = f4 ? v16[q + 8] : v16[q];
-          v8[q] = kp + __shfl_xor(snd, 16, 64);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double snd = f3 ? v8[q] : v8[q + 4];
-          const double kp = f3 ? v8[q + 4] : v8[q];
-          v4[q] = kp + dpp_mov<0x140>(snd);   // row_mirror
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const double snd = f2 ? v4[q] : v4[q + 2];
-          const double kp = f2 ? v4[q + 2] : v4[q];
-          v2[q] = kp + dpp_mov<0x141>(snd);   // row_half_mirror
-        }
-        double v1;
-        {
-          const double snd = f1 ? v2[0] : v2[1];
-          const double kp = f1 ? v2[1] : v2[0];
-          v1 = kp + dpp_mov<0x4E>(snd);       // quad_perm xor 2
-        }
-        v1 += dpp_mov<0xB1>(v1);              // quad_perm xor 1
-        if (!(Cc & 1)) {
-          const int i = BR * R + (Cc >> 2);
-          reinterpret_cast<double*>(pbuf)[2 * i + ((Cc >> 1) & 1)] = (i > j && i < N) ? v1 : 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < BR; ++a) {
-          z64 s = zmk(0, 0);
-#pragma unroll
-          for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
-          s.x = gsum<32>(s.x);
-          s.y = gsum<32>(s.y);
-          const int i = BR * R + a;
-          if (Cc == 0) pbuf[i] = (i > j && i < N) ? s : zmk(0, 0);
-        }
-      }
-    } else if (Cc == 0) {
-#pragma unroll
-      for (int a = 0; a < BR; ++a) pbuf[BR * R + a] = zmk(0, 0);
-    }
-    __syncthreads();
-    // p = tau s; alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
-    z64 dt = zmk(0, 0);
-    z64 pcol[BC];
-#pragma unroll
-    for (int b = 0; b < BC; ++b) {
-      pcol[b] = zmul(tau, pbuf[BC * Cc + b]);
-      dt = zadd(dt, zcmul(pcol[b], vloc[b]));
-    }
-    dt.x = gsum<32>(dt.x);
-    dt.y = gsum<32>(dt.y);
-    const z64 alpha2 = zscale(zmul(tau, dt), -0.5);
-    if (live) {
-#pragma unroll
-    for (int a = 0; a < BR; ++a) {
-      const z64 vr = vbuf[BR * R + a];
-      const z64 wr = zadd(zmul(tau, pbuf[BR * R + a]), zmul(alpha2, vr));
-#pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
-        A[a][b] = zsub(A[a][b], zadd(zmul(vr, zconj(wc)), zmul(wr, zconj(vloc[b]))));
-      }
-    }
-    }
-    // owners of column j + 1 broadcast it for the next step
-    if (Cc == (j + 1) / BC) {
-      constexpr int bsel = (bb + 1) % BC;
-#pragma unroll
-      for (int a = 0; a < BR; ++a) col_buf[BR * R + a] = A[a][bsel];
-    }
-    __syncthreads();
-  };
-  for (int jb = 0; jb + 1 < N; jb += BC) {
+  const TriSmem M{col_buf, vbuf, pbuf, d_s, e_s, tau_s, Rf};
+  constexpr bool kShrink = (BR == 8 && BC == 4);
+  const int jsw = (kShrink && N > 64) ? N - 64 : N - 1;   // steps on the full layout
+  for (int jb = 0; jb < jsw; jb += BC) {
     static_for<BC>([&](auto bbc) {
       const int j = jb + decltype(bbc)::value;
-      if (j + 1 < N) step(j, bbc);
+      if (j < jsw) tri_step<BR, BC, decltype(bbc)::value>(A, j, N, 0, N, M);
     });
   }
+  int spilled = 0;   // reflector entries already in the workspace
+  int cb0 = 0;       // global index of col_buf entry 0
+  if constexpr (kShrink) {
+    if (N > 64) {
+      spilled = refl_off(jsw, N);
+      for (int e = tid; e < spilled; e += NTH) {
+        refl[2 * e] = Rf[e].x;
+        refl[2 * e + 1] = Rf[e].y;
+      }
+      __syncthreads();
+      z64* Sg = Rf;   // 64 x 64 staging, row-major, local indices
+#pragma unroll
+      for (int a = 0; a < BR; ++a)
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int i = BR * R + a, jj = BC * Cc + b;
+          if (i >= jsw && jj >= jsw && i < N && jj < N) Sg[(i - jsw) * 64 + (jj - jsw)] = A[a][b];
+        }
+      __syncthreads();
+      z64 A2[4][2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) A2[a][b] = Sg[(4 * R + a) * 64 + 2 * Cc + b];
+      if (Cc == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) col_buf[4 * R + a] = A2[a][0];
+      }
+      __syncthreads();   // the staging is read before the steps write reflectors over it
+      for (int jb = 0; jb < 63; jb += 2) {
+        static_for<2>([&](auto bbc) {
+          const int jl = jb + decltype(bbc)::value;
+          if (jl < 63) tri_step<4, 2, decltype(bbc)::value>(A2, jl, 64, jsw, N, M);
+        });
+      }
+      cb0 = jsw;
+    }
+  }
   if (tid == 0) {
-    d_s[N - 1] = col_buf[N - 1].x;
+    d_s[N - 1] = col_buf[N - 1 - cb0].x;
     e_s[N - 1] = 0.0;
   }
   const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
-  for (int e = tid; e < nref; e += NTH) {
+  for (int e = spilled + tid; e < nref; e += NTH) {
     refl[2 * e] = Rf[e].x;
     refl[2 * e + 1] = Rf[e].y;
   }
@@ -423,6 +549,9 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   __syncthreads();
 
   // ---------------------------------------------------------------- 4. eigenvectors of T
+  // One lane per eigenvector.  The recurrences run over chunks of CH rows whose operands are
+  // read from LDS before the dependent arithmetic, so LDS latency is paid once per chunk.
+  constexpr int CH = 8;
   const int KP = kmax;
   double* Dp = dyn;              // inverse LDL^T pivots, [i * KP + t]
   double* X = dyn + NP * KP;     // vectors, [i * KP + t]
@@ -430,49 +559,102 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     const int t = tid;
     const double sigma = lam_s[t];
     // pivots D_i of T - sigma I = L D L^T, stored as 1 / D_i
-    double dp = d_s[0] - sigma;
-    if (fabs(dp) < pivmin) dp = -pivmin;
-    double rinv = 1.0 / dp;
+    double dp0 = d_s[0] - sigma;
+    if (fabs(dp0) < pivmin) dp0 = -pivmin;
+    double rinv = rcp_nr(dp0);
     Dp[t] = rinv;
-    for (int i = 1; i < N; ++i) {
-      dp = (d_s[i] - sigma) - e2_s[i - 1] * rinv;
-      if (fabs(dp) < pivmin) dp = -pivmin;
-      rinv = 1.0 / dp;
-      Dp[i * KP + t] = rinv;
+    X[t] = 1.0 + hash_unit((uint32_t)t, 0u);
+    for (int i0 = 1; i0 < N; i0 += CH) {
+      double dd[CH], ee[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = min(i0 + u, N - 1);
+        dd[u] = d_s[i];
+        ee[u] = e2_s[i - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        double dp = (dd[u] - sigma) - ee[u] * rinv;
+        if (fabs(dp) < pivmin) dp = -pivmin;
+        rinv = rcp_nr(dp);
+        dd[u] = rinv;
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (i0 + u < N) {
+          Dp[(i0 + u) * KP + t] = dd[u];
+          X[(i0 + u) * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)(i0 + u));
+        }
     }
-    for (int i = 0; i < N; ++i) X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
   }
   __syncthreads();
   for (int iter = 0; iter < 2; ++iter) {
     if (tid < kmax) {
       const int t = tid;
-      // forward: y_i -= l_{i-1} y_{i-1}, l_{i-1} = e_{i-1} / D_{i-1}
+      // forward: y_i = x_i - l_{i-1} y_{i-1}, l_{i-1} = e_{i-1} / D_{i-1}
       double y = X[t];
       double rprev = Dp[t];
-      for (int i = 1; i < N; ++i) {
-        const double ri = Dp[i * KP + t];
-        y = X[i * KP + t] - (e_s[i - 1] * rprev) * y;
-        X[i * KP + t] = y;
-        rprev = ri;
+      for (int i0 = 1; i0 < N; i0 += CH) {
+        double xx[CH], rr[CH], ee[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = min(i0 + u, N - 1);
+          xx[u] = X[i * KP + t];
+          rr[u] = Dp[i * KP + t];
+          ee[u] = e_s[i - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          y = xx[u] - (ee[u] * rprev) * y;
+          xx[u] = y;
+          rprev = rr[u];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (i0 + u < N) X[(i0 + u) * KP + t] = xx[u];
       }
       // backward: x_i = (y_i - e_i x_{i+1}) / D_i
       double xn = X[(N - 1) * KP + t] * Dp[(N - 1) * KP + t];
       X[(N - 1) * KP + t] = xn;
       double mx = fabs(xn);
-      for (int i = N - 2; i >= 0; --i) {
-        xn = (X[i * KP + t] - e_s[i] * xn) * Dp[i * KP + t];
-        X[i * KP + t] = xn;
-        mx = fmax(mx, fabs(xn));
+      for (int i0 = N - 2; i0 >= 0; i0 -= CH) {
+        double yy[CH], rr[CH], ee[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = max(i0 - u, 0);
+          yy[u] = X[i * KP + t];
+          rr[u] = Dp[i * KP + t];
+          ee[u] = e_s[i];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (i0 - u >= 0) {
+            xn = (yy[u] - ee[u] * xn) * rr[u];
+            yy[u] = xn;
+            mx = fmax(mx, fabs(xn));
+          }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (i0 - u >= 0) X[(i0 - u) * KP + t] = yy[u];
       }
+      // unit 2-norm (scaled by the largest entry first, so the squares cannot overflow)
       const double s1 = (mx > 0) ? 1.0 / mx : 1.0;
-      double nn = 0;
-      for (int i = 0; i < N; ++i) {
-        const double v = X[i * KP + t] * s1;
-        nn += v * v;
-        X[i * KP + t] = v;
+      double nn[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i0 = 0; i0 < N; i0 += CH) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (i0 + u < N) {
+            const double v = X[(i0 + u) * KP + t] * s1;
+            nn[u & 3] = fma(v, v, nn[u & 3]);
+          }
       }
-      const double s2 = (nn > 0) ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = 0; i < N; ++i) X[i * KP + t] *= s2;
+      const double ns = (nn[0] + nn[1]) + (nn[2] + nn[3]);
+      const double sc = s1 * ((ns > 0) ? 1.0 / sqrt(ns) : 0.0);
+      for (int i0 = 0; i0 < N; i0 += CH) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (i0 + u < N) X[(i0 + u) * KP + t] *= sc;
+      }
     }
     __syncthreads();
     for (int cs = wave; cs < kmax; cs += NTH / 64) {
@@ -485,17 +667,17 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
           dtt = gsum<64>(dtt);
           for (int i = lane; i < N; i += 64) X[i * KP + jj] -= dtt * X[i * KP + ii];
         }
-        double nn = 0;
-        for (int i = lane; i < N; i += 64) nn += X[i * KP + jj] * X[i * KP + jj];
-        nn = gsum<64>(nn);
-        const double s2 = (nn > 0) ? 1.0 / sqrt(nn) : 0.0;
+        double nq = 0;
+        for (int i = lane; i < N; i += 64) nq += X[i * KP + jj] * X[i * KP + jj];
+        nq = gsum<64>(nq);
+        const double s2 = (nq > 0) ? 1.0 / sqrt(nq) : 0.0;
         for (int i = lane; i < N; i += 64) X[i * KP + jj] *= s2;
       }
     }
     __syncthreads();
   }
 
-  // ---------------------------------------------------------------- 5. rank rule, V = Q Y, W
+  // ---------------------------------------------------------------- 5. rank rule
   if (tid == 0) {
     const double trace = sc_s[0];
     for (int t = 0; t < kmax; ++t) lam_s[t] = zero ? 0.0 : lam_s[t] * tnorm;
@@ -537,135 +719,234 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   __syncthreads();
   for (int t = tid; t < kmax; t += NTH) B.lam[t] = lam_s[t];
   const int k = k_s;
-  const double scl = sc_s[2];
   // with a record every eigenvector is formed (kmax == N <= 64), else only the kept ones
   const int nvec = B.rec ? N : k;
-  // LPC lanes per kept column (64 columns); lane g holds rows g, g + LPC, ...
-  constexpr int LPC = NTH / 64;
-  const int col = tid / LPC, g = tid % LPC;
-  constexpr int ZR = NP / LPC;
-  z64 z[ZR];
-#pragma unroll
-  for (int s = 0; s < ZR; ++s) {
-    const int i = g + LPC * s;
-    z[s] = zmk((col < nvec && i < N) ? (zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col]) : 0.0, 0.0);
+  double* Y = B.Y;
+  for (int e = tid; e < 2 * (N - 1); e += NTH) Y[e] = tau_s[e];
+  for (int e = tid; e < nvec * N; e += NTH) {
+    const int col = e / N, i = e - col * N;
+    Y[kEigYOff + col * kMaxEig + i] = zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col];
   }
-  __syncthreads();
-  // bring the reflectors back into LDS
-  for (int e = tid; e < nref; e += NTH) Rf[e] = zmk(refl[2 * e], refl[2 * e + 1]);
-  __syncthreads();
-  if (col < nvec) {
-    for (int j = N - 2; j >= 0; --j) {
-      const z64 tj = zmk(tau_s[2 * j], tau_s[2 * j + 1]);
-      if (tj.x == 0.0 && tj.y == 0.0) continue;
-      const int ro = refl_off(j, N);
-      z64 s = zmk(0, 0);
-#pragma unroll
-      for (int q = 0; q < ZR; ++q) {
-        const int i = g + LPC * q;
-        if (i >= j + 1 && i < N) {
-          const z64 v = (i == j + 1) ? zmk(1, 0) : Rf[ro + (i - j - 2)];
-          s = zadd(s, zcmul(v, z[q]));
-        }
-      }
-      s.x = gsum<LPC>(s.x);
-      s.y = gsum<LPC>(s.y);
-      const z64 ts = zmul(tj, s);
-#pragma unroll
-      for (int q = 0; q < ZR; ++q) {
-        const int i = g + LPC * q;
-        if (i >= j + 1 && i < N) {
-          const z64 v = (i == j + 1) ? zmk(1, 0) : Rf[ro + (i - j - 2)];
-          z[q] = zsub(z[q], zmul(v, ts));
-        }
-      }
-    }
-  }
-  __syncthreads();
-  z64* V = reinterpret_cast<z64*>(dyn);   // V[i * 64 + col]
-  if (col < nvec) {
-#pragma unroll
-    for (int s = 0; s < ZR; ++s) {
-      const int i = g + LPC * s;
-      if (i < N) V[i * 64 + col] = z[s];
-    }
-  }
-  __syncthreads();
   if (B.rec) {
     double* rec = B.rec;
     if (tid == 0) {
       rec[0] = (double)k;
-      rec[1] = scl;
+      rec[1] = sc_s[2];
       rec[2] = (double)N;
       rec[3] = sc_s[0];
       rec[4] = (double)renorm;
     }
     for (int t = tid; t < N; t += NTH) rec[kRecHeader + t] = lam_s[t];
-    double* rv = rec + kRecHeader + N;
-    for (int e = tid; e < N * N; e += NTH) {
-      const z64 v = V[(e / N) * 64 + (e % N)];
-      rv[2 * e] = v.x;
-      rv[2 * e + 1] = v.y;
+  }
+}
+
+// ---------------------------------------------------------------- back-transform and W
+// V = Q Y for the kept eigenvectors (every eigenvector with a record), with Q = H_0 ... H_{N-2}
+// applied from the right end, and the projection matrix
+// W_{(b,v),(b',j)} = c sum_a (E_a)_{b'b} V[(a,v), j] (split view) or W = c V_k (plain view).
+// Columns are independent, so this runs over kEigBtBlocks work-groups of kEigBtCols waves, one
+// column per wave, a lane holding rows lane + 64 s.  The packed reflectors are staged in LDS in
+// chunks of kBtChunk reflectors, in the order they are applied: the loads of the next chunk are
+// in flight while the current one is applied.
+constexpr int kBtChunk = 16;
+constexpr int kBtPer = 8;   // staged entries per thread and chunk
+static_assert(kBtChunk * (kMaxEig - 2) <= 64 * kEigBtCols * kBtPer, "a chunk must fit the staging registers");
+
+__device__ __forceinline__ void bt_chunk_range(int jhi, int N, int& e0, int& e1, int& jlo) {
+  jlo = max(0, jhi - kBtChunk + 1);
+  e0 = refl_off(jlo, N);
+  e1 = refl_off(jhi + 1, N);
+}
+
+template <class T, int RPL>
+__device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit, int c, int N, int c_out,
+                                                   const EigBufs& B, cx_t<T>* __restrict__ W, int cblk) {
+  constexpr int NP = 64 * RPL;
+  constexpr int NTB = 64 * kEigBtCols;
+  extern __shared__ __attribute__((aligned(16))) double bt_dyn[];
+  z64* rfl = reinterpret_cast<z64*>(bt_dyn);   // packed reflector entries (refl_off layout)
+  __shared__ z64 tau_l[kMaxEig];
+  __shared__ z64 Vs[kEigBtCols][NP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = B.info->k;
+  const double scl = B.info->scale;
+  const int nvec = B.rec ? N : k;
+  if (cblk * kEigBtCols >= max(nvec, c_out)) return;   // uniform over the work-group
+  const int col = cblk * kEigBtCols + wave;
+  const bool act = col < nvec;
+  const double2* __restrict__ refl = reinterpret_cast<const double2*>(B.P);
+  for (int j = tid; j < N - 1; j += NTB) tau_l[j] = zmk(B.Y[2 * j], B.Y[2 * j + 1]);
+  z64 z[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int i = lane + 64 * s;
+    z[s] = zmk((act && i < N) ? B.Y[kEigYOff + col * kMaxEig + i] : 0.0, 0.0);
+  }
+  // z and tau are needed at once; waiting here keeps the loop below from waiting on the
+  // staging loads it issues ahead of their use
+  __builtin_amdgcn_s_waitcnt(0);
+  double2 st[kBtPer];
+  int e0, e1, jlo;
+  if (N >= 2) {
+    bt_chunk_range(N - 2, N, e0, e1, jlo);
+#pragma unroll
+    for (int p = 0; p < kBtPer; ++p) {
+      const int e = e0 + tid + NTB * p;
+      st[p] = refl[e < e1 ? e : e0];
+    }
+#pragma unroll
+    for (int p = 0; p < kBtPer; ++p) {
+      const int e = e0 + tid + NTB * p;
+      if (e < e1) rfl[e] = zmk(st[p].x, st[p].y);
     }
   }
+  __syncthreads();
+  for (int jhi = N - 2; jhi >= 0; jhi -= kBtChunk) {
+    bt_chunk_range(jhi, N, e0, e1, jlo);
+    const bool more = jlo > 0;
+    int f0 = 0, f1 = 0, flo = 0;
+    if (more) {
+      bt_chunk_range(jlo - 1, N, f0, f1, flo);
+#pragma unroll
+      for (int p = 0; p < kBtPer; ++p) {
+        const int e = f0 + tid + NTB * p;
+        st[p] = refl[e < f1 ? e : f0];
+      }
+    }
+    if (act) {
+      // four reflectors at a time: their LDS reads (every lane reads, from entry 0 where it
+      // needs none, and masks the value arithmetically, so no read sits behind a branch) are
+      // issued before the first is applied
+      for (int jg = jhi; jg >= jlo; jg -= 4) {
+        z64 v[4][RPL], tj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = jg - u;
+          const int ro = refl_off(j, N) - j - 2;
+          tj[u] = tau_l[j >= 0 ? j : 0];
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) {
+            const int i = lane + 64 * s;
+            const bool stv = j >= jlo && i >= j + 2 && i < N;
+            const z64 ld = rfl[stv ? ro + i : 0];
+            const double m = stv ? 1.0 : 0.0;
+            v[u][s] = zmk(fma(ld.x, m, i == j + 1 ? 1.0 : 0.0), ld.y * m);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (jg - u >= jlo) {   // uniform
+            z64 sm = zcmul(v[u][0], z[0]);
+#pragma unroll
+            for (int s = 1; s < RPL; ++s) sm = zadd(sm, zcmul(v[u][s], z[s]));
+            wsum64x2(sm.x, sm.y);
+            const z64 ts = zmul(tj[u], sm);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) z[s] = zsub(z[s], zmul(v[u][s], ts));
+          }
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int p = 0; p < kBtPer; ++p) {
+        const int e = f0 + tid + NTB * p;
+        if (e < f1) rfl[e] = zmk(st[p].x, st[p].y);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) Vs[wave][lane + 64 * s] = z[s];
+  __syncthreads();
+  if (B.rec && col < N) {
+    double* rv = B.rec + kRecHeader + N;
+    for (int i = lane; i < N; i += 64) {
+      rv[2 * (i * N + col)] = Vs[wave][i].x;
+      rv[2 * (i * N + col) + 1] = Vs[wave][i].y;
+    }
+  }
+  if (col >= c_out) return;
   using C = cx_t<T>;
   if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
-    for (int e = tid; e < rows * cols; e += NTH) {
-      const int rw = e / cols, cl = e % cols;
-      const int b = rw / c, v = rw % c, bp = cl / c_out, jj = cl % c_out;
-      z64 acc = zmk(0, 0);
-      if (jj < k) {
-        for (int a = 0; a < ch.m; ++a)
-          acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), V[(a * c + v) * 64 + jj]));
-      }
-      C o;
-      o.x = (T)(acc.x * scl);
-      o.y = (T)(acc.y * scl);
-      W[e] = o;
-      if (B.W64) {
-        B.W64[2 * e] = acc.x * scl;
-        B.W64[2 * e + 1] = acc.y * scl;
+    for (int rw = lane; rw < rows; rw += 64) {
+      const int b = rw / c, v = rw - b * c;
+#pragma unroll
+      for (int bp = 0; bp < 2; ++bp) {
+        z64 acc = zmk(0, 0);
+        if (col < k) {
+          for (int a = 0; a < ch.m; ++a)
+            acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), Vs[wave][a * c + v]));
+        }
+        const int e = rw * cols + bp * c_out + col;
+        C o;
+        o.x = (T)(acc.x * scl);
+        o.y = (T)(acc.y * scl);
+        W[e] = o;
+        if (B.W64) {
+          B.W64[2 * e] = acc.x * scl;
+          B.W64[2 * e + 1] = acc.y * scl;
+        }
       }
     }
   } else {
-    for (int e = tid; e < N * c_out; e += NTH) {
-      const int i = e / c_out, jj = e % c_out;
-      const z64 acc = (jj < k) ? V[i * 64 + jj] : zmk(0, 0);
+    for (int i = lane; i < N; i += 64) {
+      const z64 acc = (col < k) ? Vs[wave][i] : zmk(0, 0);
       C o;
       o.x = (T)(acc.x * scl);
       o.y = (T)(acc.y * scl);
-      W[e] = o;
+      W[i * c_out + col] = o;
     }
   }
 }
 
-template <class T, int BR, int BC>
+template <int BR, int BC>
 __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* __restrict__ S, int Fc, Channel ch,
                                                    int nsplit, int c, int N, int kmax, int r_target,
-                                                   double eps, int tie, int renorm, int c_out,
-                                                   EigBufs B, cx_t<T>* __restrict__ W) {
-  eig_body<T, BR, BC>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, B, W);
+                                                   double eps, int tie, int renorm, EigBufs B) {
+  eig_body<BR, BC>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, B);
 }
 
 // One work-group per job; every job of a launch has the same size class (BR, BC).
 template <class T, int BR, int BC>
 __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_batched(const EigJob<T>* __restrict__ jobs) {
   const EigJob<T>& J = jobs[blockIdx.x];
-  eig_body<T, BR, BC>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm,
-                      J.c_out, J.B, J.W);
+  eig_body<BR, BC>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
+}
+
+template <class T, int RPL>
+__global__ __launch_bounds__(64 * kEigBtCols) void backtransform_kernel(Channel ch, int nsplit, int c, int N,
+                                                                     int c_out, EigBufs B,
+                                                                     cx_t<T>* __restrict__ W) {
+  backtransform_body<T, RPL>(ch, nsplit, c, N, c_out, B, W, blockIdx.x);
+}
+
+// kEigBtBlocks work-groups per job
+template <class T, int RPL>
+__global__ __launch_bounds__(64 * kEigBtCols) void backtransform_batched(const EigJob<T>* __restrict__ jobs) {
+  const EigJob<T>& J = jobs[blockIdx.x / kEigBtBlocks];
+  backtransform_body<T, RPL>(J.ch, J.nsplit, J.c, J.N, J.c_out, J.B, J.W, blockIdx.x % kEigBtBlocks);
 }
 
 template <int BR, int BC>
 static size_t eig_shm(int kmax) {
   constexpr int NP = 32 * BC;
-  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);
-  const size_t ph5a = (size_t)(NP * (NP - 1) / 2) * 16;
-  const size_t ph5b = (size_t)NP * 64 * 16;
-  size_t shm = ph4;
-  if (ph5a > shm) shm = ph5a;
-  if (ph5b > shm) shm = ph5b;
-  return shm;
+  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);   // pivots and vectors
+  const size_t ph2 = (size_t)(NP * (NP - 1) / 2) * 16;         // packed reflectors
+  return ph4 > ph2 ? ph4 : ph2;
+}
+
+// packed reflector entries of an order-N eigensolve (at least one entry)
+static size_t bt_shm(int N) {
+  const int ne = N >= 3 ? (N - 1) * (N - 2) / 2 : 1;
+  return (size_t)ne * 16;
+}
+
+template <class F>
+static hipError_t allow_shm(F* fn, size_t shm) {
+  if (shm <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
 template <class T, int BR, int BC>
@@ -673,12 +954,17 @@ static hipError_t launch_eig_batched_bs(const EigJob<T>* jobs, int njobs, int km
   constexpr int NP = 32 * BC;
   constexpr int NTH = 32 * (NP / BR);
   const size_t shm = eig_shm<BR, BC>(kmax_max);
-  if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_batched<T, BR, BC>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
+  hipError_t e = allow_shm(eig_batched<T, BR, BC>, shm);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eig_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  constexpr int RPL = NP > 64 ? 2 : 1;
+  const size_t bshm = bt_shm(NP);
+  e = allow_shm(backtransform_batched<T, RPL>, bshm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((backtransform_batched<T, RPL>), dim3(njobs * kEigBtBlocks), dim3(64 * kEigBtCols), bshm, s,
+                     jobs);
   return hipGetLastError();
 }
 
@@ -693,25 +979,16 @@ hipError_t launch_eig_batched(int N, const EigJob<T>* jobs, int njobs, int kmax_
 template hipError_t launch_eig_batched<float>(int, const EigJob<float>*, int, int, hipStream_t);
 template hipError_t launch_eig_batched<double>(int, const EigJob<double>*, int, int, hipStream_t);
 
-template <class T, int BR, int BC>
-static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int nsplit, int c,
-                                int N, int kmax, int r_target, double eps, int tie, int renorm,
-                                int c_out, const EigBufs& b, cx_t<T>* W, hipStream_t s) {
+template <int BR, int BC>
+static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int nsplit, int c, int N, int kmax,
+                                int r_target, double eps, int tie, int renorm, const EigBufs& b, hipStream_t s) {
   constexpr int NP = 32 * BC;
   constexpr int NTH = 32 * (NP / BR);
-  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);
-  const size_t ph5a = (size_t)(NP * (NP - 1) / 2) * 16;   // packed reflectors
-  const size_t ph5b = (size_t)NP * 64 * 16;               // V
-  size_t shm = ph4;
-  if (ph5a > shm) shm = ph5a;
-  if (ph5b > shm) shm = ph5b;
-  if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(eig_kernel<T, BR, BC>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL((eig_kernel<T, BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax,
-                     r_target, eps, tie, renorm, c_out, b, W);
+  const size_t shm = eig_shm<BR, BC>(kmax);
+  const hipError_t e = allow_shm(eig_kernel<BR, BC>, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_kernel<BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax, r_target,
+                     eps, tie, renorm, b);
   return hipGetLastError();
 }
 
@@ -719,11 +996,26 @@ template <class T>
 hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, int c, int N,
                       int kmax, int r_target, double eps, int tie, int renorm, int c_out,
                       const EigBufs& b, cx_t<T>* W, hipStream_t s) {
-  if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64) return hipErrorInvalidValue;
+  if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64 || c_out > 64) return hipErrorInvalidValue;
   if (b.rec && (N > kRecMaxN || kmax != N)) return hipErrorInvalidValue;
-  if (N <= 32) return launch_eig_bs<T, 1, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
-  if (N <= 64) return launch_eig_bs<T, 2, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
-  return launch_eig_bs<T, 8, 4>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b, W, s);
+  hipError_t e;
+  if (N <= 32) e = launch_eig_bs<1, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
+  else if (N <= 64) e = launch_eig_bs<2, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
+  else e = launch_eig_bs<8, 4>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
+  if (e != hipSuccess) return e;
+  const size_t bshm = bt_shm(N);
+  if (N <= 64) {
+    e = allow_shm(backtransform_kernel<T, 1>, bshm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((backtransform_kernel<T, 1>), dim3(kEigBtBlocks), dim3(64 * kEigBtCols), bshm, s, ch, nsplit,
+                       c, N, c_out, b, W);
+  } else {
+    e = allow_shm(backtransform_kernel<T, 2>, bshm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((backtransform_kernel<T, 2>), dim3(kEigBtBlocks), dim3(64 * kEigBtCols), bshm, s, ch, nsplit,
+                       c, N, c_out, b, W);
+  }
+  return hipGetLastError();
 }
 
 template hipError_t launch_eig<float>(const double*, int, const Channel&, int, int, int, int, int, double,

@@ -70,7 +70,13 @@ struct EigBufs {
   DevInfo* info;
   double* rec;      // nullable: compression record for the reverse sweep (every eigenpair)
   double* W64;      // nullable: W in FP64 as well (split view), for chained compressions
+  double* Y;        // reflector scalars tau_j (2 (N - 1) doubles), then at kEigYOff the kept
+                    // eigenvectors of T, column t at t * kMaxEig (eigensolver -> back-transform)
 };
+constexpr int kEigYOff = 2 * kMaxEig;
+constexpr size_t kEigYDoubles = (size_t)kEigYOff + 64 * (size_t)kMaxEig;
+constexpr int kEigBtCols = 4;                 // back-transform: columns (one wave each) per work-group
+constexpr int kEigBtBlocks = 64 / kEigBtCols; // work-groups per eigensolve (at most 64 columns)
 
 // Compression record (FP64), written by the eigensolver when EigBufs::rec is set:
 // [0] k, [1] scale c, [2] N, [3] Tr G, [4] renorm, [5..8) unused, [8, 8 + N) eigenvalues

@@ -37,7 +37,7 @@ int next_pow2(int x) {
 struct Layout {
   int r_pad, m_pad, ld, F_max, FO_max;
   size_t state_bytes;
-  size_t off_info, off_part, off_S, off_P, off_lam, off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
+  size_t off_info, off_part, off_S, off_P, off_Y, off_lam, off_W, off_out, off_pbuf, off_cdf, off_bsum, off_terms, off_pauli, off_unif, off_samp, total;
   bool adjoint;        // reverse sweep available (fused form, m_max * r_pad <= 64)
   size_t off_adj, rec_bytes;
   size_t off_chain;    // fused form: W of the pending projection, the next W (FP64) and scratch
@@ -73,6 +73,7 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   L.off_part = take((size_t)nb * NUP * 256 * rs);
   L.off_S = take((size_t)Fc * Fc * 16);
   L.off_P = take((size_t)N * (N + 1) / 2 * 16);
+  L.off_Y = take(kEigYDoubles * 8);
   L.off_lam = take(N * 8);
   L.off_W = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
   L.off_out = take(4096 * 8);
@@ -391,6 +392,7 @@ EigBufs eig_bufs(lrdm_t h) {
   b.S = h->ws<double>(h->lay.off_S);
   b.P = h->ws<double>(h->lay.off_P);
   b.lam = h->ws<double>(h->lay.off_lam);
+  b.Y = h->ws<double>(h->lay.off_Y);
   b.info = h->ws<DevInfo>(h->lay.off_info);
   b.rec = nullptr;
   b.W64 = nullptr;

@@ -102,19 +102,25 @@ __device__ __forceinline__ double hash_unit(uint32_t a, uint32_t b) {
 // offset of reflector j's entries i >= j + 2 in packed storage
 __device__ __forceinline__ int refl_off(int j, int N) { return j * (N - 2) - (j * (j - 1)) / 2; }
 
-// f / q through the hardware reciprocal refined by one Newton step (a few ulp; the Sturm
-// count only needs the sign pattern of the recurrence)
-__device__ __forceinline__ double fdiv(double f, double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  r = fma(r, fma(-q, r, 1.0), r);
-  return f * r;
-}
-
 // 1 / q through the hardware reciprocal refined by two Newton steps
 __device__ __forceinline__ double rcp_nr(double q) {
   double r = __builtin_amdgcn_rcp(q);
   r = fma(r, fma(-q, r, 1.0), r);
   return fma(r, fma(-q, r, 1.0), r);
+}
+
+// One step of the pivot recurrence q_i = (d_i - x) - e_{i-1}^2 / q_{i-1}: the reciprocal of q
+// from the hardware estimate refined by one Newton step (a few ulp; the count needs only the
+// sign pattern), fused into the update; pivots at or below pivmin count as negative and are
+// replaced by -pivmin.
+__device__ __forceinline__ void sturm_step(double& q, int& cnt, double dx, double f, double pivmin) {
+  const double r0 = __builtin_amdgcn_rcp(q);
+  const double r = fma(r0, fma(-q, r0, 1.0), r0);
+  q = fma(-f, r, dx);
+  if (q <= pivmin) {
+    ++cnt;
+    q = fmin(q, -pivmin);
+  }
 }
 
 // number of eigenvalues of T (scaled, diagonal d, squared off-diagonal e2) below x
@@ -128,21 +134,16 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
   }
   int i = 1;
   for (; i + 3 < N; i += 4) {
-    const double d0 = d[i], d1 = d[i + 1], d2 = d[i + 2], d3 = d[i + 3];
-    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
-    q = (d0 - x) - fdiv(f0, q);
-    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d1 - x) - fdiv(f1, q);
-    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d2 - x) - fdiv(f2, q);
-    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-    q = (d3 - x) - fdiv(f3, q);
-    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
+    double dd[4], ff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dd[u] = d[i + u] - x;
+      ff[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sturm_step(q, cnt, dd[u], ff[u], pivmin);
   }
-  for (; i < N; ++i) {
-    q = (d[i] - x) - fdiv(e2[i - 1], q);
-    if (q <= pivmin) { ++cnt; q = fmin(q, -pivmin); }
-  }
+  for (; i < N; ++i) sturm_step(q, cnt, d[i] - x, e2[i - 1], pivmin);
   return cnt;
 }
 
@@ -515,10 +516,15 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     const int t = tid / G, g = tid % G;
     const bool active = (t < kmax) && !zero;
     const int asc = N - 1 - t;
+    // G-section: lane g counts at the interior point g + 1 of G + 1 equal sections.  Without a
+    // record the bracket stops at an absolute width of 4 eps (eigenvalues to ||T|| eps, what the
+    // rank rule and the inverse iteration need); a record (reverse sweep) needs eigenvalue
+    // differences to relative accuracy and runs the relative rule down to 4 eps^2.
+    const double floor_w = B.rec ? 4 * epsm * epsm : 4 * epsm;
     double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
     for (int it = 0; it < 24; ++it) {
       const double w = hi - lo;
-      const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + 4 * epsm * epsm);
+      const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + floor_w);
       if (__ballot(active && !done) == 0ull) break;
       const double x = lo + w * (double)(g + 1) / (double)(G + 1);
       const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
@@ -550,11 +556,16 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
 
   // ---------------------------------------------------------------- 4. eigenvectors of T
   // One lane per eigenvector.  The recurrences run over chunks of CH rows whose operands are
-  // read from LDS before the dependent arithmetic, so LDS latency is paid once per chunk.
+  // read from LDS before the dependent arithmetic (LDS latency paid once per chunk), with a
+  // scalar remainder loop, so no load or store in a chunk is conditional.
   constexpr int CH = 8;
   const int KP = kmax;
   double* Dp = dyn;              // inverse LDL^T pivots, [i * KP + t]
   double* X = dyn + NP * KP;     // vectors, [i * KP + t]
+  for (int e = tid; e < N * kmax; e += NTH) {
+    const int i = e / kmax, t = e - i * kmax;
+    X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
+  }
   if (tid < kmax) {
     const int t = tid;
     const double sigma = lam_s[t];
@@ -563,28 +574,29 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     if (fabs(dp0) < pivmin) dp0 = -pivmin;
     double rinv = rcp_nr(dp0);
     Dp[t] = rinv;
-    X[t] = 1.0 + hash_unit((uint32_t)t, 0u);
-    for (int i0 = 1; i0 < N; i0 += CH) {
+    int i = 1;
+    for (; i + CH <= N; i += CH) {
       double dd[CH], ee[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        const int i = min(i0 + u, N - 1);
-        dd[u] = d_s[i];
-        ee[u] = e2_s[i - 1];
+        dd[u] = d_s[i + u] - sigma;
+        ee[u] = e2_s[i + u - 1];
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        double dp = (dd[u] - sigma) - ee[u] * rinv;
+        double dp = dd[u] - ee[u] * rinv;
         if (fabs(dp) < pivmin) dp = -pivmin;
         rinv = rcp_nr(dp);
         dd[u] = rinv;
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
-        if (i0 + u < N) {
-          Dp[(i0 + u) * KP + t] = dd[u];
-          X[(i0 + u) * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)(i0 + u));
-        }
+      for (int u = 0; u < CH; ++u) Dp[(i + u) * KP + t] = dd[u];
+    }
+    for (; i < N; ++i) {
+      double dp = (d_s[i] - sigma) - e2_s[i - 1] * rinv;
+      if (fabs(dp) < pivmin) dp = -pivmin;
+      rinv = rcp_nr(dp);
+      Dp[i * KP + t] = rinv;
     }
   }
   __syncthreads();
@@ -594,14 +606,14 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
       // forward: y_i = x_i - l_{i-1} y_{i-1}, l_{i-1} = e_{i-1} / D_{i-1}
       double y = X[t];
       double rprev = Dp[t];
-      for (int i0 = 1; i0 < N; i0 += CH) {
+      int i = 1;
+      for (; i + CH <= N; i += CH) {
         double xx[CH], rr[CH], ee[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-          const int i = min(i0 + u, N - 1);
-          xx[u] = X[i * KP + t];
-          rr[u] = Dp[i * KP + t];
-          ee[u] = e_s[i - 1];
+          xx[u] = X[(i + u) * KP + t];
+          rr[u] = Dp[(i + u) * KP + t];
+          ee[u] = e_s[i + u - 1];
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -610,51 +622,51 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
           rprev = rr[u];
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (i0 + u < N) X[(i0 + u) * KP + t] = xx[u];
+        for (int u = 0; u < CH; ++u) X[(i + u) * KP + t] = xx[u];
+      }
+      for (; i < N; ++i) {
+        const double ri = Dp[i * KP + t];
+        y = X[i * KP + t] - (e_s[i - 1] * rprev) * y;
+        X[i * KP + t] = y;
+        rprev = ri;
       }
       // backward: x_i = (y_i - e_i x_{i+1}) / D_i
       double xn = X[(N - 1) * KP + t] * Dp[(N - 1) * KP + t];
       X[(N - 1) * KP + t] = xn;
       double mx = fabs(xn);
-      for (int i0 = N - 2; i0 >= 0; i0 -= CH) {
+      i = N - 2;
+      for (; i - CH + 1 >= 0; i -= CH) {
         double yy[CH], rr[CH], ee[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-          const int i = max(i0 - u, 0);
-          yy[u] = X[i * KP + t];
-          rr[u] = Dp[i * KP + t];
-          ee[u] = e_s[i];
+          yy[u] = X[(i - u) * KP + t];
+          rr[u] = Dp[(i - u) * KP + t];
+          ee[u] = e_s[i - u];
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (i0 - u >= 0) {
-            xn = (yy[u] - ee[u] * xn) * rr[u];
-            yy[u] = xn;
-            mx = fmax(mx, fabs(xn));
-          }
+        for (int u = 0; u < CH; ++u) {
+          xn = (yy[u] - ee[u] * xn) * rr[u];
+          yy[u] = xn;
+          mx = fmax(mx, fabs(xn));
+        }
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (i0 - u >= 0) X[(i0 - u) * KP + t] = yy[u];
+        for (int u = 0; u < CH; ++u) X[(i - u) * KP + t] = yy[u];
+      }
+      for (; i >= 0; --i) {
+        xn = (X[i * KP + t] - e_s[i] * xn) * Dp[i * KP + t];
+        X[i * KP + t] = xn;
+        mx = fmax(mx, fabs(xn));
       }
       // unit 2-norm (scaled by the largest entry first, so the squares cannot overflow)
       const double s1 = (mx > 0) ? 1.0 / mx : 1.0;
       double nn[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i0 = 0; i0 < N; i0 += CH) {
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (i0 + u < N) {
-            const double v = X[(i0 + u) * KP + t] * s1;
-            nn[u & 3] = fma(v, v, nn[u & 3]);
-          }
+      for (int r = 0; r < N; ++r) {
+        const double v = X[r * KP + t] * s1;
+        nn[r & 3] = fma(v, v, nn[r & 3]);
       }
       const double ns = (nn[0] + nn[1]) + (nn[2] + nn[3]);
       const double sc = s1 * ((ns > 0) ? 1.0 / sqrt(ns) : 0.0);
-      for (int i0 = 0; i0 < N; i0 += CH) {
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (i0 + u < N) X[(i0 + u) * KP + t] *= sc;
-      }
+      for (int r = 0; r < N; ++r) X[r * KP + t] *= sc;
     }
     __syncthreads();
     for (int cs = wave; cs < kmax; cs += NTH / 64) {

@@ -1,23 +1,27 @@
 // FP64 eigensolver of the small Gram matrix G (order N <= 128) and the truncation rule
-// (Sec. II.B; Theorem 1, App. B), as one single-work-group kernel on the serial path between
-// the Gram and projection GEMMs.
+// (Sec. II.B; Theorem 1, App. B) on the serial path between the Gram and projection GEMMs: a
+// single-work-group kernel (steps 1-5) and a short multi-work-group back-transform (step 6).
 //
 //  1. Assemble G from S = X^H X and the Kraus set, G_{(a,v),(b,w)} = sum_{uv'} (E_a^H E_b)_{uv'}
-//     S_{(u,v),(v',w)} (split view) or G = S (plain view).  G lives in registers: a grid of
-//     (32 BC / BR) x 32 threads holds BR x BC blocks (N <= 32 BC), so a row of blocks is one
-//     half-wave.
+//     S_{(u,v),(v',w)} (split view) or G = S (plain view).  G lives in registers: half-wave R
+//     holds rows R + NH a (a < BR, NH half-waves) and lane Cc of it columns BC Cc .. BC Cc + BC - 1
+//     (N <= 32 BC), so each row is spread over one half-wave.
 //  2. Householder reduction to a real symmetric tridiagonal T = Q^H G Q with reflectors
 //     H_j = I - tau_j v_j v_j^H, v_j(j+1) = 1.  Every half-wave forms the reflector from the
-//     broadcast column, the matrix-vector product reduces across a half-wave with shuffles, and
-//     the rank-2 update is register arithmetic: two barriers per step.
-//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a group of 8 or 16
+//     broadcast column, the matrix-vector product reduces across a half-wave with lane swaps and
+//     DPP moves, and the rank-2 update is register arithmetic on the rows not yet eliminated:
+//     two barriers per step.  At order 128 the last 64 steps run on the trailing block moved to
+//     a layout with a quarter of the registers per thread.
+//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a group of up to 16
 //     lanes per eigenvalue).
 //  4. Eigenvectors of T by inverse iteration on the LDL^T factorisation of T - lambda I (one
 //     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than 1e-9 ||T|| form
 //     clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending order)
 //     after every iteration, so (near-)degenerate eigenvalues yield an orthonormal basis.
 //  5. The rank rule (cap r, threshold eps, tie policy), discarded mass and renormalisation
-//     scale; back-transform V = Q Y; the projection matrix in the bulk precision:
+//     scale.  The reflectors, their scalars and the kept eigenvectors of T go to the workspace.
+//  6. A second kernel over 16 work-groups (one wave per kept eigenvector) back-transforms
+//     V = Q Y and writes the projection matrix in the bulk precision:
 //     W_{(b,v),(b',j)} = c sum_a (E_a)_{b'b} V[(a,v), j] (split view) or W = c V_k (plain).
 #include <math.h>
 
@@ -50,6 +54,12 @@ __device__ __forceinline__ double dpp_mov(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+// value of v in lane l (uniform)
+__device__ __forceinline__ double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 // v + v(lane ^ 16) and v + v(lane ^ 32) by the lane-swap moves (permlane16/32_swap): the two
 // results of a swap of v with itself are v and its partner, in an order that depends on the lane.
 __device__ __forceinline__ double xor16_sum(double v) {
@@ -73,10 +83,6 @@ __device__ __forceinline__ double gsum(double v) {
   return v;
 }
 
-__device__ __forceinline__ double read_lane(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
 // Sums of a and of b over the 64 lanes of a wave, returned in every lane.  Transposing: the
 // 32-lane swap leaves lanes 0-31 with pair sums of a and lanes 32-63 with pair sums of b, the
 // half-waves reduce those by DPP and the 16-lane swap, and the totals are read from lanes 0 and 32.
@@ -156,11 +162,15 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// LDS operands of the tridiagonalisation steps
+// LDS operands of the tridiagonalisation steps.  The per-step vectors are double-buffered by
+// step parity (buffer p at offset p * ld), so one barrier per step orders the writes of step
+// j + 1's operands after every read of step j's.
 struct TriSmem {
-  z64* col_buf;   // column jl of the trailing matrix being reduced (local row index)
+  z64* col_buf;   // column 0 of the (trailing) matrix, for the first reflector of a stage
   z64* vbuf;      // reflector v (local index)
   z64* pbuf;      // s = A v (local index)
+  z64* cola;      // column jl + 1 of the matrix before update jl (local index)
+  int ld;         // stride between the two parities
   double* d_s;    // diagonal of T (global index)
   double* e_s;    // off-diagonal of T (global index)
   double* tau_s;  // reflector scalars (global index, interleaved)
@@ -217,30 +227,33 @@ __device__ __forceinline__ double tsum_halfwave(double (&v)[NV], int Cc) {
   return r;
 }
 
-// One Householder step on the register-resident trailing matrix A: layout <BR, BC> (thread
-// (R, Cc) holds rows BR R .. BR R + BR - 1 and columns BC Cc .. BC Cc + BC - 1), local order Nl,
-// local step jl (jl % BC == BB), global step j0 + jl.  Forms the reflector from column jl
-// (every half-wave redundantly; lane Cc owns entries BC Cc + b), s = A v reduced over each
-// half-wave, the rank-2 update A -= v w^H + w v^H, and broadcasts column jl + 1.
-template <int BR, int BC, int BB>
-__device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], const int jl, const int Nl, const int j0, const int N,
-                                         const TriSmem& M) {
-  const int tid = threadIdx.x, R = tid >> 5, Cc = tid & 31;
-  const int j = j0 + jl;
-  const z64 alpha = M.col_buf[jl + 1];
-  z64 cv[BC];
+// Householder tridiagonalisation on the register-resident trailing matrix A: layout <BR, BC>
+// (thread (R, Cc) holds rows R + NH a, NH = 32 BC / BR, and columns BC Cc + b), local order
+// Nl, local step jl, global step j0 + jl.  Every half-wave forms each reflector redundantly
+// (lane Cc owns entries BC Cc + b); rows in the eliminated part (rows <= jl) skip their
+// arithmetic, and with the rows of a half-wave spread over the whole matrix that work shrinks
+// evenly on every SIMD.
+
+// Reflector of local step jl from the column entries cv[b] = A(BC Cc + b, jl), alpha =
+// A(jl + 1, jl) and diag = Re A(jl, jl): H = I - tau v v^H with v(jl + 1) = 1 maps the column
+// below the diagonal to (beta, 0, ..., 0).  Publishes v (parity par), the packed entries, d_j,
+// e_j = beta and tau_j; returns this lane's entries of v and tau.
+template <int BC>
+__device__ __forceinline__ void tri_reflector(const z64 (&cv)[BC], const z64 alpha, const double diag, const int jl,
+                                              const int Nl, const int j, const int N, const TriSmem& M,
+                                              const int par, z64 (&vloc)[BC], z64& tau) {
+  const int tid = threadIdx.x, Cc = tid & 31;
   double xn2 = 0;
 #pragma unroll
   for (int b = 0; b < BC; ++b) {
     const int i = BC * Cc + b;
-    cv[b] = M.col_buf[i];
     if (i > jl + 1 && i < Nl) xn2 += cv[b].x * cv[b].x + cv[b].y * cv[b].y;
   }
   xn2 = gsum<32>(xn2);
   double beta = alpha.x;
-  z64 tau = zmk(0, 0), sc = zmk(0, 0);
-  const bool trivial = (xn2 == 0.0 && alpha.y == 0.0);
-  if (!trivial) {
+  tau = zmk(0, 0);
+  z64 sc = zmk(0, 0);
+  if (!(xn2 == 0.0 && alpha.y == 0.0)) {
     // 1 / ||x|| from the hardware reciprocal square root refined by two Newton steps, and
     // 1 / |alpha - beta|^2 by the refined reciprocal (short dependency chains; a few ulp)
     const double n2 = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2));
@@ -256,7 +269,6 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], const int jl, const i
     const double iden = rcp_nr(fma(dr, dr, di * di));
     sc = zmk(dr * iden, -di * iden);
   }
-  z64 (&vloc)[BC] = cv;   // v overwrites the column entries it is built from
 #pragma unroll
   for (int b = 0; b < BC; ++b) {
     const int i = BC * Cc + b;
@@ -266,37 +278,59 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], const int jl, const i
 #pragma unroll
     for (int b = 0; b < BC; ++b) {
       const int i = BC * Cc + b;
-      M.vbuf[i] = vloc[b];
+      M.vbuf[par * M.ld + i] = vloc[b];
       if (i >= jl + 2 && i < Nl) M.Rf[refl_off(j, N) + (i - jl - 2)] = vloc[b];
     }
     if (tid == 0) {
-      M.d_s[j] = M.col_buf[jl].x;
+      M.d_s[j] = diag;
       M.e_s[j] = beta;
       M.tau_s[2 * j] = tau.x;
       M.tau_s[2 * j + 1] = tau.y;
     }
   }
-  // s = A v for this thread's rows, reduced over the half-wave (pbuf holds s; p = tau s);
-  // row blocks that lie entirely in the eliminated part (rows <= jl) only publish zeros
-  const bool live = BR * R + BR - 1 > jl;   // uniform over the half-wave
-  if (live) {
+}
+
+// s = A v for this thread's rows, reduced over the half-wave, into pbuf (parity par); rows in
+// the eliminated part publish zeros.
+template <int BR, int BC>
+__device__ __forceinline__ void tri_matvec(const z64 (&A)[BR][BC], const z64 (&vloc)[BC], const int jl, const int Nl,
+                                           const TriSmem& M, const int par) {
+  const int tid = threadIdx.x, R = tid >> 5, Cc = tid & 31;
+  constexpr int NH = 32 * BC / BR;
+  z64* pb = M.pbuf + par * M.ld;
+  bool lv[BR];
+#pragma unroll
+  for (int a = 0; a < BR; ++a) lv[a] = R + NH * a > jl;   // uniform over the half-wave
+  if (lv[BR - 1]) {
     if constexpr (BR == 8 || BR == 4) {
       constexpr int NV = 2 * BR;
       double vv[NV];
 #pragma unroll
       for (int a = 0; a < BR; ++a) {
-        z64 s = zmul(A[a][0], vloc[0]);
+        // s_a = sum_b A[a][b] v_b as one FMA chain per component
+        double sx = 0.0, sy = 0.0;
+        if (lv[a]) {
+          sx = A[a][0].x * vloc[0].x;
+          sy = A[a][0].x * vloc[0].y;
+          sx = fma(-A[a][0].y, vloc[0].y, sx);
+          sy = fma(A[a][0].y, vloc[0].x, sy);
 #pragma unroll
-        for (int b = 1; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
-        vv[2 * a] = s.x;
-        vv[2 * a + 1] = s.y;
+          for (int b = 1; b < BC; ++b) {
+            sx = fma(A[a][b].x, vloc[b].x, sx);
+            sy = fma(A[a][b].x, vloc[b].y, sy);
+            sx = fma(-A[a][b].y, vloc[b].y, sx);
+            sy = fma(A[a][b].y, vloc[b].x, sy);
+          }
+        }
+        vv[2 * a] = sx;
+        vv[2 * a + 1] = sy;
       }
       const double r = tsum_halfwave<NV>(vv, Cc);
       constexpr int SH = (NV == 16) ? 1 : 2;   // lane Cc holds value Cc >> SH
       if ((Cc & ((1 << SH) - 1)) == 0) {
         const int val = Cc >> SH;
-        const int i = BR * R + (val >> 1);
-        reinterpret_cast<double*>(M.pbuf)[2 * i + (val & 1)] = (i > jl && i < Nl) ? r : 0.0;
+        const int i = R + NH * (val >> 1);
+        reinterpret_cast<double*>(pb)[2 * i + (val & 1)] = (i > jl && i < Nl) ? r : 0.0;
       }
     } else {
 #pragma unroll
@@ -306,43 +340,121 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], const int jl, const i
         for (int b = 0; b < BC; ++b) s = zadd(s, zmul(A[a][b], vloc[b]));
         s.x = gsum<32>(s.x);
         s.y = gsum<32>(s.y);
-        const int i = BR * R + a;
-        if (Cc == 0) M.pbuf[i] = (i > jl && i < Nl) ? s : zmk(0, 0);
+        const int i = R + NH * a;
+        if (Cc == 0) pb[i] = (i > jl && i < Nl) ? s : zmk(0, 0);
       }
     }
   } else if (Cc == 0) {
 #pragma unroll
-    for (int a = 0; a < BR; ++a) M.pbuf[BR * R + a] = zmk(0, 0);
+    for (int a = 0; a < BR; ++a) pb[R + NH * a] = zmk(0, 0);
+  }
+}
+
+// First reflector of a stage (local step 0) from the column in col_buf, its s = A v, and the
+// next column before the update; one barrier.
+template <int BR, int BC>
+__device__ __forceinline__ void tri_prologue(const z64 (&A)[BR][BC], const int Nl, const int j0, const int N,
+                                             const TriSmem& M, z64 (&vloc)[BC], z64& tau) {
+  const int tid = threadIdx.x, R = tid >> 5, Cc = tid & 31;
+  constexpr int NH = 32 * BC / BR;
+  z64 cv[BC];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) cv[b] = M.col_buf[BC * Cc + b];
+  tri_reflector<BC>(cv, M.col_buf[1], M.col_buf[0].x, 0, Nl, j0, N, M, 0, vloc, tau);
+  tri_matvec<BR, BC>(A, vloc, 0, Nl, M, 0);
+  if (Cc == 1 / BC) {
+#pragma unroll
+    for (int a = 0; a < BR; ++a) M.cola[R + NH * a] = A[a][1 % BC];
   }
   __syncthreads();
-  // p = tau s; alpha2 = -1/2 tau (p^H v); w = p + alpha2 v; A -= v w^H + w v^H
+}
+
+// Local step jl (jl % BC == BB), after the barrier that published v_jl, s = A v_jl and column
+// jl + 1: p = tau s, alpha2 = -1/2 tau (p^H v), w = p + alpha2 v, A -= v w^H + w v^H.  Then,
+// with prep, the updated column jl + 1 is rebuilt from the published copy (every half-wave, no
+// second barrier), reflector jl + 1 is formed (independent of the update, so the two overlap),
+// column jl + 2 is published and s = A v_{jl+1} computed; with last, only the last diagonal
+// entry of T is recorded.  One barrier.
+template <int BR, int BC, int BB>
+__device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], z64 (&vloc)[BC], z64& tau, const int jl, const int Nl,
+                                         const int j0, const int N, const TriSmem& M, const bool prep,
+                                         const bool last) {
+  const int tid = threadIdx.x, R = tid >> 5, Cc = tid & 31;
+  constexpr int NH = 32 * BC / BR;
+  const int par = jl & 1, nxt = par ^ 1;
+  const z64* pb = M.pbuf + par * M.ld;
+  const z64* vb = M.vbuf + par * M.ld;
   z64 dt = zmk(0, 0);
   z64 pcol[BC];
 #pragma unroll
   for (int b = 0; b < BC; ++b) {
-    pcol[b] = zmul(tau, M.pbuf[BC * Cc + b]);
+    pcol[b] = zmul(tau, pb[BC * Cc + b]);
     dt = zadd(dt, zcmul(pcol[b], vloc[b]));
   }
   dt.x = gsum<32>(dt.x);
   dt.y = gsum<32>(dt.y);
   const z64 alpha2 = zscale(zmul(tau, dt), -0.5);
-  if (live) {
+  z64 wc[BC];
 #pragma unroll
-    for (int a = 0; a < BR; ++a) {
-      const z64 vr = M.vbuf[BR * R + a];
-      const z64 wr = zadd(zmul(tau, M.pbuf[BR * R + a]), zmul(alpha2, vr));
+  for (int b = 0; b < BC; ++b) wc[b] = zadd(pcol[b], zmul(alpha2, vloc[b]));
+#pragma unroll
+  for (int a = 0; a < BR; ++a) {
+    if (R + NH * a > jl) {   // uniform over the half-wave
+      const z64 vr = vb[R + NH * a];
+      const z64 wr = zadd(zmul(tau, pb[R + NH * a]), zmul(alpha2, vr));
+      // A -= vr conj(wc) + wr conj(v): four FMAs per component
 #pragma unroll
       for (int b = 0; b < BC; ++b) {
-        const z64 wc = zadd(pcol[b], zmul(alpha2, vloc[b]));
-        A[a][b] = zsub(A[a][b], zadd(zmul(vr, zconj(wc)), zmul(wr, zconj(vloc[b]))));
+        double ax = A[a][b].x, ay = A[a][b].y;
+        ax = fma(-vr.x, wc[b].x, ax);
+        ay = fma(-vr.y, wc[b].x, ay);
+        ax = fma(-vr.y, wc[b].y, ax);
+        ay = fma(vr.x, wc[b].y, ay);
+        ax = fma(-wr.x, vloc[b].x, ax);
+        ay = fma(-wr.y, vloc[b].x, ay);
+        ax = fma(-wr.y, vloc[b].y, ax);
+        ay = fma(wr.x, vloc[b].y, ay);
+        A[a][b] = zmk(ax, ay);
       }
     }
   }
-  // owners of column jl + 1 broadcast it for the next step
-  if (Cc == (jl + 1) / BC) {
-    constexpr int bsel = (BB + 1) % BC;
+  if (prep || last) {
+    // column jl + 1 after this update at rows BC Cc + b (the same arithmetic as the update)
+    const z64 v1 = vb[jl + 1];
+    const z64 w1 = zadd(zmul(tau, pb[jl + 1]), zmul(alpha2, v1));
+    const z64* ca = M.cola + par * M.ld;
+    z64 c[BC];
 #pragma unroll
-    for (int a = 0; a < BR; ++a) M.col_buf[BR * R + a] = A[a][bsel];
+    for (int b = 0; b < BC; ++b) {
+      double cx = ca[BC * Cc + b].x, cy = ca[BC * Cc + b].y;
+      cx = fma(-vloc[b].x, w1.x, cx);
+      cy = fma(-vloc[b].y, w1.x, cy);
+      cx = fma(-vloc[b].y, w1.y, cx);
+      cy = fma(vloc[b].x, w1.y, cy);
+      cx = fma(-wc[b].x, v1.x, cx);
+      cy = fma(-wc[b].y, v1.x, cy);
+      cx = fma(-wc[b].y, v1.y, cx);
+      cy = fma(wc[b].x, v1.y, cy);
+      c[b] = zmk(cx, cy);
+    }
+    constexpr int bd = (BB + 1) % BC, ba = (BB + 2) % BC;
+    const double diag = read_lane(c[bd].x, (jl + 1) / BC);
+    if (last) {
+      if (tid == 0) M.d_s[j0 + jl + 1] = diag;
+    } else {
+      const int la = (jl + 2) / BC;
+      const z64 alpha = zmk(read_lane(c[ba].x, la), read_lane(c[ba].y, la));
+      z64 vn[BC], tn;
+      tri_reflector<BC>(c, alpha, diag, jl + 1, Nl, j0 + jl + 1, N, M, nxt, vn, tn);
+      if (Cc == la) {
+#pragma unroll
+        for (int a = 0; a < BR; ++a) M.cola[nxt * M.ld + R + NH * a] = A[a][ba];
+      }
+      tri_matvec<BR, BC>(A, vn, jl + 1, Nl, M, nxt);
+#pragma unroll
+      for (int b = 0; b < BC; ++b) vloc[b] = vn[b];
+      tau = tn;
+    }
   }
   __syncthreads();
 }
@@ -355,14 +467,15 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   constexpr int NTH = 32 * (NP / BR);    // threads
   extern __shared__ __attribute__((aligned(16))) double dyn[];   // phase-dependent scratch
   __shared__ z64 Mab[64];
-  __shared__ z64 col_buf[NP], vbuf[NP], pbuf[NP];
+  __shared__ z64 col_buf[NP], vbuf[2 * NP], pbuf[2 * NP], cola[2 * NP];
   __shared__ double d_s[NP], e_s[NP], e2_s[NP], lam_s[NP + 1], tau_s[2 * NP], trp[32];
   __shared__ int cl_start[NP], cl_len[NP];
   __shared__ double sc_s[4];
   __shared__ int k_s;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int R = tid >> 5, Cc = tid & 31;   // block row / block column of this thread
+  const int R = tid >> 5, Cc = tid & 31;   // half-wave / lane in it
+  constexpr int NH = NP / BR;              // half-waves; thread rows R + NH a, columns BC Cc + b
   const int m = (nsplit == 2) ? ch.m : 1;
 
   // ---------------------------------------------------------------- 1. assemble G
@@ -379,7 +492,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   for (int a = 0; a < BR; ++a)
 #pragma unroll
     for (int b = 0; b < BC; ++b) {
-      const int i = BR * R + a, j = BC * Cc + b;
+      const int i = R + NH * a, j = BC * Cc + b;
       z64 g = zmk(0, 0);
       if (i < N && j < N) {
         if (nsplit == 2) {
@@ -401,15 +514,17 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     double t = 0;
 #pragma unroll
     for (int a = 0; a < BR; ++a) {
-      const int i = BR * R + a;
-      if (i / BC == Cc) t += A[a][a % BC].x;   // BR is a multiple of BC
+      const int i = R + NH * a;
+#pragma unroll
+      for (int b = 0; b < BC; ++b)
+        if (i == BC * Cc + b) t += A[a][b].x;
     }
     t = gsum<32>(t);
     if (Cc == 0) trp[R] = t;
   }
   if (Cc == 0) {
 #pragma unroll
-    for (int a = 0; a < BR; ++a) col_buf[BR * R + a] = A[a][0];
+    for (int a = 0; a < BR; ++a) col_buf[R + NH * a] = A[a][0];
   }
   __syncthreads();
   if (tid == 0) {
@@ -427,19 +542,26 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   // through the freed LDS.
   z64* Rf = reinterpret_cast<z64*>(dyn);
   double* refl = B.P;
-  const TriSmem M{col_buf, vbuf, pbuf, d_s, e_s, tau_s, Rf};
+  const TriSmem M{col_buf, vbuf, pbuf, cola, NP, d_s, e_s, tau_s, Rf};
   constexpr bool kShrink = (BR == 8 && BC == 4);
-  const int jsw = (kShrink && N > 64) ? N - 64 : N - 1;   // steps on the full layout
-  for (int jb = 0; jb < jsw; jb += BC) {
-    static_for<BC>([&](auto bbc) {
-      const int j = jb + decltype(bbc)::value;
-      if (j < jsw) tri_step<BR, BC, decltype(bbc)::value>(A, j, N, 0, N, M);
-    });
+  const bool shrink = kShrink && N > 64;
+  const int jsw = shrink ? N - 64 : N - 1;   // updates on the full layout
+  if (N >= 2) {
+    z64 vl[BC], tau;
+    tri_prologue<BR, BC>(A, N, 0, N, M, vl, tau);
+    for (int jb = 0; jb < jsw; jb += BC) {
+      static_for<BC>([&](auto bbc) {
+        const int jl = jb + decltype(bbc)::value;
+        if (jl < jsw)
+          tri_step<BR, BC, decltype(bbc)::value>(A, vl, tau, jl, N, 0, N, M, jl + 1 < jsw, !shrink && jl + 2 == N);
+      });
+    }
+  } else if (tid == 0) {
+    d_s[0] = col_buf[0].x;
   }
   int spilled = 0;   // reflector entries already in the workspace
-  int cb0 = 0;       // global index of col_buf entry 0
   if constexpr (kShrink) {
-    if (N > 64) {
+    if (shrink) {
       spilled = refl_off(jsw, N);
       for (int e = tid; e < spilled; e += NTH) {
         refl[2 * e] = Rf[e].x;
@@ -451,7 +573,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
       for (int a = 0; a < BR; ++a)
 #pragma unroll
         for (int b = 0; b < BC; ++b) {
-          const int i = BR * R + a, jj = BC * Cc + b;
+          const int i = R + NH * a, jj = BC * Cc + b;
           if (i >= jsw && jj >= jsw && i < N && jj < N) Sg[(i - jsw) * 64 + (jj - jsw)] = A[a][b];
         }
       __syncthreads();
@@ -459,25 +581,23 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) A2[a][b] = Sg[(4 * R + a) * 64 + 2 * Cc + b];
+        for (int b = 0; b < 2; ++b) A2[a][b] = Sg[(R + 16 * a) * 64 + 2 * Cc + b];
       if (Cc == 0) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) col_buf[4 * R + a] = A2[a][0];
+        for (int a = 0; a < 4; ++a) col_buf[R + 16 * a] = A2[a][0];
       }
       __syncthreads();   // the staging is read before the steps write reflectors over it
+      z64 vl2[2], tau2;
+      tri_prologue<4, 2>(A2, 64, jsw, N, M, vl2, tau2);
       for (int jb = 0; jb < 63; jb += 2) {
         static_for<2>([&](auto bbc) {
           const int jl = jb + decltype(bbc)::value;
-          if (jl < 63) tri_step<4, 2, decltype(bbc)::value>(A2, jl, 64, jsw, N, M);
+          if (jl < 63) tri_step<4, 2, decltype(bbc)::value>(A2, vl2, tau2, jl, 64, jsw, N, M, jl + 1 < 63, jl == 62);
         });
       }
-      cb0 = jsw;
     }
   }
-  if (tid == 0) {
-    d_s[N - 1] = col_buf[N - 1 - cb0].x;
-    e_s[N - 1] = 0.0;
-  }
+  if (tid == 0) e_s[N - 1] = 0.0;
   const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
   for (int e = spilled + tid; e < nref; e += NTH) {
     refl[2 * e] = Rf[e].x;
@@ -511,10 +631,15 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   }
   __syncthreads();
   {
-    int G = 16;   // lanes per eigenvalue: the largest power of two <= 16 with G kmax <= NTH
-    while (G * kmax > NTH) G >>= 1;
-    const int t = tid / G, g = tid % G;
-    const bool active = (t < kmax) && !zero;
+    // G lanes per eigenvalue: the largest G <= 16 whose groups (64 / G per wave, never across
+    // waves; left-over lanes idle) cover the kmax eigenvalues
+    int G = 16;
+    while (G > 1 && (64 / G) * (NTH / 64) < kmax) --G;
+    const int gpw = 64 / G;
+    const int gi = lane / G;
+    const int t = wave * gpw + gi, g = lane - gi * G;
+    const bool mine = gi < gpw && t < kmax;
+    const bool active = mine && !zero;
     const int asc = N - 1 - t;
     // G-section: lane g counts at the interior point g + 1 of G + 1 equal sections.  Without a
     // record the bracket stops at an absolute width of 4 eps (eigenvalues to ||T|| eps, what the
@@ -529,17 +654,17 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
       const double x = lo + w * (double)(g + 1) / (double)(G + 1);
       const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
       const unsigned long long ball = __ballot(active && !done && cnt > asc);
-      const int gb = lane & ~(G - 1);
+      const int gb = gi * G;
       const unsigned long long grp = (ball >> gb) & ((1ull << G) - 1ull);
       const int first = grp ? (__ffsll((long long)grp) - 1) : G;
-      const double xh = __shfl(x, gb + (first < G ? first : 0), 64);
-      const double xl = __shfl(x, gb + (first == 0 ? 0 : first - 1), 64);
+      const double xh = __shfl(x, min(gb + (first < G ? first : 0), 63), 64);
+      const double xl = __shfl(x, min(gb + (first == 0 ? 0 : first - 1), 63), 64);
       if (active && !done) {
         if (first < G) hi = xh;
         if (first > 0) lo = xl;
       }
     }
-    if (g == 0 && t < kmax) lam_s[t] = active ? 0.5 * (lo + hi) : 0.0;
+    if (g == 0 && mine) lam_s[t] = active ? 0.5 * (lo + hi) : 0.0;
   }
   __syncthreads();
   if (tid == 0) {

@@ -8,38 +8,66 @@
 
 namespace lrdm {
 
-// C = op(A) B for n x n complex FP64 matrices (row-major, interleaved), op = identity or ^H;
-// with herm = 1 the Hermitian part (C + C^H) / 2 of the product is stored.
-__global__ __launch_bounds__(256) void small_zgemm(const double* __restrict__ A, int opA_h,
-                                                   const double* __restrict__ B, double* __restrict__ C,
-                                                   int n, int herm) {
+// C = op(A) B for n x n complex FP64 matrices (row-major, interleaved; n a multiple of 16), op =
+// identity or ^H.  A 16 x 16 tile of C per work-group: 16 rows of op(A) and 16 columns of B are
+// staged through LDS in K chunks of 64, and each thread accumulates one entry over two
+// interleaved partial sums.
+constexpr int kZT = 16, kZK = 64;
+__global__ __launch_bounds__(256) void small_zgemm(const double2* __restrict__ A, int opA_h,
+                                                   const double2* __restrict__ B, double2* __restrict__ C, int n) {
+  __shared__ double2 As[kZT][kZK + 1];
+  __shared__ double2 Bs[kZK][kZT + 1];
+  const int tid = threadIdx.x, ti = tid / kZT, tj = tid % kZT;
+  const int I = blockIdx.y * kZT, J = blockIdx.x * kZT;
+  double sr0 = 0, si0 = 0, sr1 = 0, si1 = 0;
+  for (int k0 = 0; k0 < n; k0 += kZK) {
+    const int kc = min(kZK, n - k0);
+    for (int e = tid; e < kZT * kZK; e += 256) {
+      if (opA_h) {   // (A^H)[I + r][k] = conj(A[k][I + r]): consecutive threads read consecutive r
+        const int r = e % kZT, k = e / kZT;
+        if (k < kc) {
+          const double2 v = A[(size_t)(k0 + k) * n + I + r];
+          As[r][k] = make_double2(v.x, -v.y);
+        }
+      } else {
+        const int r = e / kZK, k = e % kZK;
+        if (k < kc) As[r][k] = A[(size_t)(I + r) * n + k0 + k];
+      }
+      const int k = e / kZT, c = e % kZT;
+      if (k < kc) Bs[k][c] = B[(size_t)(k0 + k) * n + J + c];
+    }
+    __syncthreads();
+    for (int k = 0; k + 1 < kc; k += 2) {
+      const double2 a0 = As[ti][k], b0 = Bs[k][tj], a1 = As[ti][k + 1], b1 = Bs[k + 1][tj];
+      sr0 = fma(a0.x, b0.x, fma(-a0.y, b0.y, sr0));
+      si0 = fma(a0.x, b0.y, fma(a0.y, b0.x, si0));
+      sr1 = fma(a1.x, b1.x, fma(-a1.y, b1.y, sr1));
+      si1 = fma(a1.x, b1.y, fma(a1.y, b1.x, si1));
+    }
+    if (kc & 1) {
+      const double2 a0 = As[ti][kc - 1], b0 = Bs[kc - 1][tj];
+      sr0 = fma(a0.x, b0.x, fma(-a0.y, b0.y, sr0));
+      si0 = fma(a0.x, b0.y, fma(a0.y, b0.x, si0));
+    }
+    __syncthreads();
+  }
+  C[(size_t)(I + ti) * n + J + tj] = make_double2(sr0 + sr1, si0 + si1);
+}
+
+// S = (S + S^H) / 2 in place (one thread per entry pair i <= j)
+__global__ __launch_bounds__(256) void hermitian_part(double2* __restrict__ S, int n) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n * n) return;
   const int i = e / n, j = e % n;
-  auto entry = [&](int r, int c) {
-    double sr = 0, si = 0;
-    for (int k = 0; k < n; ++k) {
-      double ar, ai;
-      if (opA_h) {   // (A^H)[r][k] = conj(A[k][r])
-        ar = A[2 * (k * n + r)];
-        ai = -A[2 * (k * n + r) + 1];
-      } else {
-        ar = A[2 * (r * n + k)];
-        ai = A[2 * (r * n + k) + 1];
-      }
-      const double br = B[2 * (k * n + c)], bi = B[2 * (k * n + c) + 1];
-      sr += ar * br - ai * bi;
-      si += ar * bi + ai * br;
-    }
-    return make_double2(sr, si);
-  };
-  double2 v = entry(i, j);
-  if (herm) {
-    const double2 t = entry(j, i);
-    v = make_double2(0.5 * (v.x + t.x), 0.5 * (v.y - t.y));
+  if (i > j) return;
+  if (i == j) {
+    S[(size_t)i * n + i].y = 0.0;
+    return;
   }
-  C[2 * e] = v.x;
-  C[2 * e + 1] = v.y;
+  const double2 a = S[(size_t)i * n + j], b = S[(size_t)j * n + i];
+  const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  S[(size_t)i * n + j] = h;
+  S[(size_t)j * n + i] = make_double2(h.x, -h.y);
 }
 
 template <class T>
@@ -57,19 +85,24 @@ __global__ __launch_bounds__(256) void copy_cast(const double* __restrict__ src,
 }
 
 hipError_t launch_chain_gram(double* S, const double* W, double* tmp, int n, hipStream_t s) {
-  if (n < 1 || n > 256) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((n * n + 255) / 256);
-  hipLaunchKernelGGL(small_zgemm, dim3(blocks), dim3(256), 0, s, S, 0, W, tmp, n, 0);   // tmp = S W
-  hipLaunchKernelGGL(small_zgemm, dim3(blocks), dim3(256), 0, s, W, 1, tmp, S, n, 1);   // S = herm(W^H tmp)
+  if (n < kZT || n > 256 || n % kZT) return hipErrorInvalidValue;
+  const dim3 grid(n / kZT, n / kZT);
+  auto* S2 = reinterpret_cast<double2*>(S);
+  auto* T2 = reinterpret_cast<double2*>(tmp);
+  const auto* W2 = reinterpret_cast<const double2*>(W);
+  hipLaunchKernelGGL(small_zgemm, grid, dim3(256), 0, s, S2, 0, W2, T2, n);   // tmp = S W
+  hipLaunchKernelGGL(small_zgemm, grid, dim3(256), 0, s, W2, 1, T2, S2, n);   // S = W^H tmp
+  hipLaunchKernelGGL(hermitian_part, dim3((n * n + 255) / 256), dim3(256), 0, s, S2, n);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_chain_compose(double* Wp, const double* Wn, double* tmp, cx_t<T>* Wt, int n, hipStream_t s) {
-  if (n < 1 || n > 256) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((n * n + 255) / 256);
-  hipLaunchKernelGGL(small_zgemm, dim3(blocks), dim3(256), 0, s, Wp, 0, Wn, tmp, n, 0);  // tmp = Wp Wn
-  hipLaunchKernelGGL(copy_cast<T>, dim3(blocks), dim3(256), 0, s, tmp, Wp, Wt, n * n);
+  if (n < kZT || n > 256 || n % kZT) return hipErrorInvalidValue;
+  const dim3 grid(n / kZT, n / kZT);
+  hipLaunchKernelGGL(small_zgemm, grid, dim3(256), 0, s, reinterpret_cast<const double2*>(Wp), 0,
+                     reinterpret_cast<const double2*>(Wn), reinterpret_cast<double2*>(tmp), n);   // tmp = Wp Wn
+  hipLaunchKernelGGL(copy_cast<T>, dim3((n * n + 255) / 256), dim3(256), 0, s, tmp, Wp, Wt, n * n);
   return hipGetLastError();
 }
 

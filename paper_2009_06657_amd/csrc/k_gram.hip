@@ -253,7 +253,7 @@ hipError_t launch_gram_batched(int F, const GramJob<T>* jobs, int njobs, uint32_
 int gram_blocks(int n, int nsplit) {
   const uint64_t rows = 1ull << (n - (nsplit == 2 ? 1 : 0));
   const uint64_t chunks = (rows + kGramKC - 1) / kGramKC;
-  return (int)(chunks < 512 ? chunks : 512);
+  return (int)(chunks < 256 ? chunks : 256);   // one work-group per CU at the largest size
 }
 
 template <class T, int F>
@@ -307,16 +307,26 @@ __device__ __forceinline__ void gram_reduce_body(const T* __restrict__ partials,
   const int e = threadIdx.x;
   const T* p = partials + (size_t)u * 256 + e;
   const size_t stride = (size_t)NUP * 256;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  // 16 partials per round, all loads issued before the first add (memory-level parallelism);
+  // 16 FP64 running sums, combined in a fixed order
+  constexpr int RB = 16;
+  double acc[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) acc[k] = 0.0;
   int b = 0;
-  for (; b + 4 <= nblocks; b += 4) {
-    s0 += (double)p[(size_t)(b + 0) * stride];
-    s1 += (double)p[(size_t)(b + 1) * stride];
-    s2 += (double)p[(size_t)(b + 2) * stride];
-    s3 += (double)p[(size_t)(b + 3) * stride];
+  for (; b + RB <= nblocks; b += RB) {
+    T v[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) v[k] = p[(size_t)(b + k) * stride];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) acc[k] += (double)v[k];
   }
-  for (; b < nblocks; ++b) s0 += (double)p[(size_t)b * stride];
-  const double sum = (s0 + s1) + (s2 + s3);
+  for (; b < nblocks; ++b) acc[0] += (double)p[(size_t)b * stride];
+#pragma unroll
+  for (int w = RB / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int k = 0; k < w; ++k) acc[k] += acc[k + w];
+  const double sum = acc[0];
   const int lane = e >> 2, v = e & 3;
   // 16x16x4 MFMA output layout: column lane % 16; row 4 (lane / 16) + v for FP32, but
   // 4 v + lane / 16 for FP64

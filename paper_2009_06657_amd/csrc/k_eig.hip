@@ -459,6 +459,16 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], z64 (&vloc)[BC], z64&
   __syncthreads();
 }
 
+// dynamic LDS of the eigensolver work-group: the pivots and vectors of the inverse iteration or
+// the packed reflectors, whichever is larger
+template <int BR, int BC>
+__host__ __device__ __forceinline__ size_t eig_dyn_bytes(int kmax) {
+  constexpr int NP = 32 * BC;
+  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);
+  const size_t ph2 = (size_t)(NP * (NP - 1) / 2) * 16;
+  return ph4 > ph2 ? ph4 : ph2;
+}
+
 template <int BR, int BC>
 __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, const Channel& ch, int nsplit,
                                          int c, int N, int kmax, int r_target, double eps, int tie,
@@ -487,29 +497,62 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
   }
   __syncthreads();
+  // S (Fc x Fc, FP64) is staged through LDS in blocks of rows with coalesced 16-byte loads, so
+  // every entry is read from memory once; the terms of each G entry are added in the order
+  // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1) (row blocks in increasing order).
   z64 A[BR][BC];
 #pragma unroll
   for (int a = 0; a < BR; ++a)
 #pragma unroll
-    for (int b = 0; b < BC; ++b) {
-      const int i = R + NH * a, j = BC * Cc + b;
-      z64 g = zmk(0, 0);
-      if (i < N && j < N) {
-        if (nsplit == 2) {
-          const int ai = i / c, vv = i % c, bj = j / c, w = j % c;
-          for (int u = 0; u < 2; ++u)
-            for (int v = 0; v < 2; ++v) {
-              const z64 mm = Mab[((ai * m + bj) * 2 + u) * 2 + v];
-              const size_t si = 2 * ((size_t)(u * c + vv) * Fc + (v * c + w));
-              g = zadd(g, zmul(mm, zmk(S[si], S[si + 1])));
-            }
-        } else {
-          const size_t si = 2 * ((size_t)i * Fc + j);
-          g = zmk(S[si], S[si + 1]);
+    for (int b = 0; b < BC; ++b) A[a][b] = zmk(0, 0);
+  {
+    z64* Sl = reinterpret_cast<z64*>(dyn);
+    const size_t dyn_bytes = eig_dyn_bytes<BR, BC>(kmax);
+    const int rc = max(1, min(Fc, (int)(dyn_bytes / ((size_t)Fc * sizeof(z64)))));
+    const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
+    const int cs = __ffs(c) - 1;
+    for (int r0 = 0; r0 < Fc; r0 += rc) {
+      const int rows = min(rc, Fc - r0);
+      const int cnt = rows * Fc;
+      constexpr int U = 8;
+      for (int e0 = 0; e0 < cnt; e0 += U * NTH) {
+        double2 t[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int e = e0 + k * NTH + tid;
+          t[k] = S2[(size_t)r0 * Fc + (e < cnt ? e : 0)];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int e = e0 + k * NTH + tid;
+          if (e < cnt) Sl[e] = zmk(t[k].x, t[k].y);
         }
       }
-      A[a][b] = g;
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < BR; ++a)
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int i = R + NH * a, j = BC * Cc + b;
+          if (i < N && j < N) {
+            if (nsplit == 2) {   // c is a power of two in the split view
+              const int ai = i >> cs, vv = i & (c - 1), bj = j >> cs, w = j & (c - 1);
+              for (int u = 0; u < 2; ++u) {
+                const int row = u * c + vv;
+                if (row < r0 || row >= r0 + rows) continue;
+                for (int v = 0; v < 2; ++v) {
+                  const z64 mm = Mab[((ai * m + bj) * 2 + u) * 2 + v];
+                  A[a][b] = zadd(A[a][b], zmul(mm, Sl[(row - r0) * Fc + (v * c + w)]));
+                }
+              }
+            } else if (i >= r0 && i < r0 + rows) {
+              A[a][b] = Sl[(i - r0) * Fc + j];
+            }
+          }
+        }
+      __syncthreads();
     }
+  }
   {
     double t = 0;
 #pragma unroll
@@ -687,10 +730,8 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   const int KP = kmax;
   double* Dp = dyn;              // inverse LDL^T pivots, [i * KP + t]
   double* X = dyn + NP * KP;     // vectors, [i * KP + t]
-  for (int e = tid; e < N * kmax; e += NTH) {
-    const int i = e / kmax, t = e - i * kmax;
-    X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
-  }
+  for (int i = wave; i < N; i += NTH / 64)
+    for (int t = lane; t < kmax; t += 64) X[i * KP + t] = 1.0 + hash_unit((uint32_t)t, (uint32_t)i);
   if (tid < kmax) {
     const int t = tid;
     const double sigma = lam_s[t];
@@ -860,9 +901,9 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   const int nvec = B.rec ? N : k;
   double* Y = B.Y;
   for (int e = tid; e < 2 * (N - 1); e += NTH) Y[e] = tau_s[e];
-  for (int e = tid; e < nvec * N; e += NTH) {
-    const int col = e / N, i = e - col * N;
-    Y[kEigYOff + col * kMaxEig + i] = zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col];
+  for (int col = tid / NP; col < nvec; col += NTH / NP) {   // NP is a power of two
+    const int i = tid & (NP - 1);
+    if (i < N) Y[kEigYOff + col * kMaxEig + i] = zero ? (i == col ? 1.0 : 0.0) : X[i * KP + col];
   }
   if (B.rec) {
     double* rec = B.rec;
@@ -1007,8 +1048,9 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
   using C = cx_t<T>;
   if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
+    const int cs = __ffs(c) - 1;   // c is a power of two in the split view
     for (int rw = lane; rw < rows; rw += 64) {
-      const int b = rw / c, v = rw - b * c;
+      const int b = rw >> cs, v = rw & (c - 1);
 #pragma unroll
       for (int bp = 0; bp < 2; ++bp) {
         z64 acc = zmk(0, 0);
@@ -1068,10 +1110,7 @@ __global__ __launch_bounds__(64 * kEigBtCols) void backtransform_batched(const E
 
 template <int BR, int BC>
 static size_t eig_shm(int kmax) {
-  constexpr int NP = 32 * BC;
-  const size_t ph4 = (size_t)2 * NP * kmax * sizeof(double);   // pivots and vectors
-  const size_t ph2 = (size_t)(NP * (NP - 1) / 2) * 16;         // packed reflectors
-  return ph4 > ph2 ? ph4 : ph2;
+  return eig_dyn_bytes<BR, BC>(kmax);
 }
 
 // packed reflector entries of an order-N eigensolve (at least one entry)
@@ -1134,6 +1173,7 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
                       int kmax, int r_target, double eps, int tie, int renorm, int c_out,
                       const EigBufs& b, cx_t<T>* W, hipStream_t s) {
   if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64 || c_out > 64) return hipErrorInvalidValue;
+  if (nsplit == 2 && (c < 1 || (c & (c - 1)))) return hipErrorInvalidValue;   // split view: c a power of two
   if (b.rec && (N > kRecMaxN || kmax != N)) return hipErrorInvalidValue;
   hipError_t e;
   if (N <= 32) e = launch_eig_bs<1, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);

@@ -334,15 +334,17 @@ def main():
     torch.cuda.synchronize()
 
     # The eigensolve (class 3, two kernels bracketed by one pair of events) takes the most time
-    # per step; the projection (class 4) is the MFMA-bound GEMM.  Both are timed with HIP events
-    # on the handle's stream over the timed region (one class per step; the timed steps
-    # alternate between them).
+    # per step; the projection (class 4) is the MFMA-bound GEMM and the gate pass (class 0) the
+    # HBM-bound sweep.  Each is timed with HIP events on the handle's stream over the timed
+    # region, one class per step in turn; a class no timed step covered is timed on an extra,
+    # untimed step.
     dominant = 3
-    timed = {3: [0, 0.0], 4: [0, 0.0]}
+    order = (3, 4, 0)
+    timed = {c: [0, 0.0] for c in order}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cls = 3 if i % 2 == 0 or args.steps == 1 else 4
+        cls = order[i % len(order)]
         dm.timing_begin(cls)
         zz, samples, tr = run_step(dm, prog, uniforms)
         n_, m_, t_ = dm.timing_end()
@@ -350,11 +352,12 @@ def main():
         timed[cls][1] += t_
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    if timed[4][0] == 0:   # one timed step: time the projection on an extra, untimed step
-        dm.timing_begin(4)
-        run_step(dm, prog, uniforms)
-        n_, m_, t_ = dm.timing_end()
-        timed[4] = [n_, t_]
+    for cls in order:
+        if timed[cls][0] == 0:
+            dm.timing_begin(cls)
+            run_step(dm, prog, uniforms)
+            n_, m_, t_ = dm.timing_end()
+            timed[cls] = [n_, t_]
 
     layers = args.layers * args.steps
     ms_per_step = 1e3 * elapsed / args.steps
@@ -362,9 +365,13 @@ def main():
     def roof(cls, bound, peak):
         nl, tot = timed[cls]
         mean_ms = tot / max(nl, 1)
-        achieved = algorithmic_flops(prog.n, dm.r_pad, cls) / (mean_ms * 1e-3)
-        return {"bound": bound, "kernel": CLASS_NAMES[cls], "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(cls), "launches": nl,
+        if bound == "hbm":   # a gate pass reads and writes the factor once
+            work, unit, scale = 2.0 * 2 ** prog.n * dm.r_pad * 8, "GB/s", 1e9
+        else:
+            work, unit, scale = algorithmic_flops(prog.n, dm.r_pad, cls), "TFLOP/s", 1e12
+        achieved = work / (mean_ms * 1e-3)
+        return {"bound": bound, "kernel": CLASS_NAMES[cls], "achieved": achieved / scale, "peak": peak / scale,
+                "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(cls), "launches": nl,
                 "mean_ms": mean_ms}
     out = {
         "metric": METRIC, "value": layers / elapsed, "unit": "layers/s", "n_gpus": 1,
@@ -377,6 +384,7 @@ def main():
                    "eigensolve": "f64", "trace_after": tr},
         "roofline": roof(dominant, "alu", FP64_PEAK),
         "roofline_projection": roof(4, "mfma", FP32_MFMA_PEAK),
+        "roofline_gate_pass": roof(0, "hbm", HBM_PEAK),
     }
     if not args.no_breakdown:
         br = {}

@@ -54,6 +54,23 @@ template <class T> struct RC {
   T x, y;
 };
 
+// Non-temporal HBM access of one complex value (the factor is streamed once per pass)
+template <class T> struct NtV;
+template <> struct NtV<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NtV<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <class T>
+__device__ __forceinline__ RC<T> ld_nt(const cx_t<T>* p) {
+  const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NtV<T>::type*>(p));
+  return RC<T>{v[0], v[1]};
+}
+template <class T>
+__device__ __forceinline__ void st_nt(cx_t<T>* p, RC<T> x) {
+  typename NtV<T>::type v;
+  v[0] = x.x;
+  v[1] = x.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<typename NtV<T>::type*>(p));
+}
+
 // 1q gate on register bit B of 2^R registers (all indices compile-time)
 template <int B, int R, class T>
 __device__ __forceinline__ void reg_1q(RC<T> (&x)[1 << R], const T* u) {
@@ -82,64 +99,71 @@ __device__ __forceinline__ uint32_t pick_or(int i, const uint32_t (&v)[R]) {
   return r;
 }
 
-// Apply the pass's operations phase by phase in registers.  Phase p holds, per thread, the
-// 2^R tile elements that differ only in its register slots (one group per thread, the other
-// tile-index bits come from the thread id).  Phase 0 reads from HBM and the last phase writes to
-// HBM (lanes run along the columns of a row); consecutive phases exchange data through LDS.  In
-// phase mode op_a of a 1q operation is a register bit index (0 .. R-1); only 1q and 1- or
-// 2-qubit diagonal operations occur (passes with general 2q gates or Hamming-weight phases use
-// the per-operation sweeps instead).
+// Register layout of phase ph: the thread's 2^R elements differ in the phase's register slots
+// (sh_pos: their tile offsets, sh_row: their row bits); the other tile-index bits come from the
+// thread id (pos: its tile offset, sub: the local-qubit part of its row index).
 template <class T, int R>
-__device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __restrict__ L, size_t ld,
-                                            cx_t<T>* tile, int cshift, uint32_t base,
-                                            const uint32_t* slot_off) {
+__device__ __forceinline__ void phase_layout(const GatePass<T>& P, int ph, int E, int cshift,
+                                             const uint32_t* slot_off, uint32_t& pos, uint32_t& sub,
+                                             uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
+  const uint32_t tid = threadIdx.x;
+  uint32_t rmask = 0;
+#pragma unroll
+  for (int b = 0; b < R; ++b) {
+    const int slot = P.ph_slots[ph][b];
+    sh_pos[b] = 1u << (cshift + slot);
+    sh_row[b] = 1u << P.local_q[slot];
+    rmask |= sh_pos[b];
+  }
+  const uint32_t tmask = ((1u << E) - 1u) & ~rmask;
+  uint32_t p = 0;
+  int src = 0;
+  for (int q = 0; q < E; ++q)
+    if ((tmask >> q) & 1u) {
+      p |= ((tid >> src) & 1u) << q;
+      ++src;
+    }
+  pos = p;
+  sub = slot_off[(p >> cshift) & 255u];
+}
+
+// Operations of phase ph on the registers (row_g: the row index of register 0).  In phase mode
+// op_a of a 1q operation is a register bit index (0 .. R-1); only 1q and 1- or 2-qubit diagonal
+// operations occur (passes with general 2q gates or Hamming-weight phases use the
+// per-operation sweeps instead).
+template <class T, int R>
+__device__ __forceinline__ void phase_apply(const GatePass<T>& P, int ph, RC<T> (&x)[1 << R], uint32_t row_g,
+                                            const uint32_t (&sh_row)[R]) {
   using C = RC<T>;
   constexpr int NR = 1 << R;
-  const int E = P.k + cshift;
-  const uint32_t tid = threadIdx.x;
-  const bool live = tid < (1u << (E - R));
-  C x[NR];
-  uint32_t pos = 0, row_g = 0;
-  uint32_t sh_pos[R], sh_row[R];
-
-  auto layout = [&](int ph) {
-    uint32_t rmask = 0;
-#pragma unroll
-    for (int b = 0; b < R; ++b) {
-      const int slot = P.ph_slots[ph][b];
-      sh_pos[b] = 1u << (cshift + slot);
-      sh_row[b] = 1u << P.local_q[slot];
-      rmask |= sh_pos[b];
-    }
-    const uint32_t tmask = ((1u << E) - 1u) & ~rmask;
-    uint32_t p = 0;
-    int src = 0;
-    for (int q = 0; q < E; ++q)
-      if ((tmask >> q) & 1u) {
-        p |= ((tid >> src) & 1u) << q;
-        ++src;
+  const int o0 = P.ph_first[ph], o1 = o0 + P.ph_count[ph];
+  for (int o = o0; o < o1; ++o) {
+    const T* u = P.coef + P.op_coef[o];
+    const int ty = P.op_type[o];
+    if (ty == OP_1Q) {
+      switch (P.op_a[o]) {
+        case 0: reg_1q<0, R, T>(x, u); break;
+        case 1: reg_1q<1, R, T>(x, u); break;
+        case 2: reg_1q<2, R, T>(x, u); break;
+        default: reg_1q<3, R, T>(x, u); break;
       }
-    pos = p;
-    row_g = base | slot_off[(p >> cshift) & 255u];
-  };
-  auto apply = [&](int ph) {
-    const int o0 = P.ph_first[ph], o1 = o0 + P.ph_count[ph];
-    for (int o = o0; o < o1; ++o) {
-      const T* u = P.coef + P.op_coef[o];
-      const int ty = P.op_type[o];
-      if (ty == OP_1Q) {
-        switch (P.op_a[o]) {
-          case 0: reg_1q<0, R, T>(x, u); break;
-          case 1: reg_1q<1, R, T>(x, u); break;
-          case 2: reg_1q<2, R, T>(x, u); break;
-          default: reg_1q<3, R, T>(x, u); break;
+    } else {
+      // OP_DIAG1 / OP_DIAG2: the (at most four) phases are uniform; each element selects one
+      const int qa = P.op_a[o], qb = (ty == OP_DIAG2) ? P.op_b[o] : P.op_a[o];
+      const C d0{u[0], u[1]}, d1{u[2], u[3]};
+      const C d2{(ty == OP_DIAG2) ? u[4] : u[0], (ty == OP_DIAG2) ? u[5] : u[1]};
+      const C d3{(ty == OP_DIAG2) ? u[6] : u[2], (ty == OP_DIAG2) ? u[7] : u[3]};
+      if (d0.y == 0 && d1.y == 0 && d2.y == 0 && d3.y == 0) {
+        // real phases (CZ, sign flips): a real scale per element
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+          const uint32_t row = row_g | pick_or<R>(i, sh_row);
+          const bool ba = (row >> qa) & 1u, bb = (row >> qb) & 1u;
+          const T pr = bb ? (ba ? d3.x : d2.x) : (ba ? d1.x : d0.x);
+          x[i].x *= pr;
+          x[i].y *= pr;
         }
       } else {
-        // OP_DIAG1 / OP_DIAG2: the (at most four) phases are uniform; each element selects one
-        const int qa = P.op_a[o], qb = (ty == OP_DIAG2) ? P.op_b[o] : P.op_a[o];
-        const C d0{u[0], u[1]}, d1{u[2], u[3]};
-        const C d2{(ty == OP_DIAG2) ? u[4] : u[0], (ty == OP_DIAG2) ? u[5] : u[1]};
-        const C d3{(ty == OP_DIAG2) ? u[6] : u[2], (ty == OP_DIAG2) ? u[7] : u[3]};
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
           const uint32_t row = row_g | pick_or<R>(i, sh_row);
@@ -152,18 +176,16 @@ __device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __res
         }
       }
     }
-  };
-
-  layout(0);
-  if (live) {
-    const uint32_t col = pos & ((1u << cshift) - 1u);
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      const cx_t<T> v = L[(size_t)(row_g | pick_or<R>(i, sh_row)) * ld + col];
-      x[i] = C{v.x, v.y};
-    }
-    apply(0);
   }
+}
+
+// Phases 1 .. n_phases - 1 of one tile: each exchanges the registers through LDS into the next
+// phase's layout and applies its operations; on return the layout is the last phase's.
+template <class T, int R>
+__device__ __forceinline__ void phase_rest(const GatePass<T>& P, RC<T> (&x)[1 << R], cx_t<T>* tile, int E, int cshift,
+                                           const uint32_t* slot_off, uint32_t base, bool live, uint32_t& pos,
+                                           uint32_t& sub, uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
+  constexpr int NR = 1 << R;
   for (int ph = 1; ph < P.n_phases; ++ph) {
     if (live) {
 #pragma unroll
@@ -175,26 +197,43 @@ __device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __res
       }
     }
     __syncthreads();
-    layout(ph);
+    phase_layout<T, R>(P, ph, E, cshift, slot_off, pos, sub, sh_pos, sh_row);
     if (live) {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
         const cx_t<T> v = tile[pos | pick_or<R>(i, sh_pos)];
-        x[i] = C{v.x, v.y};
+        x[i] = RC<T>{v.x, v.y};
       }
-      apply(ph);
+      phase_apply<T, R>(P, ph, x, base | sub, sh_row);
     }
     if (ph + 1 < P.n_phases) __syncthreads();
   }
+}
+
+// Apply the pass's operations phase by phase in registers, one tile: phase 0 reads from HBM and
+// the last phase writes to HBM (lanes run along the columns of a row); consecutive phases
+// exchange data through LDS.
+template <class T, int R>
+__device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __restrict__ L, size_t ld,
+                                            cx_t<T>* tile, int cshift, uint32_t base,
+                                            const uint32_t* slot_off) {
+  constexpr int NR = 1 << R;
+  const int E = P.k + cshift;
+  const bool live = threadIdx.x < (1u << (E - R));
+  RC<T> x[NR];
+  uint32_t pos = 0, sub = 0, sh_pos[R], sh_row[R];
+  phase_layout<T, R>(P, 0, E, cshift, slot_off, pos, sub, sh_pos, sh_row);
   if (live) {
     const uint32_t col = pos & ((1u << cshift) - 1u);
 #pragma unroll
-    for (int i = 0; i < NR; ++i) {
-      cx_t<T> v;
-      v.x = x[i].x;
-      v.y = x[i].y;
-      L[(size_t)(row_g | pick_or<R>(i, sh_row)) * ld + col] = v;
-    }
+    for (int i = 0; i < NR; ++i) x[i] = ld_nt<T>(L + (size_t)(base | sub | pick_or<R>(i, sh_row)) * ld + col);
+    phase_apply<T, R>(P, 0, x, base | sub, sh_row);
+  }
+  phase_rest<T, R>(P, x, tile, E, cshift, slot_off, base, live, pos, sub, sh_pos, sh_row);
+  if (live) {
+    const uint32_t col = pos & ((1u << cshift) - 1u);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) st_nt<T>(L + (size_t)(base | sub | pick_or<R>(i, sh_row)) * ld + col, x[i]);
   }
 }
 
@@ -329,6 +368,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<
                                                         int cshift) {
   gate_pass_body<T>(P, L, cshift, blockIdx.x);
 }
+
 
 template <class T>
 __global__ __launch_bounds__(kGateThreads) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {

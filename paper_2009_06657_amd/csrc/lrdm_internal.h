@@ -208,14 +208,24 @@ constexpr int kFdmMaxCoef = 512;
 
 // One fused pass over the 2n-bit vector form of rho: local slot j <-> index bit local_q[j]
 // (slots 0..4 are bits 0..4); ops on slots (1q, 2q) or on any index bit (diagonal).
+// With n_phases > 0 (full tiles of kFdmMaxLocal bits) the operations run in register phases:
+// phase p holds the tile elements differing in the tile slots ph_slots[p][0 .. 4) in registers
+// and applies operations [ph_first[p], ph_first[p] + ph_count[p]); op_a / op_b of a 1- or
+// 2-bit operation are then register bit indices (op_a < op_b for 2-bit operations), and an
+// operand of a diagonal operation that is a register bit is 64 + register (register operands
+// first, ascending).
+constexpr int kFdmMaxPhases = kFdmMaxOps;
 struct FdmPass {
-  int nbits, k, n_ops;
+  int nbits, k, n_ops, n_phases;
   int local_q[kFdmMaxLocal];
   int sorted_hi[kFdmMaxLocal];   // local bits above the low block, ascending
   int op_type[kFdmMaxOps];
   int op_a[kFdmMaxOps];
   int op_b[kFdmMaxOps];
   int op_coef[kFdmMaxOps];
+  unsigned char ph_first[kFdmMaxPhases];
+  unsigned char ph_count[kFdmMaxPhases];
+  unsigned char ph_slots[kFdmMaxPhases][4];
   float coef[kFdmMaxCoef];
 };
 

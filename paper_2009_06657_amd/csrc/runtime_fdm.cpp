@@ -18,7 +18,7 @@ struct lrdm_fdm_ctx {
     int type;          // OP_1Q, OP_2Q (slots), OP_DIAG1, OP_DIAG2 (index bits)
     int a, b;          // index bits
     uint64_t mask;     // index bits touched
-    std::vector<float> coef;
+    std::vector<double> coef;  // interleaved complex: 2x2 / 4x4 row-major, or 2 / 4 diagonal entries
   };
   int n = 0;
   float2* rho = nullptr;
@@ -69,7 +69,7 @@ bool unitary(const double* u, int d) {
   return true;
 }
 
-void push_op(lrdm_fdm_t h, int type, int a, int b, const std::vector<float>& coef) {
+void push_op(lrdm_fdm_t h, int type, int a, int b, const std::vector<double>& coef) {
   lrdm_fdm_ctx::Op op;
   op.type = type;
   op.a = a;
@@ -79,14 +79,198 @@ void push_op(lrdm_fdm_t h, int type, int a, int b, const std::vector<float>& coe
   h->ops.push_back(op);
 }
 
-// d x d complex matrix (interleaved FP64) -> FP32, optionally conjugated
-std::vector<float> mat(const double* u, int d, bool conj) {
-  std::vector<float> c(2 * d * d);
+// d x d complex matrix (interleaved FP64), optionally conjugated
+std::vector<double> mat(const double* u, int d, bool conj) {
+  std::vector<double> c(2 * d * d);
   for (int i = 0; i < d * d; ++i) {
-    c[2 * i] = (float)u[2 * i];
-    c[2 * i + 1] = (float)(conj ? -u[2 * i + 1] : u[2 * i + 1]);
+    c[2 * i] = u[2 * i];
+    c[2 * i + 1] = conj ? -u[2 * i + 1] : u[2 * i + 1];
   }
   return c;
+}
+
+// An operation as a dense d x d matrix over the ordered bit list (x) or (x, y), element
+// t = bit x + 2 bit y.
+void dense_on(const lrdm_fdm_ctx::Op& op, int x, int y, int d, double* m) {
+  std::fill(m, m + 2 * d * d, 0.0);
+  const bool diag = op.type == OP_DIAG1 || op.type == OP_DIAG2;
+  const bool two = op.type == OP_2Q || op.type == OP_DIAG2;
+  auto bitof = [&](int t, int bit) { return bit == x ? (t & 1) : ((t >> 1) & 1); };
+  for (int to = 0; to < d; ++to)
+    for (int ti = 0; ti < d; ++ti) {
+      // the operation's own indices and the identity on the remaining bit
+      const int so = bitof(to, op.a) + (two ? 2 * bitof(to, op.b) : 0);
+      const int si = bitof(ti, op.a) + (two ? 2 * bitof(ti, op.b) : 0);
+      bool same_rest = true;
+      if (d == 4 && !two) {
+        const int other = op.a == x ? y : x;
+        same_rest = bitof(to, other) == bitof(ti, other);
+      }
+      if (!same_rest) continue;
+      const int od = two ? 4 : 2;
+      double re, im;
+      if (diag) {
+        if (so != si) continue;
+        re = op.coef[2 * so];
+        im = op.coef[2 * so + 1];
+      } else {
+        re = op.coef[2 * (so * od + si)];
+        im = op.coef[2 * (so * od + si) + 1];
+      }
+      m[2 * (to * d + ti)] = re;
+      m[2 * (to * d + ti) + 1] = im;
+    }
+}
+
+// Operator fusion: an operation joins the latest earlier operation that touches any of its index
+// bits when the two together act on at most 2 bits (everything in between acts on other bits
+// and commutes with it).  The product is formed in FP64; two diagonal operations stay diagonal.
+// A 1-bit operation may also join the latest operation on the other index bit of the same qubit
+// (row bit n + q <-> column bit q) when nothing after that one touches its own bit: the pair
+// U (x) conj(U) then becomes one 4 x 4 operator that the qubit's channels fuse into.
+void fuse_ops(std::vector<lrdm_fdm_ctx::Op>& ops, int n) {
+  std::vector<lrdm_fdm_ctx::Op> out;
+  std::vector<int> latest(64, -1);
+  for (auto& op : ops) {
+    int x = -1;
+    for (int b = 0; b < 64; ++b)
+      if ((op.mask >> b) & 1ull) x = std::max(x, latest[b]);
+    if ((x < 0 || __builtin_popcountll(out[x].mask | op.mask) > 2) && __builtin_popcountll(op.mask) == 1) {
+      const int b = __builtin_ctzll(op.mask);
+      const int y = latest[b >= n ? b - n : b + n];
+      if (y >= 0 && y >= x && __builtin_popcountll(out[y].mask | op.mask) <= 2) x = y;
+    }
+    if (x >= 0 && __builtin_popcountll(out[x].mask | op.mask) <= 2) {
+      auto& X = out[x];
+      const uint64_t um = X.mask | op.mask;
+      const int b0 = __builtin_ctzll(um);
+      const int b1 = um == (1ull << b0) ? -1 : 63 - __builtin_clzll(um);
+      const int d = b1 < 0 ? 2 : 4;
+      double mx[32], mo[32];
+      dense_on(X, b0, b1, d, mx);
+      dense_on(op, b0, b1, d, mo);
+      std::vector<double> prod(2 * d * d, 0.0);
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+          for (int k = 0; k < d; ++k) {
+            const double ar = mo[2 * (i * d + k)], ai = mo[2 * (i * d + k) + 1];
+            const double br = mx[2 * (k * d + j)], bi = mx[2 * (k * d + j) + 1];
+            prod[2 * (i * d + j)] += ar * br - ai * bi;
+            prod[2 * (i * d + j) + 1] += ar * bi + ai * br;
+          }
+      const bool diag = (X.type == OP_DIAG1 || X.type == OP_DIAG2) && (op.type == OP_DIAG1 || op.type == OP_DIAG2);
+      X.a = b0;
+      X.b = b1;
+      X.mask = um;
+      if (diag) {
+        X.type = d == 2 ? OP_DIAG1 : OP_DIAG2;
+        X.coef.assign(2 * d, 0.0);
+        for (int i = 0; i < d; ++i) {
+          X.coef[2 * i] = prod[2 * (i * d + i)];
+          X.coef[2 * i + 1] = prod[2 * (i * d + i) + 1];
+        }
+      } else {
+        X.type = d == 2 ? OP_1Q : OP_2Q;
+        X.coef = prod;
+      }
+      // a bit of X may have later operations; only the joining operation's bits move to X
+      for (int b = 0; b < 64; ++b)
+        if ((op.mask >> b) & 1ull) latest[b] = std::max(latest[b], x);
+    } else {
+      out.push_back(op);
+      for (int b = 0; b < 64; ++b)
+        if ((op.mask >> b) & 1ull) latest[b] = (int)out.size() - 1;
+    }
+  }
+  ops.swap(out);
+}
+
+// Register phases of a full-tile pass: consecutive operations whose non-diagonal operands fit
+// in 4 tile slots share a phase (diagonal operations join the current one).  Each phase holds
+// exactly 4 distinct slots, filled preferably above the low block so that lanes run along the
+// contiguous low index bits; operands become register indices (0..3), and a 2-slot operator
+// whose first operand maps above its second has its 4x4 matrix permuted (t = 1 <-> t = 2).
+void build_phases(FdmPass& p) {
+  int nph = 0, cur[4], ncur = 0;
+  auto reg_of = [&](int slot) {
+    for (int r = 0; r < ncur; ++r) if (cur[r] == slot) return r;
+    return -1;
+  };
+  auto close_phase = [&](int ph) {
+    bool used[kFdmMaxLocal] = {};
+    for (int r = 0; r < ncur; ++r) used[cur[r]] = true;
+    for (int sl = p.k - 1; sl >= 0 && ncur < 4; --sl)
+      if (!used[sl]) { cur[ncur++] = sl; used[sl] = true; }
+    for (int r = 0; r < 4; ++r) p.ph_slots[ph][r] = (unsigned char)cur[r];
+  };
+  for (int o = 0; o < p.n_ops; ++o) {
+    const int ty = p.op_type[o];
+    const bool diag = ty == OP_DIAG1 || ty == OP_DIAG2;
+    int need[2], nn = 0;
+    if (!diag) {
+      need[nn++] = p.op_a[o];
+      if (ty == OP_2Q) need[nn++] = p.op_b[o];
+    }
+    int extra = 0;
+    for (int j = 0; j < nn; ++j) extra += reg_of(need[j]) < 0;
+    if (nph == 0 || ncur + extra > 4) {
+      if (nph > 0) close_phase(nph - 1);
+      p.ph_first[nph] = (unsigned char)o;
+      p.ph_count[nph] = 0;
+      ++nph;
+      ncur = 0;
+    }
+    for (int j = 0; j < nn; ++j)
+      if (reg_of(need[j]) < 0) cur[ncur++] = need[j];
+    ++p.ph_count[nph - 1];
+  }
+  if (nph > 0) close_phase(nph - 1);
+  p.n_phases = nph;
+  // slots -> register indices
+  for (int ph = 0; ph < nph; ++ph)
+    for (int o = p.ph_first[ph]; o < p.ph_first[ph] + p.ph_count[ph]; ++o) {
+      const int ty = p.op_type[o];
+      auto reg = [&](int slot) {
+        for (int r = 0; r < 4; ++r) if (p.ph_slots[ph][r] == slot) return r;
+        return -1;
+      };
+      if (ty == OP_DIAG1 || ty == OP_DIAG2) {
+        // an operand on a register bit becomes 64 + register; register operands come first, in
+        // ascending order (a swap permutes the 4 diagonal entries, t = 1 <-> t = 2)
+        auto reg_of_bit = [&](int bit) {
+          for (int sl = 0; sl < p.k; ++sl)
+            if (p.local_q[sl] == bit) return reg(sl);
+          return -1;
+        };
+        int qa = p.op_a[o], qb = ty == OP_DIAG2 ? p.op_b[o] : -1;
+        int ra = reg_of_bit(qa), rb = qb >= 0 ? reg_of_bit(qb) : -1;
+        if (ty == OP_DIAG2 && ((ra < 0 && rb >= 0) || (ra >= 0 && rb >= 0 && rb < ra))) {
+          float* u = p.coef + p.op_coef[o];
+          std::swap(u[2], u[4]);
+          std::swap(u[3], u[5]);
+          std::swap(qa, qb);
+          std::swap(ra, rb);
+        }
+        p.op_a[o] = ra >= 0 ? 64 + ra : qa;
+        if (ty == OP_DIAG2) p.op_b[o] = rb >= 0 ? 64 + rb : qb;
+        continue;
+      }
+      int ra = reg(p.op_a[o]), rb = ty == OP_2Q ? reg(p.op_b[o]) : 0;
+      if (ty == OP_2Q && ra > rb) {
+        float* u = p.coef + p.op_coef[o];
+        float t[32];
+        const int sg[4] = {0, 2, 1, 3};
+        for (int r = 0; r < 4; ++r)
+          for (int m = 0; m < 4; ++m) {
+            t[8 * r + 2 * m] = u[8 * sg[r] + 2 * sg[m]];
+            t[8 * r + 2 * m + 1] = u[8 * sg[r] + 2 * sg[m] + 1];
+          }
+        std::memcpy(u, t, sizeof(t));
+        std::swap(ra, rb);
+      }
+      p.op_a[o] = ra;
+      p.op_b[o] = rb;
+    }
 }
 
 lrdm_status flush(lrdm_fdm_t h) {
@@ -95,6 +279,7 @@ lrdm_status flush(lrdm_fdm_t h) {
   const int lo = std::min(kmax, kFdmLowBits);
   const int free_slots = kmax - lo;
   const uint64_t lowmask = (1ull << lo) - 1ull;
+  fuse_ops(h->ops, h->n);
   std::vector<char> placed(h->ops.size(), 0);
   size_t remaining = h->ops.size();
   while (remaining > 0) {
@@ -131,7 +316,7 @@ lrdm_status flush(lrdm_fdm_t h) {
         p.op_a[o] = slot(op.a);
         p.op_b[o] = op.b >= 0 ? slot(op.b) : 0;
       }
-      for (float v : op.coef) p.coef[nc++] = v;
+      for (double v : op.coef) p.coef[nc++] = (float)v;
       placed[i] = 1;
       --remaining;
     }
@@ -144,6 +329,7 @@ lrdm_status flush(lrdm_fdm_t h) {
     std::vector<int> sh = hi;
     std::sort(sh.begin(), sh.end());
     for (size_t j = 0; j < sh.size(); ++j) p.sorted_hi[j] = sh[j];
+    if (p.k == kFdmMaxLocal) build_phases(p);
     FHIP(h, launch_fdm_pass(p, h->rho, h->stream));
   }
   h->ops.clear();
@@ -212,10 +398,10 @@ lrdm_status lrdm_fdm_apply_gate(lrdm_fdm_t h, int k, const int* qubits, const do
       if (i != j && (u[2 * (i * d + j)] != 0.0 || u[2 * (i * d + j) + 1] != 0.0)) diag = false;
   const int n = h->n;
   if (diag) {
-    std::vector<float> ph(2 * d), phc(2 * d);
+    std::vector<double> ph(2 * d), phc(2 * d);
     for (int i = 0; i < d; ++i) {
-      ph[2 * i] = phc[2 * i] = (float)u[2 * (i * d + i)];
-      ph[2 * i + 1] = (float)u[2 * (i * d + i) + 1];
+      ph[2 * i] = phc[2 * i] = u[2 * (i * d + i)];
+      ph[2 * i + 1] = u[2 * (i * d + i) + 1];
       phc[2 * i + 1] = -ph[2 * i + 1];
     }
     if (k == 1) {
@@ -258,7 +444,7 @@ lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e
         return ffail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
     }
   // S[(r + 2c), (r' + 2c')] = sum_a E_a[r][r'] conj(E_a[c][c']) on the bit pair (n + q, q)
-  std::vector<float> S(32);
+  std::vector<double> S(32);
   for (int mo = 0; mo < 4; ++mo)
     for (int mi = 0; mi < 4; ++mi) {
       const int r = mo & 1, c = mo >> 1, rp = mi & 1, cp = mi >> 1;
@@ -269,8 +455,8 @@ lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e
         re += xr * yr - xi * yi;
         im += xr * yi + xi * yr;
       }
-      S[2 * (mo * 4 + mi)] = (float)re;
-      S[2 * (mo * 4 + mi) + 1] = (float)im;
+      S[2 * (mo * 4 + mi)] = re;
+      S[2 * (mo * 4 + mi) + 1] = im;
     }
   push_op(h, OP_2Q, h->n + qubit, qubit, S);
   return LRDM_OK;

@@ -160,19 +160,22 @@ def gradient_throughput(reps: int = 3) -> dict:
     return out
 
 
-def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 16) -> dict:
+def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 0) -> dict:
     """Same-GPU comparison with the full-rank density matrix: the brickwork layer (SU(2) on every
     qubit, CZ, amplitude damping + dephasing per qubit) on the full-rank kernel at n <= 16
     (rho of 8 * 4^n bytes; n = 20 would need 8.8 TB), the low-rank path at n = 16, r = 64 for a
-    measured same-n ratio, and T_full(16) * 4^(20 - 16) as the extrapolated n = 20 layer time."""
+    measured same-n ratio, and T_full(16) * 4^(20 - 16) as the extrapolated n = 20 layer time.
+    The timed full-rank layers are queued together and run at one synchronization, so the
+    host's operator fusion joins each layer's channels with the next layer's gates."""
     import torch
 
     import paper_2009_06657_amd as lr
     from workloads import circuits as C
 
+    lret_n = lret_n or max(sizes)
     per_layer = {}
     for n in sizes:
-        reps = 2 if n >= 16 else 4
+        reps = 4
         prog = C.cfg3_program(n=n, r=64, layers=1 + reps)
         layers = [[]]
         for op in prog.ops:
@@ -308,6 +311,10 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-throughput leg")
     ap.add_argument("--no-fdm", action="store_true", help="skip the full-rank comparator leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
+    ap.add_argument("--fdm-only", action="store_true",
+                    help="only run the full-rank comparator leg and print its result")
+    ap.add_argument("--fdm-sizes", type=str, default="10,12,14,16",
+                    help="qubit counts of the full-rank comparator leg (comma-separated, <= 16)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -320,6 +327,13 @@ def main():
 
     if args.copy_calib:
         copy_calibration(torch)
+        return
+    fdm_sizes = tuple(int(x) for x in args.fdm_sizes.split(","))
+    if not fdm_sizes or min(fdm_sizes) < 1 or max(fdm_sizes) > 16:
+        print("--fdm-sizes: qubit counts must lie in [1, 16]", file=sys.stderr)
+        sys.exit(2)
+    if args.fdm_only:
+        print(json.dumps({"vs_full_rank_dm": fdm_comparator(fdm_sizes)}), flush=True)
         return
 
     import paper_2009_06657_amd as lr
@@ -399,7 +413,7 @@ def main():
     if not args.no_batch:
         out["batched_serving"] = batched_serving()
     if not args.no_fdm:
-        fd = fdm_comparator()
+        fd = fdm_comparator(fdm_sizes)
         fd["speedup_n20_vs_extrapolated_full_rank"] = fd["full_rank_ms_per_layer_n20_extrapolated"] / ms_per_layer
         out["vs_full_rank_dm"] = fd
     if not args.no_cpu_baseline:

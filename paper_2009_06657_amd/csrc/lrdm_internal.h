@@ -214,7 +214,7 @@ constexpr int kFdmMaxCoef = 512;
 // 2-bit operation are then register bit indices (op_a < op_b for 2-bit operations), and an
 // operand of a diagonal operation that is a register bit is 64 + register (register operands
 // first, ascending).
-constexpr int kFdmMaxPhases = kFdmMaxOps;
+constexpr int kFdmMaxPhases = kFdmMaxOps + 2;   // + an empty load and store phase
 struct FdmPass {
   int nbits, k, n_ops, n_phases;
   int local_q[kFdmMaxLocal];

@@ -225,6 +225,26 @@ void build_phases(FdmPass& p) {
     ++p.ph_count[nph - 1];
   }
   if (nph > 0) close_phase(nph - 1);
+  // HBM accesses happen in the first and last phase: when one of them holds a low slot (lanes
+  // would then not run along the contiguous low bits), an empty phase on the top 4 slots does
+  // the load or the store instead, at the cost of one more LDS exchange
+  auto has_low = [&](int ph) {
+    for (int r = 0; r < 4; ++r) if (p.ph_slots[ph][r] < kFdmLowBits) return true;
+    return false;
+  };
+  auto empty_phase = [&](int at, int first) {
+    for (int ph = nph; ph > at; --ph) {
+      p.ph_first[ph] = p.ph_first[ph - 1];
+      p.ph_count[ph] = p.ph_count[ph - 1];
+      for (int r = 0; r < 4; ++r) p.ph_slots[ph][r] = p.ph_slots[ph - 1][r];
+    }
+    p.ph_first[at] = (unsigned char)first;
+    p.ph_count[at] = 0;
+    for (int r = 0; r < 4; ++r) p.ph_slots[at][r] = (unsigned char)(p.k - 4 + r);
+    ++nph;
+  };
+  if (nph > 0 && has_low(0)) empty_phase(0, 0);
+  if (nph > 0 && has_low(nph - 1)) empty_phase(nph, p.n_ops);
   p.n_phases = nph;
   // slots -> register indices
   for (int ph = 0; ph < nph; ++ph)

@@ -11,8 +11,10 @@
 //
 // Tiling: a work-group owns 128 rows of X (32 per wave) and all output columns; K is streamed
 // in chunks of 32 reals through LDS together with the matching 32 rows of the expanded W, the
-// next chunk prefetched into registers during the MFMAs.  Every row is read before any row is
-// written, and no other work-group touches these rows.
+// next chunk prefetched into registers (16-byte loads) during the MFMAs.  W is the first MFMA
+// operand, so the accumulator of a lane holds 4 consecutive output columns of one row, written
+// back as one 16-byte non-temporal store.  Every row is read before any row is written, and no
+// other work-group touches these rows.
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -32,9 +34,9 @@ __device__ __forceinline__ pv4d pmfma16(double a, double b, pv4d c) {
 
 constexpr int kProjBM = 128;   // rows per work-group
 constexpr int kProjKC = 32;    // reals of K per chunk
-constexpr int kProjXS = kProjKC + 2;   // LDS row stride of the X chunk (8-byte aligned rows)
+constexpr int kProjXS = kProjKC + 4;   // LDS row stride of the X chunk (16-byte aligned rows)
 
-template <class T> struct PPair;   // two reals, the unit of the X-chunk staging
+template <class T> struct PPair;   // two reals: one complex entry
 template <> struct PPair<float> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct PPair<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
@@ -49,9 +51,6 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
   constexpr int NTO = FO / 16;
   constexpr int FCO = FO / 2;              // complex output columns of W
   constexpr int WS = FO + 16;              // LDS row stride of the W chunk
-  constexpr int XPT = kProjBM * kProjKC / 2 / 256;            // X pairs per thread
-  constexpr int WPT = (kProjKC / 2) * FCO / 256;              // W entries per thread (may be 0)
-  constexpr int WREM = (kProjKC / 2) * FCO - WPT * 256;       // leftover W entries
   __shared__ __attribute__((aligned(16))) T xs[kProjBM * kProjXS];
   __shared__ __attribute__((aligned(16))) T ws[kProjKC * WS];
 
@@ -73,53 +72,65 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
     return ((((y >> q) << (q + 1)) | (y & ((1u << q) - 1u))) | ((uint32_t)h << q));
   };
 
-  P2 xb[XPT];
-  P2 wb[WPT > 0 ? WPT : 1];
-  P2 wr1 = {0, 0};
+  using Q4 = typename PAcc4<T>::type;
+  constexpr int XQ = kProjBM * kProjKC / 4 / 256;             // X quads per thread
+  constexpr int WP = (kProjKC / 2) * FCO / 2;                 // W complex pairs per chunk
+  constexpr int WQ = (WP + 255) / 256;                         // per thread (the last guarded)
+  static_assert(XQ * 256 * 4 == kProjBM * kProjKC, "shape");
+  Q4 xb[XQ];
+  Q4 wb[WQ > 0 ? WQ : 1];
   auto fetch = [&](int kc) {
 #pragma unroll
-    for (int k = 0; k < XPT; ++k) {
+    for (int k = 0; k < XQ; ++k) {
       const int e = tid + k * 256;
-      const int rr = e >> 4, f = kc + ((e & 15) << 1);
+      const int rr = e >> 3, f = kc + ((e & 7) << 2);
       const uint32_t y = y0 + rr;
-      P2 v = {0, 0};
+      Q4 v = {0, 0, 0, 0};
       if (y < rows && f < F) {
-        const int h = f >> seg_in_shift, w = f & seg_in_mask;
-        v = *reinterpret_cast<const P2*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w);
+        if (seg_in_shift >= 2) {
+          const int h = f >> seg_in_shift, w = f & seg_in_mask;
+          v = *reinterpret_cast<const Q4*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w);
+        } else {
+          // one complex column per half (rank 1): the quad spans both halves
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int fu = f + 2 * u;
+            if (fu < F) {
+              const int h = fu >> seg_in_shift, w = fu & seg_in_mask;
+              const P2 p = *reinterpret_cast<const P2*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w);
+              v[2 * u] = p[0];
+              v[2 * u + 1] = p[1];
+            }
+          }
+        }
       }
       xb[k] = v;
     }
 #pragma unroll
-    for (int k = 0; k < WPT; ++k) {
+    for (int k = 0; k < WQ; ++k) {
       const int e = tid + k * 256;
-      const int pr = e / FCO, qc = e % FCO;
-      P2 v = {0, 0};
-      if (kc / 2 + pr < F / 2) v = *reinterpret_cast<const P2*>(Wr + ((size_t)(kc / 2 + pr) * FCO + qc) * 2);
+      const int pr = e / (FCO / 2), qc = 2 * (e % (FCO / 2));
+      Q4 v = {0, 0, 0, 0};
+      if (e < WP && kc / 2 + pr < F / 2) v = *reinterpret_cast<const Q4*>(Wr + ((size_t)(kc / 2 + pr) * FCO + qc) * 2);
       wb[k] = v;
     }
-    if (WREM > 0 && tid < WREM) {
-      const int e = tid + WPT * 256;
-      const int pr = e / FCO, qc = e % FCO;
-      P2 v = {0, 0};
-      if (kc / 2 + pr < F / 2) v = *reinterpret_cast<const P2*>(Wr + ((size_t)(kc / 2 + pr) * FCO + qc) * 2);
-      wr1 = v;
-    }
-  };
-  auto put_w = [&](int e, P2 v) {
-    const int pr = e / FCO, qc = e % FCO;
-    T* w0 = ws + (2 * pr) * WS + 2 * qc;
-    *reinterpret_cast<P2*>(w0) = v;                          // ( re, im)
-    *reinterpret_cast<P2*>(w0 + WS) = P2{-v[1], v[0]};        // (-im, re)
   };
   auto stage = [&]() {
 #pragma unroll
-    for (int k = 0; k < XPT; ++k) {
+    for (int k = 0; k < XQ; ++k) {
       const int e = tid + k * 256;
-      *reinterpret_cast<P2*>(xs + (e >> 4) * kProjXS + ((e & 15) << 1)) = xb[k];
+      *reinterpret_cast<Q4*>(xs + (e >> 3) * kProjXS + ((e & 7) << 2)) = xb[k];
     }
 #pragma unroll
-    for (int k = 0; k < WPT; ++k) put_w(tid + k * 256, wb[k]);
-    if (WREM > 0 && tid < WREM) put_w(tid + WPT * 256, wr1);
+    for (int k = 0; k < WQ; ++k) {
+      const int e = tid + k * 256;
+      if (e >= WP) break;
+      const int pr = e / (FCO / 2), qc = 2 * (e % (FCO / 2));
+      T* w0 = ws + (2 * pr) * WS + 2 * qc;
+      const Q4 v = wb[k];
+      *reinterpret_cast<Q4*>(w0) = v;                                  // ( re, im) of two entries
+      *reinterpret_cast<Q4*>(w0 + WS) = Q4{-v[1], v[0], -v[3], v[2]};  // (-im, re)
+    }
   };
 
   fetch(0);
@@ -135,29 +146,37 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
 #pragma unroll
       for (int t = 0; t < NTO; ++t) {
         const T b = wrow[16 * t];
-        acc[0][t] = pmfma16(a0, b, acc[0][t]);
-        acc[1][t] = pmfma16(a1, b, acc[1][t]);
+        acc[0][t] = pmfma16(b, a0, acc[0][t]);
+        acc[1][t] = pmfma16(b, a1, acc[1][t]);
       }
     }
     __syncthreads();
   }
 
-  // write back: output real column f -> half h, real offset w inside that half
+  // write back: lane (kq, m) holds row m of its 16-row tile and output real columns
+  // 16 t + 4 kq .. + 3 (the MFMA output rows index W's columns)
   const int seg_out_mask = (1 << seg_out_shift) - 1;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
+    const uint32_t y = y0 + 32 * wave + 16 * r + m;
+    if (y >= rows) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // 16x16x4 MFMA output row: 4 (lane / 16) + v for FP32, 4 v + lane / 16 for FP64
-      const int orow = (sizeof(T) == 8) ? (4 * v + kq) : (4 * kq + v);
-      const uint32_t y = y0 + 32 * wave + 16 * r + orow;
-      if (y >= rows) continue;
-#pragma unroll
-      for (int t = 0; t < NTO; ++t) {
-        const int f = 16 * t + m;
+    for (int t = 0; t < NTO; ++t) {
+      if constexpr (sizeof(T) == 4) {
+        // FP32 output: register v is column 16 t + 4 kq + v (a half holds >= 8 reals here)
+        const int f = 16 * t + 4 * kq;
         const int h = f >> seg_out_shift;
         const int w = f & seg_out_mask;
-        Lr[((size_t)row_index(y, h) * ld) * 2 + w] = acc[r][t][v];
+        __builtin_nontemporal_store(acc[r][t], reinterpret_cast<A4*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w));
+      } else {
+        // FP64 output: register v is column 16 t + 4 v + kq
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int f = 16 * t + 4 * v + kq;
+          const int h = f >> seg_out_shift;
+          const int w = f & seg_out_mask;
+          Lr[((size_t)row_index(y, h) * ld) * 2 + w] = acc[r][t][v];
+        }
       }
     }
   }

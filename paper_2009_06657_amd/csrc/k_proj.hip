@@ -13,8 +13,10 @@
 // in chunks of 32 reals through LDS together with the matching 32 rows of the expanded W, the
 // next chunk prefetched into registers (16-byte loads) during the MFMAs.  W is the first MFMA
 // operand, so the accumulator of a lane holds 4 consecutive output columns of one row, written
-// back as one 16-byte non-temporal store.  Every row is read before any row is written, and no
-// other work-group touches these rows.
+// back as one 16-byte store (ordinary stores: the cache joins the two 64-byte halves of each
+// 128-byte line that a wave writes with consecutive stores, non-temporal ones reached HBM as
+// partial lines and raised the written bytes by a third).  Every row is read before any row is
+// written, and no other work-group touches these rows.
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -167,7 +169,7 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
         const int f = 16 * t + 4 * kq;
         const int h = f >> seg_out_shift;
         const int w = f & seg_out_mask;
-        __builtin_nontemporal_store(acc[r][t], reinterpret_cast<A4*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w));
+        *reinterpret_cast<A4*>(Lr + ((size_t)row_index(y, h) * ld) * 2 + w) = acc[r][t];
       } else {
         // FP64 output: register v is column 16 t + 4 v + kq
 #pragma unroll

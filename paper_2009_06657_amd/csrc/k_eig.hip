@@ -690,7 +690,9 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     // differences to relative accuracy and runs the relative rule down to 4 eps^2.
     const double floor_w = B.rec ? 4 * epsm * epsm : 4 * epsm;
     double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
-    for (int it = 0; it < 24; ++it) {
+    // every layout gives G >= 4: (G + 1)-section reaches 4 eps^2 from width 2 in at most 44
+    // iterations; the loop ends as soon as every bracket has converged
+    for (int it = 0; it < 64; ++it) {
       const double w = hi - lo;
       const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + floor_w);
       if (__ballot(active && !done) == 0ull) break;
@@ -1148,7 +1150,7 @@ template <class T>
 hipError_t launch_eig_batched(int N, const EigJob<T>* jobs, int njobs, int kmax_max, hipStream_t s) {
   if (njobs < 1 || N < 1 || N > kMaxEig || kmax_max < 1) return hipErrorInvalidValue;
   if (N <= 32) return launch_eig_batched_bs<T, 4, 1>(jobs, njobs, kmax_max, s);
-  if (N <= 64) return launch_eig_batched_bs<T, 8, 2>(jobs, njobs, kmax_max, s);
+  if (N <= 64) return launch_eig_batched_bs<T, 4, 2>(jobs, njobs, kmax_max, s);
   return launch_eig_batched_bs<T, 8, 4>(jobs, njobs, kmax_max, s);
 }
 
@@ -1176,11 +1178,11 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
   if (nsplit == 2 && (c < 1 || (c & (c - 1)))) return hipErrorInvalidValue;   // split view: c a power of two
   if (b.rec && (N > kRecMaxN || kmax != N)) return hipErrorInvalidValue;
   hipError_t e;
-  // layouts: order <= 32 on 256 threads (<4, 1>), <= 64 on 256 threads (<8, 2>), <= 128 on 512
+  // layouts: order <= 32 on 256 threads (<4, 1>), <= 64 on 512 threads (<4, 2>), <= 128 on 512
   // threads (<8, 4>, the last 64 steps on <4, 2>): fewer waves per barrier and reduction where the
   // matrix is small (a 64 x 64 reduction on 1024 threads took 1.5x as long)
   if (N <= 32) e = launch_eig_bs<4, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
-  else if (N <= 64) e = launch_eig_bs<8, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
+  else if (N <= 64) e = launch_eig_bs<4, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
   else e = launch_eig_bs<8, 4>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, b, s);
   if (e != hipSuccess) return e;
   const size_t bshm = bt_shm(N);

@@ -13,8 +13,11 @@ record, and propagates the adjoint Lbar (dE = 2 Re Tr(Lbar^H dL)) through the la
     Derivatives of rotations whose generator commutes with every gate between them and the
     current point are evaluated together in one overlap call.
 
-Memory: one checkpoint per layer plus one layer's channel inputs and records.  This module only
-orders calls into liblrdm; every step runs in its kernels.
+Memory: one checkpoint per layer plus one layer's channel inputs and records; when every channel's
+input and record fit in store_all_bytes, the forward pass keeps them all and the reverse sweep
+re-runs nothing (each layer starts from the next layer's checkpoint, which is bit-for-bit the
+state the re-run would reach).  This module only orders calls into liblrdm; every step runs in
+its kernels.
 """
 from __future__ import annotations
 
@@ -59,7 +62,7 @@ class EnergyGradient:
     param = (index into theta.ravel(), axis)."""
 
     def __init__(self, n: int, r: int, m_max: int, xmask, zmask, coeff, dtype: int = 0,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", store_all_bytes: int = 8 << 30):
         import torch
 
         self.n, self.r, self.m_max = n, r, m_max
@@ -71,9 +74,11 @@ class EnergyGradient:
         self.rec_bytes = self.dm.record_bytes()
         self.state_bytes = self.dm.state.numel()
         self.device = torch.device(device)
+        self.store_all_bytes = int(store_all_bytes)
         self._ckpt = None
         self._xbuf = None
         self._rec = None
+        self._all = False
         self.program = None
 
     # ------------------------------------------------------------------ buffers
@@ -90,12 +95,13 @@ class EnergyGradient:
         self._rec = grow(self._rec, max(max_channels, 1), self.rec_bytes)
 
     # ------------------------------------------------------------------ forward
-    def _run_layer(self, ops, keep: bool):
-        """Issue one layer; with keep=True save every channel's input and compression record."""
+    def _run_layer(self, ops, keep: bool, j0: int = 0):
+        """Issue one layer; with keep=True save every channel's input and compression record
+        (channel slots from j0 on)."""
         from workloads.circuits import Compress, DiagWeight, Gate, Kraus
 
         dm = self.dm
-        j = 0
+        j = j0
         for op in ops:
             if isinstance(op, Gate):
                 dm.apply_gate(op.qubits, op.u)
@@ -121,14 +127,18 @@ class EnergyGradient:
             for i, op in enumerate(seg):
                 if isinstance(op, Compress) and (i == 0 or not isinstance(seg[i - 1], Kraus)):
                     raise NotImplementedError("the reverse sweep needs a Kraus channel before every compression")
-        self._ensure(len(self.layers), max(chans) if chans else 1)
-        self._xrank = [0] * max(max(chans) if chans else 1, 1)
+        total = sum(chans)
+        self._all = total * (self.state_bytes + self.rec_bytes) <= self.store_all_bytes
+        slots = total if self._all else (max(chans) if chans else 1)
+        self._ensure(len(self.layers), slots)
+        self._xrank = [0] * max(slots, 1)
         self._ckrank = [0] * len(self.layers)
+        self._j0 = [sum(chans[:l]) if self._all else 0 for l in range(len(self.layers))]
         dm = self.dm
         dm.reset()
         for l, seg in enumerate(self.layers):
             self._ckrank[l] = dm.checkpoint(self._ckpt[l])
-            self._run_layer(seg, keep=False)
+            self._run_layer(seg, keep=self._all, j0=self._j0[l])
         self.energy = dm.expect_pauli(self.xm, self.zm, self.coeff, summed=True)
         return self.energy
 
@@ -191,11 +201,17 @@ class EnergyGradient:
 
         grad = np.zeros(n_params)
         self.bar.apply_pauli_sum_from(self.dm, self.xm, self.zm, self.coeff)
-        for l in range(len(self.layers) - 1, -1, -1):
+        last = len(self.layers) - 1
+        for l in range(last, -1, -1):
             seg = self.layers[l]
-            self.dm.restore(self._ckpt[l], self._ckrank[l])
-            self._run_layer(seg, keep=True)
-            j = sum(isinstance(o, Kraus) for o in seg)
+            if self._all:
+                # the layer's inputs and records are kept; its end state is the next checkpoint
+                if l < last:
+                    self.dm.restore(self._ckpt[l + 1], self._ckrank[l + 1])
+            else:
+                self.dm.restore(self._ckpt[l], self._ckrank[l])
+                self._run_layer(seg, keep=True)
+            j = self._j0[l] + sum(isinstance(o, Kraus) for o in seg)
             i = len(seg)
             while i > 0:
                 op = seg[i - 1]

@@ -160,12 +160,19 @@ hipError_t launch_gram_exact(const cx_t<T>* L, int n, int ld, int c, int q, doub
 }
 
 // ---------------------------------------------------------------- small FP64 matrices
-// One work-group.  Phases are separated by barriers; all arrays live in the workspace.
+// One work-group of kAdjSmallThreads.  The recorded eigenvectors V (N x N, N <= kRecMaxN), H
+// (later U) and Zhat live in LDS (4.5 N^2 doubles, 144 KiB at N = 64); M goes through the
+// workspace, written and read by this work-group only.  Phases are separated by barriers.
+constexpr int kAdjSmallThreads = 1024;
+inline size_t adj_small_shm(int N) { return (size_t)(4 * N * N + (N * N) / 2) * sizeof(double); }
+
 template <class T>
-__global__ __launch_bounds__(256) void adj_small_kernel(const double* __restrict__ rec, Channel ch, int c,
-                                                        AdjBufs b) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(kAdjSmallThreads) void adj_small_kernel(const double* __restrict__ rec, Channel ch, int c,
+                                                                     AdjBufs b) {
+  extern __shared__ __attribute__((aligned(16))) double adj_dyn[];
+  __shared__ double red[kAdjSmallThreads / 64];
+  constexpr int NT = kAdjSmallThreads;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int k = (int)rec[0];
   const double cs = rec[1];
   const int N = (int)rec[2];
@@ -173,80 +180,77 @@ __global__ __launch_bounds__(256) void adj_small_kernel(const double* __restrict
   const int m = ch.m;
   const int w2 = 2 * c;
   const double* lam = rec + kRecHeader;
-  const double* V = rec + kRecHeader + N;   // complex N x N
+  const double* Vg = rec + kRecHeader + N;   // complex N x N
   const int nd = N - k;
+  double* Vs = adj_dyn;                      // N x N complex
+  double* HU = Vs + 2 * N * N;               // N x k complex: H, then U
+  double* Zs = HU + 2 * N * N;               // nd x k complex (nd k <= N^2 / 4)
 
+  for (int e = tid; e < 2 * N * N; e += NT) Vs[e] = Vg[e];
   // 1. H[(a, v), j] = (L'^H Lbar_n)[(a, v), j] = sum_{b, b'} conj(E_a[b'][b]) C[(b, v), (b', j)]
-  for (int e = tid; e < N * k; e += 256) {
+  for (int e = tid; e < N * k; e += NT) {
     const int row = e / k, j = e % k;
     const int a = row / c, v = row % c;
     zd acc = zmake(0, 0);
     for (int bb = 0; bb < 2; ++bb)
       for (int bp = 0; bp < 2; ++bp)
         acc = zplus(acc, ztimes(zbar(echan(ch, a, bp, bb)), zget(b.C, (size_t)(bb * c + v) * w2 + (bp * c + j))));
-    zput(b.H, (size_t)row * c + j, acc);
+    zput(HU, e, acc);
   }
   __syncthreads();
   // 2. Zhat[d, i] = c (V_D^H H)[d, i] / (lambda_i - lambda_{k+d});  s = c Re sum_j (H^H V_K)_jj
   const double tiny = 1e-13 * fmax(rec[3], 1e-300);
-  for (int e = tid; e < nd * k; e += 256) {
+  for (int e = tid; e < nd * k; e += NT) {
     const int d = e / k, i = e % k;
     zd acc = zmake(0, 0);
     for (int row = 0; row < N; ++row)
-      acc = zplus(acc, ztimes(zbar(zget(V, (size_t)row * N + k + d)), zget(b.H, (size_t)row * c + i)));
+      acc = zplus(acc, ztimes(zbar(zget(Vs, row * N + k + d)), zget(HU, row * k + i)));
     const double den = lam[i] - lam[k + d];
     const double f = (fabs(den) > tiny) ? cs / den : 0.0;
-    zput(b.Zh, (size_t)d * c + i, zmake(acc.x * f, acc.y * f));
+    zput(Zs, e, zmake(acc.x * f, acc.y * f));
   }
   double sp = 0;
-  for (int e = tid; e < N * k; e += 256) {
+  for (int e = tid; e < N * k; e += NT) {
     const int row = e / k, j = e % k;
-    const zd h = zget(b.H, (size_t)row * c + j), vv = zget(V, (size_t)row * N + j);
+    const zd h = zget(HU, e), vv = zget(Vs, row * N + j);
     sp += h.x * vv.x + h.y * vv.y;   // Re(conj(h) v)
   }
-  red[tid] = sp;
+  for (int o = 32; o > 0; o >>= 1) sp += __shfl_xor(sp, o, 64);
+  if (lane == 0) red[wave] = sp;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  const double sval = cs * red[0];
-  // 3. T1 = V_K Zhat^H  (N x nd)
-  for (int e = tid; e < N * nd; e += 256) {
-    const int r1 = e / nd, d = e % nd;
+  double sval = 0;
+  for (int w = 0; w < NT / 64; ++w) sval += red[w];   // fixed order
+  sval *= cs;
+  // 3. U = V_D Zhat (N x k), over H:  V_K Zhat^H V_D^H = V_K U^H
+  for (int e = tid; e < N * k; e += NT) {
+    const int r = e / k, i = e % k;
     zd acc = zmake(0, 0);
-    for (int i = 0; i < k; ++i)
-      acc = zplus(acc, ztimes(zget(V, (size_t)r1 * N + i), zbar(zget(b.Zh, (size_t)d * c + i))));
-    zput(b.T1, (size_t)r1 * N + d, acc);
+    for (int d = 0; d < nd; ++d) acc = zplus(acc, ztimes(zget(Vs, r * N + k + d), zget(Zs, d * k + i)));
+    zput(HU, e, acc);
   }
   __syncthreads();
-  // 4. Ghat = T1 V_D^H (N x N)
-  for (int e = tid; e < N * N; e += 256) {
-    const int r1 = e / N, r2 = e % N;
-    zd acc = zmake(0, 0);
-    for (int d = 0; d < nd; ++d)
-      acc = zplus(acc, ztimes(zget(b.T1, (size_t)r1 * N + d), zbar(zget(V, (size_t)r2 * N + k + d))));
-    zput(b.Gh, e, acc);
-  }
-  __syncthreads();
-  // 5. M = Ghat + Ghat^H - s c^2 V_K V_K^H
+  // 4. M = Ghat + Ghat^H - s c^2 V_K V_K^H with Ghat = V_K U^H
   const double sc2 = renorm ? sval * cs * cs : 0.0;
-  for (int e = tid; e < N * N; e += 256) {
+  for (int e = tid; e < N * N; e += NT) {
     const int r1 = e / N, r2 = e % N;
-    zd acc = zplus(zget(b.Gh, e), zbar(zget(b.Gh, (size_t)r2 * N + r1)));
-    if (sc2 != 0.0) {
-      zd pk = zmake(0, 0);
-      for (int i = 0; i < k; ++i)
-        pk = zplus(pk, ztimes(zget(V, (size_t)r1 * N + i), zbar(zget(V, (size_t)r2 * N + i))));
-      acc = zplus(acc, zmake(-sc2 * pk.x, -sc2 * pk.y));
+    zd acc = zmake(0, 0);
+    for (int i = 0; i < k; ++i) {
+      const zd v1 = zget(Vs, r1 * N + i), v2 = zget(Vs, r2 * N + i);
+      const zd u1 = zget(HU, r1 * k + i), u2 = zget(HU, r2 * k + i);
+      acc = zplus(acc, zplus(ztimes(v1, zbar(u2)), ztimes(u1, zbar(v2))));
+      if (sc2 != 0.0) {
+        const zd p = ztimes(v1, zbar(v2));
+        acc = zplus(acc, zmake(-sc2 * p.x, -sc2 * p.y));
+      }
     }
     zput(b.M, e, acc);
   }
   __syncthreads();
+  const double* V = Vs;
   // 6. P and Q in the bulk precision
   cx_t<T>* P = static_cast<cx_t<T>*>(b.P);
   cx_t<T>* Q = static_cast<cx_t<T>*>(b.Q);
-  for (int e = tid; e < w2 * w2; e += 256) {
+  for (int e = tid; e < w2 * w2; e += NT) {
     const int rr = e / w2, cc = e % w2;
     const int bo = cc / c, v = cc % c;   // output column (b, v)
     {
@@ -343,7 +347,17 @@ hipError_t launch_compress_adjoint(cx_t<T>* Ybar, const cx_t<T>* X, int n, int l
                      c, q, half_rows, rpc, b.part);
   hipLaunchKernelGGL(cross_gram_reduce_kernel, dim3((nent + 255) / 256), dim3(256), 0, s, b.part, nchunks,
                      nent, b.C);
-  hipLaunchKernelGGL(adj_small_kernel<T>, dim3(1), dim3(256), 0, s, rec, ch, c, b);
+  const int Nr = ch.m * c;
+  const size_t sshm = adj_small_shm(Nr);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(adj_small_kernel<T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)adj_small_shm(kRecMaxN));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(adj_small_kernel<T>, dim3(1), dim3(kAdjSmallThreads), sshm, s, rec, ch, c, b);
   const size_t shm = (size_t)2 * kAdjRB * w2 * sizeof(cx_t<T>);
   hipLaunchKernelGGL(dual_project_kernel<T>, dim3((half_rows + kAdjRB - 1) / kAdjRB), dim3(256), shm, s,
                      Ybar, X, ld, c, q, half_rows, static_cast<const cx_t<T>*>(b.P),

@@ -192,6 +192,49 @@ def test_gradient_mixed_program(lr):
     np.testing.assert_allclose(g, g_ref, atol=1e-9)
 
 
+def test_gradient_store_all_matches_rerun(lr):
+    """Keeping every channel's input and record (the default budget) and re-running each layer
+    in the reverse sweep (store_all_bytes=0) give bit-identical energies and gradients, both
+    matching the oracle; the first layer ends with gates, so its reverse sweep starts from the
+    restored checkpoint of the next layer."""
+    from paper_2009_06657_amd.adjoint import EnergyGradient
+
+    _say("energy_grad store-all vs re-run")
+    n, r = 6, 4
+    rng = np.random.default_rng(21)
+    theta = rng.uniform(-np.pi, np.pi, size=5)
+    xm, zm, co, _ = C.random_pauli_sum(n, terms=20, max_weight=3, seed=21)
+
+    def make(t):
+        ops = [C.Gate((0,), C.H, False, "h"),
+               C.Gate((1,), C.rx(t[0]), False, "rx", (0, "X")),
+               C.Kraus(1, C.amplitude_damping(0.2), "ad"), C.Compress(r, 0.0, 0, 1),
+               C.Gate((2,), C.ry(t[1]), False, "ry", (1, "Y")),
+               C.Gate((1, 2), C.CZ, True, "cz"),
+               C.Gate((0,), C.rz(t[2]), False, "rz", (2, "Z")),
+               C.LayerEnd(0),
+               C.Kraus(0, C.depolarizing(0.1), "dep"), C.Compress(r, 0.0, 0, 1),
+               C.Gate((3,), C.rx(t[3]), False, "rx", (3, "X")),
+               C.Kraus(3, C.phase_flip(0.15), "deph"), C.Compress(r, 0.0, 0, 1),
+               C.Gate((4,), C.ry(t[4]), False, "ry", (4, "Y")),
+               C.LayerEnd(1)]
+        return C.Program(n, ops, r, "c128", 4, "mixed", 2)
+
+    E_ref, g_ref = OG.energy_grad_adjoint(make(theta), theta.size, xm, zm, co)
+    keep = EnergyGradient(n, r, 4, xm, zm, co, dtype=lr.C128)
+    rerun = EnergyGradient(n, r, 4, xm, zm, co, dtype=lr.C128, store_all_bytes=0)
+    Ea = keep.forward(make(theta))
+    ga = keep.backward(theta.size)
+    Eb = rerun.forward(make(theta))
+    gb = rerun.backward(theta.size)
+    assert keep._all and not rerun._all
+    assert Ea == Eb and np.array_equal(ga, gb)
+    assert abs(Ea - E_ref) <= 1e-10
+    np.testing.assert_allclose(ga, g_ref, atol=1e-9)
+    keep.close()
+    rerun.close()
+
+
 def test_ansatz_full_size_against_finite_differences(lr):
     """n=12, r=16, 8 layers, 200 Pauli terms, complex64 bulk: energy and all 192 derivatives
     against the oracle's central differences (h = 1e-4) stored in tests/golden/cfg4_grad.json."""

@@ -497,60 +497,49 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
   }
   __syncthreads();
-  // S (Fc x Fc, FP64) is staged through LDS in blocks of rows with coalesced 16-byte loads, so
-  // every entry is read from memory once; the terms of each G entry are added in the order
-  // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1) (row blocks in increasing order).
+  // Each thread reads the S entries of its own G entries straight from memory (S is at most
+  // 256 KiB): one row of the thread's layout per round, the 4 BC loads of a round in flight
+  // before the first product; the terms of each G entry are added in the order
+  // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1).  (A chunked LDS staging of S was slower.)
   z64 A[BR][BC];
-#pragma unroll
-  for (int a = 0; a < BR; ++a)
-#pragma unroll
-    for (int b = 0; b < BC; ++b) A[a][b] = zmk(0, 0);
   {
-    z64* Sl = reinterpret_cast<z64*>(dyn);
-    const size_t dyn_bytes = eig_dyn_bytes<BR, BC>(kmax);
-    const int rc = max(1, min(Fc, (int)(dyn_bytes / ((size_t)Fc * sizeof(z64)))));
     const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
     const int cs = __ffs(c) - 1;
-    for (int r0 = 0; r0 < Fc; r0 += rc) {
-      const int rows = min(rc, Fc - r0);
-      const int cnt = rows * Fc;
-      constexpr int U = 8;
-      for (int e0 = 0; e0 < cnt; e0 += U * NTH) {
-        double2 t[U];
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-          const int e = e0 + k * NTH + tid;
-          t[k] = S2[(size_t)r0 * Fc + (e < cnt ? e : 0)];
-        }
+    for (int a = 0; a < BR; ++a) {
+      const int i = R + NH * a;
+      double2 t[BC][4];
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-          const int e = e0 + k * NTH + tid;
-          if (e < cnt) Sl[e] = zmk(t[k].x, t[k].y);
+      for (int b = 0; b < BC; ++b) {
+        const int j = BC * Cc + b;
+        const bool in = i < N && j < N;
+#pragma unroll
+        for (int uv = 0; uv < 4; ++uv) {
+          size_t off;
+          if (nsplit == 2) {   // c is a power of two in the split view
+            off = (size_t)((uv >> 1) * c + (i & (c - 1))) * Fc + ((uv & 1) * c + (j & (c - 1)));
+          } else {
+            off = (size_t)i * Fc + j;
+          }
+          t[b][uv] = S2[in && (nsplit == 2 || uv == 0) ? off : 0];
         }
       }
-      __syncthreads();
 #pragma unroll
-      for (int a = 0; a < BR; ++a)
+      for (int b = 0; b < BC; ++b) {
+        const int j = BC * Cc + b;
+        z64 acc = zmk(0, 0);
+        if (i < N && j < N) {
+          if (nsplit == 2) {
+            const int ai = i >> cs, bj = j >> cs;
 #pragma unroll
-        for (int b = 0; b < BC; ++b) {
-          const int i = R + NH * a, j = BC * Cc + b;
-          if (i < N && j < N) {
-            if (nsplit == 2) {   // c is a power of two in the split view
-              const int ai = i >> cs, vv = i & (c - 1), bj = j >> cs, w = j & (c - 1);
-              for (int u = 0; u < 2; ++u) {
-                const int row = u * c + vv;
-                if (row < r0 || row >= r0 + rows) continue;
-                for (int v = 0; v < 2; ++v) {
-                  const z64 mm = Mab[((ai * m + bj) * 2 + u) * 2 + v];
-                  A[a][b] = zadd(A[a][b], zmul(mm, Sl[(row - r0) * Fc + (v * c + w)]));
-                }
-              }
-            } else if (i >= r0 && i < r0 + rows) {
-              A[a][b] = Sl[(i - r0) * Fc + j];
-            }
+            for (int uv = 0; uv < 4; ++uv)
+              acc = zadd(acc, zmul(Mab[(ai * m + bj) * 4 + uv], zmk(t[b][uv].x, t[b][uv].y)));
+          } else {
+            acc = zmk(t[b][0].x, t[b][0].y);
           }
         }
-      __syncthreads();
+        A[a][b] = acc;
+      }
     }
   }
   {

@@ -370,6 +370,17 @@ __global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<
 }
 
 
+// Register-phase passes over wide factors split the columns in two: a work-group owns one half
+// of a tile's columns (the gates act on rows only), 256 threads and half the LDS, so four
+// work-groups share a CU and their loads, phases and stores overlap more evenly.
+template <class T>
+__global__ __launch_bounds__(kGateThreads / 2, 4) void gate_pass_split_kernel(const GatePass<T> P,
+                                                                              cx_t<T>* __restrict__ L,
+                                                                              int cshift) {
+  const uint32_t half = blockIdx.x & 1u;
+  gate_pass_body<T>(P, L + (size_t)half * (1u << cshift), cshift, blockIdx.x >> 1);
+}
+
 template <class T>
 __global__ __launch_bounds__(kGateThreads) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {
   const int j = find_job(jobs, njobs, blockIdx.x);
@@ -397,6 +408,15 @@ hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
   const size_t shm = gate_pass_shm(p.ncols, p.k, sizeof(cx_t<T>), p.n_phases);
   if (shm > 65536) return hipErrorInvalidValue;
   const uint32_t tiles = 1u << (p.n - p.k);
+  if constexpr (sizeof(T) == 4) {   // complex64 (the complex128 phases need more than 128 registers)
+    // passes with several operations (a lone gate streams slightly faster unsplit)
+    if (p.n_phases > 0 && p.n_ops > 2 && p.ncols >= 64 && p.k + cshift - 1 >= 8) {
+      // every live thread of the 256 holds 16 elements: 2^(k + cshift - 1) = 16 * 256 at most
+      hipLaunchKernelGGL(gate_pass_split_kernel<T>, dim3(2 * tiles), dim3(kGateThreads / 2), shm / 2, s, p, L,
+                         cshift - 1);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(kGateThreads), shm, s, p, L, cshift);
   return hipGetLastError();
 }

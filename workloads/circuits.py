@@ -193,6 +193,76 @@ def brickwork_program(n: int, layers: int, r: int, channels: Sequence[Tuple[str,
     return Program(n, ops, r, dtype, m_max, name, layers)
 
 
+GATES_1Q = ("X", "Y", "Z", "S", "T", "RX", "RY", "RZ")
+GATES_2Q = ("SWAP", "CZ", "CNOT")
+CIRCUIT_KINDS = ("dense-local", "dense-global", "sparse-local")
+
+
+def random_circuit(n: int, depth: int, kind: str = "dense-local", channel: str = "dep",
+                   p: float = 0.001, r: int = 32, eps: float = 1e-4, seed: int = 0,
+                   dtype: str = "c64", sparsity: float = 0.5, tie: int = 0, renorm: int = 1,
+                   noise: bool = True) -> Program:
+    """Randomized-benchmarking circuits (Sec. III.A): gates drawn uniformly from X, Y, Z, S, T,
+    RX, RY, RZ (angles U(0, 2 pi)) and SWAP, CZ, CNOT (random control/target order), a 1- or a
+    2-qubit gate with equal probability at every placement.  Time step t walks the qubits in
+    ascending order; a qubit not yet used in the step gets a 2-qubit gate with probability 1/2
+    when a partner is free (dense-local / sparse-local: the next qubit; dense-global: any free
+    qubit), else a 1-qubit gate.  Dense circuits place a gate on every qubit at every step; in
+    sparse ones a free qubit starts no gate with probability sparsity (it can still be taken as
+    the partner of the qubit before it).  Noise: the channel on
+    every qubit after each step (dense) or only on the qubits a gate touched (sparse), each
+    followed by a compression (rank cap r, threshold eps).  noise=False gives the same gates
+    without channels (the noiseless reference)."""
+    if kind not in CIRCUIT_KINDS:
+        raise ValueError(f"kind must be one of {CIRCUIT_KINDS}")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    one = {"X": X, "Y": Y, "Z": Z, "S": S, "T": T}
+    ops: list = []
+    for t in range(depth):
+        free = set(range(n))
+        touched = []
+        for q in range(n):
+            if q not in free:
+                continue
+            if kind.startswith("sparse") and rng.random() < sparsity:
+                continue
+            free.discard(q)
+            partner = -1
+            if rng.random() < 0.5:
+                if kind.endswith("local"):
+                    partner = q + 1 if (q + 1) in free else -1
+                else:
+                    cand = sorted(free)
+                    partner = int(cand[rng.integers(len(cand))]) if cand else -1
+            if partner >= 0:
+                free.discard(partner)
+                g = GATES_2Q[int(rng.integers(len(GATES_2Q)))]
+                a, b = (q, partner) if rng.random() < 0.5 else (partner, q)
+                if g == "SWAP":
+                    ops.append(_g2(a, b, SWAP, "swap"))
+                elif g == "CZ":
+                    ops.append(_g2(a, b, CZ, "cz", diagonal=True))
+                else:
+                    ops.append(_g2(a, b, CNOT, "cnot"))
+                touched += [q, partner]
+            else:
+                g = GATES_1Q[int(rng.integers(len(GATES_1Q)))]
+                if g in one:
+                    ops.append(_g1(q, one[g], g.lower()))
+                else:
+                    theta = float(rng.uniform(0.0, 2.0 * np.pi))
+                    ops.append(_g1(q, {"RX": rx, "RY": ry, "RZ": rz}[g](theta), g.lower()))
+                touched.append(q)
+        if noise:
+            for q in (sorted(touched) if kind.startswith("sparse") else range(n)):
+                ops.append(Kraus(q, _channel(channel, p), channel))
+                ops.append(Compress(r, eps, tie, renorm))
+        ops.append(LayerEnd(t))
+    m_max = _channel(channel, p).shape[0] if noise else 1
+    return Program(n, ops, r, dtype, m_max, f"random-{kind}", depth,
+                   {"kind": kind, "channel": channel, "p": p, "eps": eps, "seed": seed})
+
+
 def _channel(ch: str, p: float) -> np.ndarray:
     return {"dep": depolarizing, "bitflip": bit_flip, "deph": phase_flip,
             "ad": amplitude_damping}[ch](p)

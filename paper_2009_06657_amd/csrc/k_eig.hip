@@ -175,6 +175,7 @@ struct TriSmem {
   double* e_s;    // off-diagonal of T (global index)
   double* tau_s;  // reflector scalars (global index, interleaved)
   z64* Rf;        // packed reflector entries i >= j + 2 (global packing)
+  double tiny2;   // squared column norm below which a column counts as already reduced
 };
 
 // Transposing exchange across lane ^ 16: lanes with bit 4 clear get a + a(lane ^ 16), lanes
@@ -253,10 +254,15 @@ __device__ __forceinline__ void tri_reflector(const z64 (&cv)[BC], const z64 alp
   double beta = alpha.x;
   tau = zmk(0, 0);
   z64 sc = zmk(0, 0);
-  if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+  // A column whose squared norm is at most tiny2 = max((1e-30 Tr G)^2, 1e-290) is taken as
+  // reduced: its entries below the subdiagonal and the imaginary part of alpha are
+  // dropped, a perturbation far below rounding.  Such columns hold only cancellation residue
+  // (e.g. a qubit in an exact basis state); unscaled, their squared norm leaves the FP64 normal
+  // range and the reciprocal square root below overflows.
+  const double n2 = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2));
+  if (!(xn2 == 0.0 && alpha.y == 0.0) && n2 > M.tiny2) {
     // 1 / ||x|| from the hardware reciprocal square root refined by two Newton steps, and
     // 1 / |alpha - beta|^2 by the refined reciprocal (short dependency chains; a few ulp)
-    const double n2 = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, xn2));
     double rn = __builtin_amdgcn_rsq(n2);
     rn = rn * fma(-0.5 * n2, rn * rn, 1.5);
     rn = rn * fma(-0.5 * n2, rn * rn, 1.5);
@@ -574,7 +580,9 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   // through the freed LDS.
   z64* Rf = reinterpret_cast<z64*>(dyn);
   double* refl = B.P;
-  const TriSmem M{col_buf, vbuf, pbuf, cola, NP, d_s, e_s, tau_s, Rf};
+  double tr_all = 0;   // every thread forms the trace from the published partials (same order)
+  for (int i = 0; i < NTH / 32; ++i) tr_all += trp[i];
+  const TriSmem M{col_buf, vbuf, pbuf, cola, NP, d_s, e_s, tau_s, Rf, fmax(1e-60 * tr_all * tr_all, 1e-290)};
   constexpr bool kShrink = (BR == 8 && BC == 4);
   const bool shrink = kShrink && N > 64;
   const int jsw = shrink ? N - 64 : N - 1;   // updates on the full layout

@@ -221,6 +221,55 @@ def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 0) -> dict:
             "extrapolation": f"T_full({nmax}) * 4^(20 - {nmax})"}
 
 
+def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
+    """Synthetic re-runs of the paper's accuracy studies (Sec. III.A): distortion of the low-rank
+    path against the full-rank density matrix, both on this GPU, on seeded random circuits from
+    the paper's gate set, averaged over seeds, at depths 4, 8 and 12 (one run per circuit gives
+    every depth).  Studies: depolarizing p = 0.1 % over n and eps (Fig. 4); p = 0.3 % and 1 %
+    with eps/p in {1, 0.3, 0.1, 0.03, 0.01} (Fig. 5); bit flip and amplitude damping p = 0.1 %
+    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  Rank caps:
+    r = 32 for depolarizing (four Kraus operators, Gram order 4r <= 128), 64 otherwise; the
+    compressions whose threshold rank lay above the cap are counted."""
+    import paper_2009_06657_amd as lr
+    from paper_2009_06657_amd import accuracy as A
+
+    lr.load_library()
+    depths = [d for d in (4, 8, 12) if d <= depth]
+    studies = []
+    eps_grid = (1e-2, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
+    for n in (4, 6, 8, 10, 12):
+        studies.append(("fig4-depolarizing", n, "dense-local", "dep", 1e-3, eps_grid))
+    for p in (3e-3, 1e-2):
+        for n in (6, 8, 10, 12):
+            studies.append(("fig5-noise-strength", n, "dense-local", "dep", p, tuple(p * f for f in (1, .3, .1, .03, .01))))
+    for ch in ("bitflip", "ad"):
+        for n in (4, 6, 8, 10, 12):
+            studies.append(("fig7-channels", n, "dense-local", ch, 1e-3, eps_grid))
+    for kind in ("dense-global", "dense-local", "sparse-local"):
+        studies.append(("fig8-circuit-types", 13, kind, "bitflip", 1e-3, (1e-4,)))
+    rows = []
+    t0 = time.perf_counter()
+    for name, n, kind, ch, p, eps_list in studies:
+        r = 32 if ch == "dep" else 64
+        runs = [A.distortion_study(n, depth, kind, ch, p, eps_list, seed, r) for seed in seeds]
+        for eps in eps_list:
+            per = [run["eps"][eps] for run in runs]
+            rows.append({"study": name, "n": n, "kind": kind, "channel": ch, "p": p, "eps": eps,
+                         "distortion": {str(d): float(np.mean([q["distortion"][d - 1] for q in per])) for d in depths},
+                         "distortion_max_over_seeds": {str(d): float(np.max([q["distortion"][d - 1] for q in per]))
+                                                       for d in depths},
+                         "rank_by_layer": [float(np.mean([q["ranks"][t] for q in per])) for t in range(depth)],
+                         "max_rank": int(max(q["max_rank"] for q in per)),
+                         "cap_hits": int(sum(q["cap_hits"] for q in per)),
+                         "compressions": int(sum(q["compressions"] for q in per))})
+        print(f"accuracy: {name} n={n} {kind} {ch} p={p:g} done ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    return {"workload": f"random circuits (dense/sparse x local/global, paper gate set), depth {depth}, "
+                        f"seeds {list(seeds)}; low rank (complex FP32, FP64 eigensolve, plain threshold "
+                        "rule) vs full-rank density matrix (complex FP32), both on the GPU",
+            "seconds": time.perf_counter() - t0, "rows": rows}
+
+
 def batched_serving(count: int = 256, loop_budget_s: float = 30.0) -> dict:
     """The serving mix: `count` independent brickwork instances (n ~ U{8..16}, r ~ U{8,16,32},
     10..30 layers, depolarizing p ~ U(1e-4, 5e-3), compress after every channel, <Z> per
@@ -315,6 +364,8 @@ def main():
                     help="only run the full-rank comparator leg and print its result")
     ap.add_argument("--fdm-sizes", type=str, default="10,12,14,16",
                     help="qubit counts of the full-rank comparator leg (comma-separated, <= 16)")
+    ap.add_argument("--accuracy-only", action="store_true",
+                    help="only run the distortion sweeps (random circuits, low rank vs full rank) and print them")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -334,6 +385,9 @@ def main():
         sys.exit(2)
     if args.fdm_only:
         print(json.dumps({"vs_full_rank_dm": fdm_comparator(fdm_sizes)}), flush=True)
+        return
+    if args.accuracy_only:
+        print(json.dumps({"accuracy": accuracy_sweep()}), flush=True)
         return
 
     import paper_2009_06657_amd as lr

@@ -227,13 +227,30 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     the paper's gate set, averaged over seeds, at depths 4, 8 and 12 (one run per circuit gives
     every depth).  Studies: depolarizing p = 0.1 % over n and eps (Fig. 4); p = 0.3 % and 1 %
     with eps/p in {1, 0.3, 0.1, 0.03, 0.01} (Fig. 5); bit flip and amplitude damping p = 0.1 %
-    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  Rank caps:
+    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  First, the
+    distortion of the fixed-rank workloads: n = 6 depolarizing (r = 13, complex128), noisy Grover
+    at n = 14 (r = 32) and the RY/RZ/CZ ansatz at n = 12 (r = 16).  Rank caps:
     r = 32 for depolarizing (four Kraus operators, Gram order 4r <= 128), 64 otherwise; the
     compressions whose threshold rank lay above the cap are counted."""
     import paper_2009_06657_amd as lr
     from paper_2009_06657_amd import accuracy as A
 
     lr.load_library()
+    from workloads import circuits as C
+
+    t0 = time.perf_counter()
+    configs = {}
+    for name, prog, dt in (("n6_r13_depolarizing_c128", C.cfg1_program(), lr.C128),
+                           ("grover_n14_r32", C.cfg2_program(), lr.C64),
+                           ("ry_rz_cz_n12_r16", C.cfg4_program(C.cfg4_angles()), lr.C64)):
+        res = A.program_distortion(prog, dtype=dt)
+        # layers whose exact diagonal is within 1e-3 of the noiseless one (e.g. a uniform
+        # superposition, which depolarizing noise leaves uniform) give no meaningful ratio
+        by_layer = [d if den >= 1e-3 else None for d, den in zip(res["distortion"], res["exact_minus_noiseless"])]
+        configs[name] = {"distortion_final": res["distortion"][-1], "distortion_by_layer": by_layer,
+                         "layers": len(res["distortion"]), "max_rank": res["max_rank"], "r": prog.r,
+                         "compressions": res["compressions"]}
+        print(f"accuracy: {name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
     depths = [d for d in (4, 8, 12) if d <= depth]
     studies = []
     eps_grid = (1e-2, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
@@ -248,7 +265,6 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     for kind in ("dense-global", "dense-local", "sparse-local"):
         studies.append(("fig8-circuit-types", 13, kind, "bitflip", 1e-3, (1e-4,)))
     rows = []
-    t0 = time.perf_counter()
     for name, n, kind, ch, p, eps_list in studies:
         r = 32 if ch == "dep" else 64
         runs = [A.distortion_study(n, depth, kind, ch, p, eps_list, seed, r) for seed in seeds]
@@ -267,7 +283,7 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     return {"workload": f"random circuits (dense/sparse x local/global, paper gate set), depth {depth}, "
                         f"seeds {list(seeds)}; low rank (complex FP32, FP64 eigensolve, plain threshold "
                         "rule) vs full-rank density matrix (complex FP32), both on the GPU",
-            "seconds": time.perf_counter() - t0, "rows": rows}
+            "seconds": time.perf_counter() - t0, "configs": configs, "rows": rows}
 
 
 def batched_serving(count: int = 256, loop_budget_s: float = 30.0) -> dict:

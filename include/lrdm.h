@@ -231,6 +231,12 @@ lrdm_status lrdm_fdm_destroy(lrdm_fdm_t h);
 lrdm_status lrdm_fdm_apply_gate(lrdm_fdm_t h, int k, const int* qubits, const double* u);
 /* rho <- sum_a E_a rho E_a^H on one qubit; arguments as lrdm_apply_kraus (m in [1, 4]). */
 lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e);
+/* rho[x][y] <- phase[popcount(x)] conj(phase[popcount(y)]) rho[x][y]: the Hamming-weight
+ * diagonal gate of lrdm_apply_diagonal_weight (Grover oracle and reflection, Sec. III.C) on the
+ * full-rank state; phase has n + 1 unit-modulus complex entries (interleaved FP64, checked within
+ * 1e-10, else LRDM_E_ARG).  Queued operations are applied first; this one runs at once as its
+ * own pass over rho.  Queued on the stream. */
+lrdm_status lrdm_fdm_apply_diagonal_weight(lrdm_fdm_t h, const double* phase);
 /* Prob(x) = Re rho[x][x] into p_dev (2^n doubles, device).  Applies queued operations. */
 lrdm_status lrdm_fdm_probabilities(lrdm_fdm_t h, double* p_dev);
 /* Apply queued operations and wait for the stream. */

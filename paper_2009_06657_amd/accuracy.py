@@ -31,9 +31,9 @@ def distortion(p_lret: np.ndarray, p_exact: np.ndarray, p_noiseless: np.ndarray)
 
 
 def exact_diagonals(program) -> List[np.ndarray]:
-    """Diagonal of the exact noisy state after every layer: the program's gates and channels on
-    the full-rank density matrix (its compressions do not apply there)."""
-    from workloads.circuits import Compress, Gate, Kraus, LayerEnd
+    """Diagonal of the exact noisy state after every layer: the program's gates, phases and
+    channels on the full-rank density matrix (its compressions do not apply there)."""
+    from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
     f = FullRankDM(program.n)
     out = []
@@ -43,6 +43,8 @@ def exact_diagonals(program) -> List[np.ndarray]:
                 f.apply_gate(op.qubits, op.u)
             elif isinstance(op, Kraus):
                 f.apply_kraus(op.qubit, op.ops)
+            elif isinstance(op, DiagWeight):
+                f.apply_diagonal_weight(op.phase)
             elif isinstance(op, LayerEnd):
                 out.append(_host(f.probabilities()))
             elif not isinstance(op, Compress):

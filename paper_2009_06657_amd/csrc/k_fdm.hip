@@ -439,4 +439,39 @@ hipError_t launch_fdm_diag(const float2* rho, int n, double* p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// rho[x][y] *= phase[pop(x)] conj(phase[pop(y)]): a diagonal gate that depends on the Hamming
+// weight, on the row and the column side (Sec. III.C's Grover oracle and |0..0> reflection).
+// The (n + 1)^2 products are formed in FP64 once per work-group and kept in LDS as complex64;
+// each thread step takes two neighbouring entries of one row (a 16-byte access).
+__global__ void __launch_bounds__(256) fdm_weight_kernel(float2* __restrict__ rho, int n, FdmPhase P) {
+  __shared__ float2 tab[(kFdmMaxQubits + 1) * (kFdmMaxQubits + 1)];
+  const int nw = n + 1;
+  for (int i = threadIdx.x; i < nw * nw; i += 256) {
+    const int a = i / nw, b = i - a * nw;
+    const double ax = P.ph[2 * a], ay = P.ph[2 * a + 1], bx = P.ph[2 * b], by = P.ph[2 * b + 1];
+    tab[i] = make_float2((float)(ax * bx + ay * by), (float)(ay * bx - ax * by));
+  }
+  __syncthreads();
+  const uint64_t pairs = 1ull << (2 * n - 1);
+  const uint32_t cmask = (1u << n) - 1u;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  float4* r4 = reinterpret_cast<float4*>(rho);
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < pairs; e += stride) {
+    const uint32_t x = (uint32_t)((2 * e) >> n), y = (uint32_t)(2 * e) & cmask;   // y even
+    const int px = __popc(x) * nw, py = __popc(y);
+    const float2 w0 = tab[px + py], w1 = tab[px + py + 1];   // pop(y + 1) = pop(y) + 1
+    const float4 v = r4[e];
+    r4[e] = make_float4(v.x * w0.x - v.y * w0.y, v.x * w0.y + v.y * w0.x,
+                        v.z * w1.x - v.w * w1.y, v.z * w1.y + v.w * w1.x);
+  }
+}
+
+hipError_t launch_fdm_weight(float2* rho, int n, const FdmPhase& ph, hipStream_t s) {
+  const uint64_t pairs = 1ull << (2 * n - 1);
+  const uint64_t want = (pairs + 255) / 256;
+  const uint32_t blocks = (uint32_t)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(fdm_weight_kernel, dim3(blocks), dim3(256), 0, s, rho, n, ph);
+  return hipGetLastError();
+}
+
 }  // namespace lrdm

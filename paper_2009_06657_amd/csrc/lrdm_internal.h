@@ -232,6 +232,11 @@ struct FdmPass {
 hipError_t launch_fdm_pass(const FdmPass& p, float2* rho, hipStream_t s);
 hipError_t launch_fdm_reset(float2* rho, int n, hipStream_t s);
 hipError_t launch_fdm_diag(const float2* rho, int n, double* p, hipStream_t s);
+constexpr int kFdmMaxQubits = 16;
+struct FdmPhase {   // Hamming-weight phase table, FP64 interleaved
+  double ph[2 * (kFdmMaxQubits + 1)];
+};
+hipError_t launch_fdm_weight(float2* rho, int n, const FdmPhase& ph, hipStream_t s);
 
 // ---------------------------------------------------------------- reverse sweep (k_adj.hip)
 // dst = sum_t coeff[t] P_t src, column by column (terms: xm[n], zm[n], coeff[n] as doubles).

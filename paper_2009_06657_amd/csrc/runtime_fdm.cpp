@@ -482,6 +482,23 @@ lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e
   return LRDM_OK;
 }
 
+lrdm_status lrdm_fdm_apply_diagonal_weight(lrdm_fdm_t h, const double* phase) {
+  lrdm_status st = fusable(h);
+  if (st != LRDM_OK) return st;
+  if (!phase) return ffail(h, LRDM_E_ARG, "null phase table");
+  FdmPhase ph{};
+  for (int w = 0; w <= h->n; ++w) {
+    const double m = std::hypot(phase[2 * w], phase[2 * w + 1]);
+    if (!(std::fabs(m - 1.0) <= 1e-10)) return ffail(h, LRDM_E_ARG, "phase entries must have unit modulus");
+    ph.ph[2 * w] = phase[2 * w];
+    ph.ph[2 * w + 1] = phase[2 * w + 1];
+  }
+  st = flush(h);   // queued operations come first
+  if (st != LRDM_OK) return st;
+  FHIP(h, launch_fdm_weight(h->rho, h->n, ph, h->stream));
+  return LRDM_OK;
+}
+
 lrdm_status lrdm_fdm_probabilities(lrdm_fdm_t h, double* p_dev) {
   lrdm_status st = fusable(h);
   if (st != LRDM_OK) return st;

@@ -27,7 +27,7 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_version", "lrdm_record_bytes", "lrdm_compress_record", "lrdm_checkpoint",
            "lrdm_restore", "lrdm_apply_pauli_sum", "lrdm_pauli_overlap", "lrdm_compress_adjoint",
            "lrdm_fdm_state_bytes", "lrdm_fdm_init", "lrdm_fdm_reset", "lrdm_fdm_destroy",
-           "lrdm_fdm_apply_gate", "lrdm_fdm_apply_kraus", "lrdm_fdm_probabilities",
+           "lrdm_fdm_apply_gate", "lrdm_fdm_apply_kraus", "lrdm_fdm_apply_diagonal_weight", "lrdm_fdm_probabilities",
            "lrdm_fdm_synchronize", "lrdm_fdm_last_error", "lrdm_batch_create", "lrdm_batch_begin",
            "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
            "lrdm_batch_times", "lrdm_batch_destroy"]
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "lrdm_fdm_destroy": [P],
         "lrdm_fdm_apply_gate": [P, I, ctypes.POINTER(I), dp],
         "lrdm_fdm_apply_kraus": [P, I, I, dp],
+        "lrdm_fdm_apply_diagonal_weight": [P, dp],
         "lrdm_fdm_probabilities": [P, P],
         "lrdm_fdm_synchronize": [P],
         "lrdm_batch_create": [ctypes.POINTER(P), I, ctypes.POINTER(P), P],
@@ -352,6 +353,10 @@ class FullRankDM:
         m = _cplx(ops)
         self._chk(self.lib.lrdm_fdm_apply_kraus(self.h, int(qubit), ops.shape[0], _dptr(m)))
 
+    def apply_diagonal_weight(self, phase):
+        m = _cplx(phase)
+        self._chk(self.lib.lrdm_fdm_apply_diagonal_weight(self.h, _dptr(m)))
+
     def probabilities(self, out=None):
         import torch
 
@@ -445,8 +450,8 @@ class Batch:
 
 
 def run_program_fdm(fdm: FullRankDM, program):
-    """Gates and channels of a Program on the full-rank comparator (compressions do not apply;
-    diagonal Hamming-weight phases are not supported there)."""
+    """Gates, Hamming-weight phases and channels of a Program on the full-rank comparator
+    (compressions do not apply there)."""
     from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
     for op in program.ops:
@@ -454,10 +459,10 @@ def run_program_fdm(fdm: FullRankDM, program):
             fdm.apply_gate(op.qubits, op.u)
         elif isinstance(op, Kraus):
             fdm.apply_kraus(op.qubit, op.ops)
+        elif isinstance(op, DiagWeight):
+            fdm.apply_diagonal_weight(op.phase)
         elif isinstance(op, (Compress, LayerEnd)):
             pass
-        elif isinstance(op, DiagWeight):
-            raise NotImplementedError("Hamming-weight phases are not supported by the full-rank comparator")
         else:
             raise TypeError(f"unknown op {op!r}")
 

@@ -108,6 +108,20 @@ hipError_t launch_fdm_reset(float2*, int n, hipStream_t) {
 }
 
 hipError_t launch_fdm_diag(const float2*, int, double*, hipStream_t) { return hipSuccess; }
+
+// rho[x][y] *= phase[pop(x)] conj(phase[pop(y)]), row bits above the column bits
+hipError_t launch_fdm_weight(float2*, int n, const FdmPhase& ph, hipStream_t) {
+  const size_t dim = size_t(1) << n;
+  for (size_t x = 0; x < dim; ++x)
+    for (size_t y = 0; y < dim; ++y) {
+      const int a = __builtin_popcountll(x), b = __builtin_popcountll(y);
+      const std::complex<double> w = std::complex<double>(ph.ph[2 * a], ph.ph[2 * a + 1]) *
+                                     std::conj(std::complex<double>(ph.ph[2 * b], ph.ph[2 * b + 1]));
+      std::complex<float>& v = g_state[(x << n) | y];
+      v = std::complex<float>(std::complex<double>(v) * w);
+    }
+  return hipSuccess;
+}
 }  // namespace lrdm
 
 int main(int argc, char** argv) {
@@ -128,6 +142,10 @@ int main(int argc, char** argv) {
       std::vector<double> u(2 << (2 * k));
       for (auto& x : u) if (std::fscanf(f, "%lf", &x) != 1) return 4;
       if (lrdm_fdm_apply_gate(h, k, q, u.data()) != LRDM_OK) return 5;
+    } else if (t[0] == 'W') {
+      std::vector<double> ph(2 * (n + 1));
+      for (auto& x : ph) if (std::fscanf(f, "%lf", &x) != 1) return 4;
+      if (lrdm_fdm_apply_diagonal_weight(h, ph.data()) != LRDM_OK) return 5;
     } else {
       int q, m;
       if (std::fscanf(f, "%d %d", &q, &m) != 2 || m < 1 || m > 4) return 4;

@@ -40,6 +40,8 @@ def _write(prog, path):
                 u = np.asarray(op.u, dtype=complex)
                 f.write("G %d %s %s\n" % (len(op.qubits), " ".join(map(str, op.qubits)),
                                           " ".join("%.17g %.17g" % (z.real, z.imag) for z in u.ravel())))
+            elif isinstance(op, C.DiagWeight):
+                f.write("W %s\n" % " ".join("%.17g %.17g" % (z.real, z.imag) for z in np.asarray(op.phase, complex)))
             elif isinstance(op, C.Kraus):
                 e = np.asarray(op.ops, dtype=complex)
                 f.write("K %d %d %s\n" % (op.qubit, e.shape[0],
@@ -75,3 +77,12 @@ def test_schedule_brickwork(checker, tmp_path):
     ref = ofdm.run_fdm(prog)
     assert np.max(np.abs(rho - ref)) <= 1e-5, log
     assert abs(np.trace(rho).real - 1) <= 1e-5
+
+
+def test_schedule_hamming_weight_phase(checker, tmp_path):
+    """Noisy Grover at n = 7 (Sec. III.C): each Hamming-weight phase flushes the queued passes
+    and runs as its own sweep, so order with the fused gates and channels is kept."""
+    prog = C.cfg2_program(n=7, r=16, iterations=2, p=0.003)
+    rho, log = _run(checker, prog, tmp_path)
+    ref = ofdm.run_fdm(prog)
+    assert np.max(np.abs(rho - ref)) <= 1e-5, log

@@ -71,8 +71,37 @@ def test_fdm_equals_full_rank_lret(lr):
     assert np.max(np.abs(p_f - p_l)) <= 2e-5
 
 
+@pytest.mark.parametrize("n", [1, 4, 7])
+def test_fdm_hamming_weight_phase(lr, n):
+    """Hamming-weight phases on both sides of rho: noisy Grover (real phases, Sec. III.C) and
+    random complex unit-modulus phases between queued gates and channels."""
+    _say(f"fdm hamming-weight phase n={n}")
+    rng = np.random.default_rng(70 + n)
+    ops = []
+    for t in range(3):
+        ops += [C.Gate((q,), C.haar_su2(rng)) for q in range(n)]
+        ops.append(C.DiagWeight(np.exp(1j * rng.uniform(0, 2 * np.pi, n + 1))))
+        ops += [C.Kraus(q, C.depolarizing(0.01)) for q in range(n)]
+        if n > 1:
+            ops.append(C.Gate((0, n - 1), C.CNOT))
+    progs = [C.Program(n, ops, 8)]
+    if n >= 4:
+        progs.append(C.cfg2_program(n=n, r=16, iterations=2, p=0.003))
+    for prog in progs:
+        ref = ofdm.run_fdm(prog)
+        f = lr.FullRankDM(n)
+        lr.run_program_fdm(f, prog)
+        rho = f.rho()
+        err = np.max(np.abs(rho - ref))
+        _say(f"  {prog.name or 'random phases'}: max |d rho| {err:.2e}")
+        assert err <= 1e-5
+        f.close()
+
+
 def test_fdm_errors(lr):
     f = lr.FullRankDM(3)
+    with pytest.raises(lr.LrdmError):
+        f.apply_diagonal_weight(np.array([1, 1, 1, 1.5]))
     with pytest.raises(lr.LrdmError):
         f.apply_gate((0,), np.array([[1, 1], [0, 1]]))
     with pytest.raises(lr.LrdmError):

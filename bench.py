@@ -221,21 +221,12 @@ def fdm_comparator(sizes=(10, 12, 14, 16), lret_n: int = 0) -> dict:
             "extrapolation": f"T_full({nmax}) * 4^(20 - {nmax})"}
 
 
-def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
-    """Synthetic re-runs of the paper's accuracy studies (Sec. III.A): distortion of the low-rank
-    path against the full-rank density matrix, both on this GPU, on seeded random circuits from
-    the paper's gate set, averaged over seeds, at depths 4, 8 and 12 (one run per circuit gives
-    every depth).  Studies: depolarizing p = 0.1 % over n and eps (Fig. 4); p = 0.3 % and 1 %
-    with eps/p in {1, 0.3, 0.1, 0.03, 0.01} (Fig. 5); bit flip and amplitude damping p = 0.1 %
-    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  First, the
-    distortion of the fixed-rank workloads: n = 6 depolarizing (r = 13, complex128), noisy Grover
-    at n = 14 (r = 32) and the RY/RZ/CZ ansatz at n = 12 (r = 16).  Rank caps:
-    r = 32 for depolarizing (four Kraus operators, Gram order 4r <= 128), 64 otherwise; the
-    compressions whose threshold rank lay above the cap are counted."""
+def fixed_rank_distortion() -> dict:
+    """Distortion (Sec. III, Eq. "distortion") of the fixed-rank workloads against the full-rank
+    density matrix on the same GPU: n = 6 depolarizing (r = 13, complex128), noisy Grover at
+    n = 14 (r = 32) and the RY/RZ/CZ ansatz at n = 12 (r = 16), per layer and at the end."""
     import paper_2009_06657_amd as lr
     from paper_2009_06657_amd import accuracy as A
-
-    lr.load_library()
     from workloads import circuits as C
 
     t0 = time.perf_counter()
@@ -251,6 +242,26 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
                          "layers": len(res["distortion"]), "max_rank": res["max_rank"], "r": prog.r,
                          "compressions": res["compressions"]}
         print(f"accuracy: {name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    return configs
+
+
+def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
+    """Synthetic re-runs of the paper's accuracy studies (Sec. III.A): distortion of the low-rank
+    path against the full-rank density matrix, both on this GPU, on seeded random circuits from
+    the paper's gate set, averaged over seeds, at depths 4, 8 and 12 (one run per circuit gives
+    every depth).  Studies: depolarizing p = 0.1 % over n and eps (Fig. 4); p = 0.3 % and 1 %
+    with eps/p in {1, 0.3, 0.1, 0.03, 0.01} (Fig. 5); bit flip and amplitude damping p = 0.1 %
+    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  First, the
+    distortion of the fixed-rank workloads: n = 6 depolarizing (r = 13, complex128), noisy Grover
+    at n = 14 (r = 32) and the RY/RZ/CZ ansatz at n = 12 (r = 16).  Rank caps:
+    r = 32 for depolarizing (four Kraus operators, Gram order 4r <= 128), 64 otherwise; the
+    compressions whose threshold rank lay above the cap are counted."""
+    import paper_2009_06657_amd as lr
+    from paper_2009_06657_amd import accuracy as A
+
+    lr.load_library()
+    t0 = time.perf_counter()
+    configs = fixed_rank_distortion()
     depths = [d for d in (4, 8, 12) if d <= depth]
     studies = []
     eps_grid = (1e-2, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
@@ -380,6 +391,8 @@ def main():
                     help="only run the full-rank comparator leg and print its result")
     ap.add_argument("--fdm-sizes", type=str, default="10,12,14,16",
                     help="qubit counts of the full-rank comparator leg (comma-separated, <= 16)")
+    ap.add_argument("--no-distortion", action="store_true",
+                    help="skip the distortion of the fixed-rank workloads against the full-rank DM")
     ap.add_argument("--accuracy-only", action="store_true",
                     help="only run the distortion sweeps (random circuits, low rank vs full rank) and print them")
     ap.add_argument("--copy-calib", action="store_true",
@@ -491,6 +504,8 @@ def main():
         fd = fdm_comparator(fdm_sizes)
         fd["speedup_n20_vs_extrapolated_full_rank"] = fd["full_rank_ms_per_layer_n20_extrapolated"] / ms_per_layer
         out["vs_full_rank_dm"] = fd
+    if not args.no_distortion:
+        out["distortion"] = fixed_rank_distortion()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prog.n, prog.r)
     print(json.dumps(out), flush=True)

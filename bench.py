@@ -430,7 +430,7 @@ def main():
         run_step(dm, prog, uniforms)
     torch.cuda.synchronize()
 
-    # The eigensolve (class 3, two kernels bracketed by one pair of events) takes the most time
+    # The eigensolve (class 3, four kernels bracketed by one pair of events) takes the most time
     # per step; the projection (class 4) is the MFMA-bound GEMM and the gate pass (class 0) the
     # HBM-bound sweep.  Each is timed with HIP events on the handle's stream over the timed
     # region, one class per step in turn; a class no timed step covered is timed on an extra,
@@ -484,8 +484,9 @@ def main():
         "roofline_gate_pass": roof(0, "hbm", HBM_PEAK),
     }
     if dominant == 3:
-        # the eigensolve is one work-group on the serial path (its back-transform uses 16): its
-        # fraction of a single CU's FP64 peak (256 CUs) is the meaningful utilisation figure
+        # the eigensolve runs on the serial path, its reduction and eigenvector kernels on one
+        # work-group (the multisection uses one per wave, the back-transform 16): its fraction
+        # of a single CU's FP64 peak (256 CUs) is the meaningful utilisation figure
         out["roofline"]["peak_one_cu"] = FP64_PEAK / 256 / 1e12
         out["roofline"]["frac_one_cu"] = out["roofline"]["frac"] * 256
     if not args.no_breakdown:

@@ -465,6 +465,57 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], z64 (&vloc)[BC], z64&
   __syncthreads();
 }
 
+// G lanes per eigenvalue for a work-group of nth threads: the largest G <= 16 whose groups
+// (64 / G per wave, never across waves; left-over lanes idle) cover the kmax eigenvalues
+__host__ __device__ __forceinline__ int eig_lanes(int nth, int kmax) {
+  int G = 16;
+  while (G > 1 && (64 / G) * (nth / 64) < kmax) --G;
+  return G;
+}
+
+// The leading eigenvalues of the scaled T (diagonal d, squared off-diagonal e2) handled by wave
+// w of the fused layout: eigenvalue t = w (64 / G) + lane / G, its G lanes counting at the
+// interior points of G + 1 equal sections of its bracket.  Each eigenvalue's bracket sequence
+// depends only on T, G and its own counts, so every placement of the waves gives the same bits.
+__device__ __forceinline__ void multisection_wave(const double* d_s, const double* e2_s, int N, int kmax, int G,
+                                                  int wv, bool zero, bool rec, double* lam_out) {
+  const double epsm = 2.220446049250313e-16;
+  const double pivmin = 1e-290;
+  const int lane = threadIdx.x & 63;
+  const int gpw = 64 / G;
+  const int gi = lane / G;
+  const int t = wv * gpw + gi, g = lane - gi * G;
+  const bool mine = gi < gpw && t < kmax;
+  const bool active = mine && !zero;
+  const int asc = N - 1 - t;
+  // G-section: lane g counts at the interior point g + 1 of G + 1 equal sections.  Without a
+  // record the bracket stops at an absolute width of 4 eps (eigenvalues to ||T|| eps, what the
+  // rank rule and the inverse iteration need); a record (reverse sweep) needs eigenvalue
+  // differences to relative accuracy and runs the relative rule down to 4 eps^2.
+  const double floor_w = rec ? 4 * epsm * epsm : 4 * epsm;
+  double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
+  // every layout gives G >= 4: (G + 1)-section reaches 4 eps^2 from width 2 in at most 44
+  // iterations; the loop ends as soon as every bracket has converged
+  for (int it = 0; it < 64; ++it) {
+    const double w = hi - lo;
+    const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + floor_w);
+    if (__ballot(active && !done) == 0ull) break;
+    const double x = lo + w * (double)(g + 1) / (double)(G + 1);
+    const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
+    const unsigned long long ball = __ballot(active && !done && cnt > asc);
+    const int gb = gi * G;
+    const unsigned long long grp = (ball >> gb) & ((1ull << G) - 1ull);
+    const int first = grp ? (__ffsll((long long)grp) - 1) : G;
+    const double xh = __shfl(x, min(gb + (first < G ? first : 0), 63), 64);
+    const double xl = __shfl(x, min(gb + (first == 0 ? 0 : first - 1), 63), 64);
+    if (active && !done) {
+      if (first < G) hi = xh;
+      if (first > 0) lo = xl;
+    }
+  }
+  if (g == 0 && mine) lam_out[t] = active ? 0.5 * (lo + hi) : 0.0;
+}
+
 // dynamic LDS of the eigensolver work-group: the pivots and vectors of the inverse iteration or
 // the packed reflectors, whichever is larger
 template <int BR, int BC>
@@ -475,7 +526,7 @@ __host__ __device__ __forceinline__ size_t eig_dyn_bytes(int kmax) {
   return ph4 > ph2 ? ph4 : ph2;
 }
 
-template <int BR, int BC>
+template <int BR, int BC, int PART>
 __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, const Channel& ch, int nsplit,
                                          int c, int N, int kmax, int r_target, double eps, int tie,
                                          int renorm, const EigBufs& B) {
@@ -494,220 +545,209 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   constexpr int NH = NP / BR;              // half-waves; thread rows R + NH a, columns BC Cc + b
   const int m = (nsplit == 2) ? ch.m : 1;
 
-  // ---------------------------------------------------------------- 1. assemble G
-  if (nsplit == 2 && tid < m * m * 4) {
-    const int a = tid / (m * 4), b = (tid / 4) % m, u = (tid >> 1) & 1, v = tid & 1;
-    z64 acc = zmk(0, 0);
-    for (int r = 0; r < 2; ++r)
-      acc = zadd(acc, zcmul(zmk(ch.e[a][r][u][0], ch.e[a][r][u][1]), zmk(ch.e[b][r][v][0], ch.e[b][r][v][1])));
-    Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
-  }
-  __syncthreads();
-  // Each thread reads the S entries of its own G entries straight from memory (S is at most
-  // 256 KiB): one row of the thread's layout per round, the 4 BC loads of a round in flight
-  // before the first product; the terms of each G entry are added in the order
-  // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1).  (A chunked LDS staging of S was slower.)
-  z64 A[BR][BC];
-  {
-    const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
-    const int cs = __ffs(c) - 1;
-#pragma unroll
-    for (int a = 0; a < BR; ++a) {
-      const int i = R + NH * a;
-      double2 t[BC][4];
-#pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        const int j = BC * Cc + b;
-        const bool in = i < N && j < N;
-#pragma unroll
-        for (int uv = 0; uv < 4; ++uv) {
-          size_t off;
-          if (nsplit == 2) {   // c is a power of two in the split view
-            off = (size_t)((uv >> 1) * c + (i & (c - 1))) * Fc + ((uv & 1) * c + (j & (c - 1)));
-          } else {
-            off = (size_t)i * Fc + j;
-          }
-          t[b][uv] = S2[in && (nsplit == 2 || uv == 0) ? off : 0];
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        const int j = BC * Cc + b;
-        z64 acc = zmk(0, 0);
-        if (i < N && j < N) {
-          if (nsplit == 2) {
-            const int ai = i >> cs, bj = j >> cs;
-#pragma unroll
-            for (int uv = 0; uv < 4; ++uv)
-              acc = zadd(acc, zmul(Mab[(ai * m + bj) * 4 + uv], zmk(t[b][uv].x, t[b][uv].y)));
-          } else {
-            acc = zmk(t[b][0].x, t[b][0].y);
-          }
-        }
-        A[a][b] = acc;
-      }
+  if constexpr (PART != 2) {   // phases 1 and 2 (and the scaling of T below) run in part 1
+    // ---------------------------------------------------------------- 1. assemble G
+    if (nsplit == 2 && tid < m * m * 4) {
+      const int a = tid / (m * 4), b = (tid / 4) % m, u = (tid >> 1) & 1, v = tid & 1;
+      z64 acc = zmk(0, 0);
+      for (int r = 0; r < 2; ++r)
+        acc = zadd(acc, zcmul(zmk(ch.e[a][r][u][0], ch.e[a][r][u][1]), zmk(ch.e[b][r][v][0], ch.e[b][r][v][1])));
+      Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
     }
-  }
-  {
-    double t = 0;
-#pragma unroll
-    for (int a = 0; a < BR; ++a) {
-      const int i = R + NH * a;
-#pragma unroll
-      for (int b = 0; b < BC; ++b)
-        if (i == BC * Cc + b) t += A[a][b].x;
-    }
-    t = gsum<32>(t);
-    if (Cc == 0) trp[R] = t;
-  }
-  if (Cc == 0) {
-#pragma unroll
-    for (int a = 0; a < BR; ++a) col_buf[R + NH * a] = A[a][0];
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0;
-    for (int i = 0; i < NTH / 32; ++i) t += trp[i];
-    sc_s[0] = t;   // trace
-  }
-
-  // ---------------------------------------------------------------- 2. tridiagonalisation
-  // Reflector entries i >= j + 2 are kept in LDS while reducing (a global store inside the
-  // loop would make every barrier wait for its completion) and spilled to the workspace
-  // afterwards, because the eigenvector phase reuses this LDS.  With the 128-order layout the
-  // last 64 steps run on the trailing 64 x 64 block moved to a <4, 2> layout (a quarter of the
-  // arithmetic per step): the finished reflectors are spilled first and the move is staged
-  // through the freed LDS.
-  z64* Rf = reinterpret_cast<z64*>(dyn);
-  double* refl = B.P;
-  double tr_all = 0;   // every thread forms the trace from the published partials (same order)
-  for (int i = 0; i < NTH / 32; ++i) tr_all += trp[i];
-  const TriSmem M{col_buf, vbuf, pbuf, cola, NP, d_s, e_s, tau_s, Rf, fmax(1e-60 * tr_all * tr_all, 1e-290)};
-  constexpr bool kShrink = (BR == 8 && BC == 4);
-  const bool shrink = kShrink && N > 64;
-  const int jsw = shrink ? N - 64 : N - 1;   // updates on the full layout
-  if (N >= 2) {
-    z64 vl[BC], tau;
-    tri_prologue<BR, BC>(A, N, 0, N, M, vl, tau);
-    for (int jb = 0; jb < jsw; jb += BC) {
-      static_for<BC>([&](auto bbc) {
-        const int jl = jb + decltype(bbc)::value;
-        if (jl < jsw)
-          tri_step<BR, BC, decltype(bbc)::value>(A, vl, tau, jl, N, 0, N, M, jl + 1 < jsw, !shrink && jl + 2 == N);
-      });
-    }
-  } else if (tid == 0) {
-    d_s[0] = col_buf[0].x;
-  }
-  int spilled = 0;   // reflector entries already in the workspace
-  if constexpr (kShrink) {
-    if (shrink) {
-      spilled = refl_off(jsw, N);
-      for (int e = tid; e < spilled; e += NTH) {
-        refl[2 * e] = Rf[e].x;
-        refl[2 * e + 1] = Rf[e].y;
-      }
-      __syncthreads();
-      z64* Sg = Rf;   // 64 x 64 staging, row-major, local indices
-#pragma unroll
-      for (int a = 0; a < BR; ++a)
-#pragma unroll
+    __syncthreads();
+    // Each thread reads the S entries of its own G entries straight from memory (S is at most
+    // 256 KiB): one row of the thread's layout per round, the 4 BC loads of a round in flight
+    // before the first product; the terms of each G entry are added in the order
+    // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1).  (A chunked LDS staging of S was slower.)
+    z64 A[BR][BC];
+    {
+      const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
+      const int cs = __ffs(c) - 1;
+  #pragma unroll
+      for (int a = 0; a < BR; ++a) {
+        const int i = R + NH * a;
+        double2 t[BC][4];
+  #pragma unroll
         for (int b = 0; b < BC; ++b) {
-          const int i = R + NH * a, jj = BC * Cc + b;
-          if (i >= jsw && jj >= jsw && i < N && jj < N) Sg[(i - jsw) * 64 + (jj - jsw)] = A[a][b];
+          const int j = BC * Cc + b;
+          const bool in = i < N && j < N;
+  #pragma unroll
+          for (int uv = 0; uv < 4; ++uv) {
+            size_t off;
+            if (nsplit == 2) {   // c is a power of two in the split view
+              off = (size_t)((uv >> 1) * c + (i & (c - 1))) * Fc + ((uv & 1) * c + (j & (c - 1)));
+            } else {
+              off = (size_t)i * Fc + j;
+            }
+            t[b][uv] = S2[in && (nsplit == 2 || uv == 0) ? off : 0];
+          }
         }
-      __syncthreads();
-      z64 A2[4][2];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) A2[a][b] = Sg[(R + 16 * a) * 64 + 2 * Cc + b];
-      if (Cc == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) col_buf[R + 16 * a] = A2[a][0];
+  #pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int j = BC * Cc + b;
+          z64 acc = zmk(0, 0);
+          if (i < N && j < N) {
+            if (nsplit == 2) {
+              const int ai = i >> cs, bj = j >> cs;
+  #pragma unroll
+              for (int uv = 0; uv < 4; ++uv)
+                acc = zadd(acc, zmul(Mab[(ai * m + bj) * 4 + uv], zmk(t[b][uv].x, t[b][uv].y)));
+            } else {
+              acc = zmk(t[b][0].x, t[b][0].y);
+            }
+          }
+          A[a][b] = acc;
+        }
       }
-      __syncthreads();   // the staging is read before the steps write reflectors over it
-      z64 vl2[2], tau2;
-      tri_prologue<4, 2>(A2, 64, jsw, N, M, vl2, tau2);
-      for (int jb = 0; jb < 63; jb += 2) {
-        static_for<2>([&](auto bbc) {
+    }
+    {
+      double t = 0;
+  #pragma unroll
+      for (int a = 0; a < BR; ++a) {
+        const int i = R + NH * a;
+  #pragma unroll
+        for (int b = 0; b < BC; ++b)
+          if (i == BC * Cc + b) t += A[a][b].x;
+      }
+      t = gsum<32>(t);
+      if (Cc == 0) trp[R] = t;
+    }
+    if (Cc == 0) {
+  #pragma unroll
+      for (int a = 0; a < BR; ++a) col_buf[R + NH * a] = A[a][0];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0;
+      for (int i = 0; i < NTH / 32; ++i) t += trp[i];
+      sc_s[0] = t;   // trace
+    }
+
+    // ---------------------------------------------------------------- 2. tridiagonalisation
+    // Reflector entries i >= j + 2 are kept in LDS while reducing (a global store inside the
+    // loop would make every barrier wait for its completion) and spilled to the workspace
+    // afterwards, because the eigenvector phase reuses this LDS.  With the 128-order layout the
+    // last 64 steps run on the trailing 64 x 64 block moved to a <4, 2> layout (a quarter of the
+    // arithmetic per step): the finished reflectors are spilled first and the move is staged
+    // through the freed LDS.
+    z64* Rf = reinterpret_cast<z64*>(dyn);
+    double* refl = B.P;
+    double tr_all = 0;   // every thread forms the trace from the published partials (same order)
+    for (int i = 0; i < NTH / 32; ++i) tr_all += trp[i];
+    const TriSmem M{col_buf, vbuf, pbuf, cola, NP, d_s, e_s, tau_s, Rf, fmax(1e-60 * tr_all * tr_all, 1e-290)};
+    constexpr bool kShrink = (BR == 8 && BC == 4);
+    const bool shrink = kShrink && N > 64;
+    const int jsw = shrink ? N - 64 : N - 1;   // updates on the full layout
+    if (N >= 2) {
+      z64 vl[BC], tau;
+      tri_prologue<BR, BC>(A, N, 0, N, M, vl, tau);
+      for (int jb = 0; jb < jsw; jb += BC) {
+        static_for<BC>([&](auto bbc) {
           const int jl = jb + decltype(bbc)::value;
-          if (jl < 63) tri_step<4, 2, decltype(bbc)::value>(A2, vl2, tau2, jl, 64, jsw, N, M, jl + 1 < 63, jl == 62);
+          if (jl < jsw)
+            tri_step<BR, BC, decltype(bbc)::value>(A, vl, tau, jl, N, 0, N, M, jl + 1 < jsw, !shrink && jl + 2 == N);
         });
       }
+    } else if (tid == 0) {
+      d_s[0] = col_buf[0].x;
     }
-  }
-  if (tid == 0) e_s[N - 1] = 0.0;
-  const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
-  for (int e = spilled + tid; e < nref; e += NTH) {
-    refl[2 * e] = Rf[e].x;
-    refl[2 * e + 1] = Rf[e].y;
-  }
-  __syncthreads();
-
-  // ---------------------------------------------------------------- 3. eigenvalues
-  // scale T to unit Gershgorin norm
-  if (wave == 0) {
-    double mx = 0;
-    for (int i = lane; i < N; i += 64) {
-      const double el = (i > 0) ? fabs(e_s[i - 1]) : 0.0;
-      const double er = (i + 1 < N) ? fabs(e_s[i]) : 0.0;
-      mx = fmax(mx, fabs(d_s[i]) + el + er);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) sc_s[1] = mx;
-  }
-  __syncthreads();
-  const double tnorm = sc_s[1];
-  const bool zero = !(tnorm > 0.0);
-  const double inv = zero ? 1.0 : 1.0 / tnorm;
-  const double epsm = 2.220446049250313e-16;
-  const double pivmin = 1e-290;
-  for (int i = tid; i < N; i += NTH) {
-    d_s[i] *= inv;
-    e_s[i] = (i + 1 < N) ? e_s[i] * inv : 0.0;
-    e2_s[i] = e_s[i] * e_s[i];
-  }
-  __syncthreads();
-  {
-    // G lanes per eigenvalue: the largest G <= 16 whose groups (64 / G per wave, never across
-    // waves; left-over lanes idle) cover the kmax eigenvalues
-    int G = 16;
-    while (G > 1 && (64 / G) * (NTH / 64) < kmax) --G;
-    const int gpw = 64 / G;
-    const int gi = lane / G;
-    const int t = wave * gpw + gi, g = lane - gi * G;
-    const bool mine = gi < gpw && t < kmax;
-    const bool active = mine && !zero;
-    const int asc = N - 1 - t;
-    // G-section: lane g counts at the interior point g + 1 of G + 1 equal sections.  Without a
-    // record the bracket stops at an absolute width of 4 eps (eigenvalues to ||T|| eps, what the
-    // rank rule and the inverse iteration need); a record (reverse sweep) needs eigenvalue
-    // differences to relative accuracy and runs the relative rule down to 4 eps^2.
-    const double floor_w = B.rec ? 4 * epsm * epsm : 4 * epsm;
-    double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
-    // every layout gives G >= 4: (G + 1)-section reaches 4 eps^2 from width 2 in at most 44
-    // iterations; the loop ends as soon as every bracket has converged
-    for (int it = 0; it < 64; ++it) {
-      const double w = hi - lo;
-      const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + floor_w);
-      if (__ballot(active && !done) == 0ull) break;
-      const double x = lo + w * (double)(g + 1) / (double)(G + 1);
-      const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
-      const unsigned long long ball = __ballot(active && !done && cnt > asc);
-      const int gb = gi * G;
-      const unsigned long long grp = (ball >> gb) & ((1ull << G) - 1ull);
-      const int first = grp ? (__ffsll((long long)grp) - 1) : G;
-      const double xh = __shfl(x, min(gb + (first < G ? first : 0), 63), 64);
-      const double xl = __shfl(x, min(gb + (first == 0 ? 0 : first - 1), 63), 64);
-      if (active && !done) {
-        if (first < G) hi = xh;
-        if (first > 0) lo = xl;
+    int spilled = 0;   // reflector entries already in the workspace
+    if constexpr (kShrink) {
+      if (shrink) {
+        spilled = refl_off(jsw, N);
+        for (int e = tid; e < spilled; e += NTH) {
+          refl[2 * e] = Rf[e].x;
+          refl[2 * e + 1] = Rf[e].y;
+        }
+        __syncthreads();
+        z64* Sg = Rf;   // 64 x 64 staging, row-major, local indices
+  #pragma unroll
+        for (int a = 0; a < BR; ++a)
+  #pragma unroll
+          for (int b = 0; b < BC; ++b) {
+            const int i = R + NH * a, jj = BC * Cc + b;
+            if (i >= jsw && jj >= jsw && i < N && jj < N) Sg[(i - jsw) * 64 + (jj - jsw)] = A[a][b];
+          }
+        __syncthreads();
+        z64 A2[4][2];
+  #pragma unroll
+        for (int a = 0; a < 4; ++a)
+  #pragma unroll
+          for (int b = 0; b < 2; ++b) A2[a][b] = Sg[(R + 16 * a) * 64 + 2 * Cc + b];
+        if (Cc == 0) {
+  #pragma unroll
+          for (int a = 0; a < 4; ++a) col_buf[R + 16 * a] = A2[a][0];
+        }
+        __syncthreads();   // the staging is read before the steps write reflectors over it
+        z64 vl2[2], tau2;
+        tri_prologue<4, 2>(A2, 64, jsw, N, M, vl2, tau2);
+        for (int jb = 0; jb < 63; jb += 2) {
+          static_for<2>([&](auto bbc) {
+            const int jl = jb + decltype(bbc)::value;
+            if (jl < 63) tri_step<4, 2, decltype(bbc)::value>(A2, vl2, tau2, jl, 64, jsw, N, M, jl + 1 < 63, jl == 62);
+          });
+        }
       }
     }
-    if (g == 0 && mine) lam_s[t] = active ? 0.5 * (lo + hi) : 0.0;
+    if (tid == 0) e_s[N - 1] = 0.0;
+    const int nref = (N >= 2) ? refl_off(N - 1, N) : 0;
+    for (int e = spilled + tid; e < nref; e += NTH) {
+      refl[2 * e] = Rf[e].x;
+      refl[2 * e + 1] = Rf[e].y;
+    }
+    __syncthreads();
   }
+
+  // ---------------------------------------------------------------- 3. eigenvalues
+  const double pivmin = 1e-290;
+  double* Tst = B.Y + kEigTOff;   // T, tau, trace and norm between the parts of a split solve
+  if constexpr (PART != 2) {
+    // scale T to unit Gershgorin norm
+    if (wave == 0) {
+      double mx = 0;
+      for (int i = lane; i < N; i += 64) {
+        const double el = (i > 0) ? fabs(e_s[i - 1]) : 0.0;
+        const double er = (i + 1 < N) ? fabs(e_s[i]) : 0.0;
+        mx = fmax(mx, fabs(d_s[i]) + el + er);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+      if (lane == 0) sc_s[1] = mx;
+    }
+    __syncthreads();
+    const double tn = sc_s[1];
+    const double inv = (tn > 0.0) ? 1.0 / tn : 1.0;
+    for (int i = tid; i < N; i += NTH) {
+      d_s[i] *= inv;
+      e_s[i] = (i + 1 < N) ? e_s[i] * inv : 0.0;
+      e2_s[i] = e_s[i] * e_s[i];
+    }
+    __syncthreads();
+  }
+  if constexpr (PART == 1) {
+    for (int i = tid; i < N; i += NTH) {
+      Tst[i] = d_s[i];
+      Tst[kMaxEig + i] = e_s[i];
+      Tst[2 * kMaxEig + i] = e2_s[i];
+    }
+    for (int i = tid; i < 2 * N; i += NTH) Tst[3 * kMaxEig + i] = tau_s[i];
+    if (tid < 2) Tst[5 * kMaxEig + tid] = sc_s[tid];   // trace, Gershgorin norm
+    return;
+  }
+  if constexpr (PART == 2) {
+    for (int i = tid; i < N; i += NTH) {
+      d_s[i] = Tst[i];
+      e_s[i] = Tst[kMaxEig + i];
+      e2_s[i] = Tst[2 * kMaxEig + i];
+    }
+    for (int i = tid; i < 2 * N; i += NTH) tau_s[i] = Tst[3 * kMaxEig + i];
+    if (tid < 2) sc_s[tid] = Tst[5 * kMaxEig + tid];
+    for (int t = tid; t < kmax; t += NTH) lam_s[t] = B.lam[t];   // from the multisection kernel
+    __syncthreads();
+  }
+  const double tnorm = sc_s[1];
+  const bool zero = !(tnorm > 0.0);
+  if constexpr (PART == 0) multisection_wave(d_s, e2_s, N, kmax, eig_lanes(NTH, kmax), wave, zero, B.rec != nullptr, lam_s);
   __syncthreads();
   if (tid == 0) {
     const double ctol = 1e-9;
@@ -1079,18 +1119,45 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
   }
 }
 
+// A single solve runs in three kernels: part 1 (assembly, tridiagonal reduction, scaling of T)
+// and part 2 (eigenvectors of T, rank rule) on one work-group each, and between them the
+// multisection with each wave of the fused layout in a work-group of its own, so each runs on its
+// own CU instead of two waves sharing a SIMD (the Sturm counts are issue-bound there).  The
+// eigenvalues are the same bits as the fused kernel's.
 template <int BR, int BC>
-__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_kernel(const double* __restrict__ S, int Fc, Channel ch,
-                                                   int nsplit, int c, int N, int kmax, int r_target,
-                                                   double eps, int tie, int renorm, EigBufs B) {
-  eig_body<BR, BC>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, B);
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_reduce_kernel(const double* __restrict__ S, int Fc,
+                                                                         Channel ch, int nsplit, int c, int N,
+                                                                         int kmax, int r_target, double eps, int tie,
+                                                                         int renorm, EigBufs B) {
+  eig_body<BR, BC, 1>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, B);
+}
+
+template <int BR, int BC>
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_vectors_kernel(const double* __restrict__ S, int Fc,
+                                                                          Channel ch, int nsplit, int c, int N,
+                                                                          int kmax, int r_target, double eps, int tie,
+                                                                          int renorm, EigBufs B) {
+  eig_body<BR, BC, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, B);
+}
+
+// wave blockIdx.x of the fused layout's multisection (G lanes per eigenvalue)
+__global__ __launch_bounds__(64) void eig_sturm_kernel(int N, int kmax, int G, const double* __restrict__ Tst,
+                                                       double* __restrict__ lam, int rec) {
+  __shared__ double d_s[kMaxEig], e2_s[kMaxEig];
+  for (int i = threadIdx.x; i < N; i += 64) {
+    d_s[i] = Tst[i];
+    e2_s[i] = Tst[2 * kMaxEig + i];
+  }
+  __syncthreads();
+  const bool zero = !(Tst[5 * kMaxEig + 1] > 0.0);
+  multisection_wave(d_s, e2_s, N, kmax, G, blockIdx.x, zero, rec != 0, lam);
 }
 
 // One work-group per job; every job of a launch has the same size class (BR, BC).
 template <class T, int BR, int BC>
 __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_batched(const EigJob<T>* __restrict__ jobs) {
   const EigJob<T>& J = jobs[blockIdx.x];
-  eig_body<BR, BC>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
+  eig_body<BR, BC, 0>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
 }
 
 template <class T, int RPL>
@@ -1160,10 +1227,22 @@ static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int 
   constexpr int NP = 32 * BC;
   constexpr int NTH = 32 * (NP / BR);
   const size_t shm = eig_shm<BR, BC>(kmax);
-  const hipError_t e = allow_shm(eig_kernel<BR, BC>, shm);
+  hipError_t e = allow_shm(eig_reduce_kernel<BR, BC>, shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((eig_kernel<BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax, r_target,
-                     eps, tie, renorm, b);
+  e = allow_shm(eig_vectors_kernel<BR, BC>, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_reduce_kernel<BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax,
+                     r_target, eps, tie, renorm, b);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int G = eig_lanes(NTH, kmax);
+  const int waves = (kmax + 64 / G - 1) / (64 / G);
+  hipLaunchKernelGGL(eig_sturm_kernel, dim3(waves), dim3(64), 0, s, N, kmax, G, b.Y + kEigTOff, b.lam,
+                     b.rec ? 1 : 0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_vectors_kernel<BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax,
+                     r_target, eps, tie, renorm, b);
   return hipGetLastError();
 }
 

@@ -74,7 +74,10 @@ struct EigBufs {
                     // eigenvectors of T, column t at t * kMaxEig (eigensolver -> back-transform)
 };
 constexpr int kEigYOff = 2 * kMaxEig;
-constexpr size_t kEigYDoubles = (size_t)kEigYOff + 64 * (size_t)kMaxEig;
+// after the eigenvectors: the scaled T (d, e, e^2), tau, the trace and the Gershgorin norm,
+// handed between the kernels of a single (unbatched) eigensolve
+constexpr int kEigTOff = kEigYOff + 64 * kMaxEig;
+constexpr size_t kEigYDoubles = (size_t)kEigTOff + 5 * (size_t)kMaxEig + 8;
 constexpr int kEigBtCols = 4;                 // back-transform: columns (one wave each) per work-group
 constexpr int kEigBtBlocks = 64 / kEigBtCols; // work-groups per eigensolve (at most 64 columns)
 

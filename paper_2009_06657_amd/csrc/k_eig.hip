@@ -1,6 +1,7 @@
 // FP64 eigensolver of the small Gram matrix G (order N <= 128) and the truncation rule
-// (Sec. II.B; Theorem 1, App. B) on the serial path between the Gram and projection GEMMs: a
-// single-work-group kernel (steps 1-5) and a short multi-work-group back-transform (step 6).
+// (Sec. II.B; Theorem 1, App. B) on the serial path between the Gram and projection GEMMs: one
+// work-group for steps 1-2 (and the scaling of T), one work-group per wave for step 3, one
+// work-group for steps 4-5, and a short multi-work-group back-transform (step 6).
 //
 //  1. Assemble G from S = X^H X and the Kraus set, G_{(a,v),(b,w)} = sum_{uv'} (E_a^H E_b)_{uv'}
 //     S_{(u,v),(v',w)} (split view) or G = S (plain view).  G lives in registers: half-wave R
@@ -12,8 +13,9 @@
 //     DPP moves, and the rank-2 update is register arithmetic on the rows not yet eliminated:
 //     two barriers per step.  At order 128 the last 64 steps run on the trailing block moved to
 //     a layout with a quarter of the registers per thread.
-//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a group of up to 16
-//     lanes per eigenvalue).
+//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (32 lanes per
+//     eigenvalue, two eigenvalues per wave, each wave a work-group of its own; recorded solves
+//     use 8 or 16 lanes).
 //  4. Eigenvectors of T by inverse iteration on the LDL^T factorisation of T - lambda I (one
 //     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than 1e-9 ||T|| form
 //     clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending order)
@@ -465,9 +467,14 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], z64 (&vloc)[BC], z64&
   __syncthreads();
 }
 
-// G lanes per eigenvalue for a work-group of nth threads: the largest G <= 16 whose groups
-// (64 / G per wave, never across waves; left-over lanes idle) cover the kmax eigenvalues
-__host__ __device__ __forceinline__ int eig_lanes(int nth, int kmax) {
+// Lanes per eigenvalue of the multisection: two eigenvalues per wave, a 33-section per step.
+// Recorded solves (reverse sweep, eigenvalues to 4 eps^2) keep the lane count of a work-group of
+// 256 threads (order <= 32) or 512, the largest G <= 16 that covers kmax with 64 / G groups per
+// wave, whose eigenvalues the reverse sweep was validated with.
+constexpr int kSturmLanes = 32;
+__host__ __device__ __forceinline__ int sturm_lanes(int N, int kmax, bool rec) {
+  if (!rec) return kSturmLanes;
+  const int nth = N <= 32 ? 256 : 512;
   int G = 16;
   while (G > 1 && (64 / G) * (nth / 64) < kmax) --G;
   return G;
@@ -494,8 +501,8 @@ __device__ __forceinline__ void multisection_wave(const double* d_s, const doubl
   // differences to relative accuracy and runs the relative rule down to 4 eps^2.
   const double floor_w = rec ? 4 * epsm * epsm : 4 * epsm;
   double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
-  // every layout gives G >= 4: (G + 1)-section reaches 4 eps^2 from width 2 in at most 44
-  // iterations; the loop ends as soon as every bracket has converged
+  // a 33-section reaches 4 eps^2 from width 2 in at most 21 iterations, 4 eps in 11; the loop
+  // ends as soon as every bracket of the wave has converged
   for (int it = 0; it < 64; ++it) {
     const double w = hi - lo;
     const bool done = !(w > 2 * epsm * fmax(fabs(lo), fabs(hi)) + floor_w);
@@ -504,7 +511,7 @@ __device__ __forceinline__ void multisection_wave(const double* d_s, const doubl
     const int cnt = (active && !done) ? sturm_count(d_s, e2_s, N, x, pivmin) : 0;
     const unsigned long long ball = __ballot(active && !done && cnt > asc);
     const int gb = gi * G;
-    const unsigned long long grp = (ball >> gb) & ((1ull << G) - 1ull);
+    const unsigned long long grp = (ball >> gb) & (G >= 64 ? ~0ull : ((1ull << G) - 1ull));
     const int first = grp ? (__ffsll((long long)grp) - 1) : G;
     const double xh = __shfl(x, min(gb + (first < G ? first : 0), 63), 64);
     const double xl = __shfl(x, min(gb + (first == 0 ? 0 : first - 1), 63), 64);
@@ -747,7 +754,6 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   }
   const double tnorm = sc_s[1];
   const bool zero = !(tnorm > 0.0);
-  if constexpr (PART == 0) multisection_wave(d_s, e2_s, N, kmax, eig_lanes(NTH, kmax), wave, zero, B.rec != nullptr, lam_s);
   __syncthreads();
   if (tid == 0) {
     const double ctol = 1e-9;
@@ -1119,11 +1125,11 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
   }
 }
 
-// A single solve runs in three kernels: part 1 (assembly, tridiagonal reduction, scaling of T)
-// and part 2 (eigenvectors of T, rank rule) on one work-group each, and between them the
-// multisection with each wave of the fused layout in a work-group of its own, so each runs on its
-// own CU instead of two waves sharing a SIMD (the Sturm counts are issue-bound there).  The
-// eigenvalues are the same bits as the fused kernel's.
+// A solve runs in three kernels before the back-transform: part 1 (assembly, tridiagonal
+// reduction, scaling of T) and part 2 (eigenvectors of T, rank rule) on one work-group each, and
+// between them the multisection with one work-group per wave (two eigenvalues per wave), each on
+// a CU of its own, so the Sturm counts run at their latency instead of sharing SIMDs.  The batched
+// twins take one job (or one job's wave) per work-group and compute the same bits.
 template <int BR, int BC>
 __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_reduce_kernel(const double* __restrict__ S, int Fc,
                                                                          Channel ch, int nsplit, int c, int N,
@@ -1140,9 +1146,9 @@ __global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_vectors_kernel(const 
   eig_body<BR, BC, 2>(S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, B);
 }
 
-// wave blockIdx.x of the fused layout's multisection (G lanes per eigenvalue)
-__global__ __launch_bounds__(64) void eig_sturm_kernel(int N, int kmax, int G, const double* __restrict__ Tst,
-                                                       double* __restrict__ lam, int rec) {
+__device__ __forceinline__ void sturm_body(int N, int kmax, int wv, const double* __restrict__ Tst,
+                                           double* __restrict__ lam, bool rec) {
+  const int G = sturm_lanes(N, kmax, rec);
   __shared__ double d_s[kMaxEig], e2_s[kMaxEig];
   for (int i = threadIdx.x; i < N; i += 64) {
     d_s[i] = Tst[i];
@@ -1150,14 +1156,40 @@ __global__ __launch_bounds__(64) void eig_sturm_kernel(int N, int kmax, int G, c
   }
   __syncthreads();
   const bool zero = !(Tst[5 * kMaxEig + 1] > 0.0);
-  multisection_wave(d_s, e2_s, N, kmax, G, blockIdx.x, zero, rec != 0, lam);
+  multisection_wave(d_s, e2_s, N, kmax, G, wv, zero, rec, lam);
+}
+
+// waves of one solve's multisection (at most kmax / 2: every G is 8 or more for kmax > 16)
+__host__ __device__ __forceinline__ int sturm_waves(int N, int kmax, bool rec) {
+  const int per = 64 / sturm_lanes(N, kmax, rec);
+  return (kmax + per - 1) / per;
+}
+
+__global__ __launch_bounds__(64) void eig_sturm_kernel(int N, int kmax, const double* __restrict__ Tst,
+                                                       double* __restrict__ lam, int rec) {
+  sturm_body(N, kmax, blockIdx.x, Tst, lam, rec != 0);
 }
 
 // One work-group per job; every job of a launch has the same size class (BR, BC).
 template <class T, int BR, int BC>
-__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_batched(const EigJob<T>* __restrict__ jobs) {
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_reduce_batched(const EigJob<T>* __restrict__ jobs) {
   const EigJob<T>& J = jobs[blockIdx.x];
-  eig_body<BR, BC, 0>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
+  eig_body<BR, BC, 1>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
+}
+
+template <class T, int BR, int BC>
+__global__ __launch_bounds__(32 * (32 * BC / BR)) void eig_vectors_batched(const EigJob<T>* __restrict__ jobs) {
+  const EigJob<T>& J = jobs[blockIdx.x];
+  eig_body<BR, BC, 2>(J.S, J.Fc, J.ch, J.nsplit, J.c, J.N, J.kmax, J.r_target, J.eps, J.tie, J.renorm, J.B);
+}
+
+// wpj work-groups (waves) per job; a job with fewer eigenvalues leaves its last ones idle
+template <class T>
+__global__ __launch_bounds__(64) void eig_sturm_batched(const EigJob<T>* __restrict__ jobs, int wpj) {
+  const EigJob<T>& J = jobs[blockIdx.x / wpj];
+  const int wv = blockIdx.x % wpj;
+  if (wv >= sturm_waves(J.N, J.kmax, J.B.rec != nullptr)) return;   // uniform over the work-group
+  sturm_body(J.N, J.kmax, wv, J.B.Y + kEigTOff, J.B.lam, J.B.rec != nullptr);
 }
 
 template <class T, int RPL>
@@ -1196,9 +1228,18 @@ static hipError_t launch_eig_batched_bs(const EigJob<T>* jobs, int njobs, int km
   constexpr int NP = 32 * BC;
   constexpr int NTH = 32 * (NP / BR);
   const size_t shm = eig_shm<BR, BC>(kmax_max);
-  hipError_t e = allow_shm(eig_batched<T, BR, BC>, shm);
+  hipError_t e = allow_shm(eig_reduce_batched<T, BR, BC>, shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((eig_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
+  e = allow_shm(eig_vectors_batched<T, BR, BC>, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_reduce_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int wpj = (kmax_max + 1) / 2;   // the most waves any job of the launch needs
+  hipLaunchKernelGGL(eig_sturm_batched<T>, dim3(njobs * wpj), dim3(64), 0, s, jobs, wpj);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eig_vectors_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int RPL = NP > 64 ? 2 : 1;
@@ -1235,10 +1276,8 @@ static hipError_t launch_eig_bs(const double* S, int Fc, const Channel& ch, int 
                      r_target, eps, tie, renorm, b);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int G = eig_lanes(NTH, kmax);
-  const int waves = (kmax + 64 / G - 1) / (64 / G);
-  hipLaunchKernelGGL(eig_sturm_kernel, dim3(waves), dim3(64), 0, s, N, kmax, G, b.Y + kEigTOff, b.lam,
-                     b.rec ? 1 : 0);
+  hipLaunchKernelGGL(eig_sturm_kernel, dim3(sturm_waves(N, kmax, b.rec != nullptr)), dim3(64), 0, s, N, kmax,
+                     b.Y + kEigTOff, b.lam, b.rec ? 1 : 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eig_vectors_kernel<BR, BC>), dim3(1), dim3(NTH), shm, s, S, Fc, ch, nsplit, c, N, kmax,

@@ -13,9 +13,8 @@
 //     DPP moves, and the rank-2 update is register arithmetic on the rows not yet eliminated:
 //     two barriers per step.  At order 128 the last 64 steps run on the trailing block moved to
 //     a layout with a quarter of the registers per thread.
-//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (32 lanes per
-//     eigenvalue, two eigenvalues per wave, each wave a work-group of its own; recorded solves
-//     use 8 or 16 lanes).
+//  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a wave per
+//     eigenvalue, each wave a work-group of its own; recorded solves use 8 or 16 lanes).
 //  4. Eigenvectors of T by inverse iteration on the LDL^T factorisation of T - lambda I (one
 //     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than 1e-9 ||T|| form
 //     clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending order)
@@ -467,11 +466,11 @@ __device__ __forceinline__ void tri_step(z64 (&A)[BR][BC], z64 (&vloc)[BC], z64&
   __syncthreads();
 }
 
-// Lanes per eigenvalue of the multisection: two eigenvalues per wave, a 33-section per step.
+// Lanes per eigenvalue of the multisection: one eigenvalue per wave, a 65-section per step.
 // Recorded solves (reverse sweep, eigenvalues to 4 eps^2) keep the lane count of a work-group of
 // 256 threads (order <= 32) or 512, the largest G <= 16 that covers kmax with 64 / G groups per
 // wave, whose eigenvalues the reverse sweep was validated with.
-constexpr int kSturmLanes = 32;
+constexpr int kSturmLanes = 64;
 __host__ __device__ __forceinline__ int sturm_lanes(int N, int kmax, bool rec) {
   if (!rec) return kSturmLanes;
   const int nth = N <= 32 ? 256 : 512;
@@ -481,9 +480,9 @@ __host__ __device__ __forceinline__ int sturm_lanes(int N, int kmax, bool rec) {
 }
 
 // The leading eigenvalues of the scaled T (diagonal d, squared off-diagonal e2) handled by wave
-// w of the fused layout: eigenvalue t = w (64 / G) + lane / G, its G lanes counting at the
-// interior points of G + 1 equal sections of its bracket.  Each eigenvalue's bracket sequence
-// depends only on T, G and its own counts, so every placement of the waves gives the same bits.
+// wv: eigenvalue t = wv (64 / G) + lane / G, its G lanes counting at the interior points of
+// G + 1 equal sections of its bracket.  Each eigenvalue's bracket sequence depends only on T, G
+// and its own counts, so batched and single solves give the same bits.
 __device__ __forceinline__ void multisection_wave(const double* d_s, const double* e2_s, int N, int kmax, int G,
                                                   int wv, bool zero, bool rec, double* lam_out) {
   const double epsm = 2.220446049250313e-16;
@@ -501,7 +500,7 @@ __device__ __forceinline__ void multisection_wave(const double* d_s, const doubl
   // differences to relative accuracy and runs the relative rule down to 4 eps^2.
   const double floor_w = rec ? 4 * epsm * epsm : 4 * epsm;
   double lo = -1.0 - 4 * epsm, hi = 1.0 + 4 * epsm;
-  // a 33-section reaches 4 eps^2 from width 2 in at most 21 iterations, 4 eps in 11; the loop
+  // a 65-section reaches 4 eps in 9 iterations, a 9-section 4 eps^2 in at most 33; the loop
   // ends as soon as every bracket of the wave has converged
   for (int it = 0; it < 64; ++it) {
     const double w = hi - lo;
@@ -1127,7 +1126,7 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
 
 // A solve runs in three kernels before the back-transform: part 1 (assembly, tridiagonal
 // reduction, scaling of T) and part 2 (eigenvectors of T, rank rule) on one work-group each, and
-// between them the multisection with one work-group per wave (two eigenvalues per wave), each on
+// between them the multisection with one work-group per wave (one eigenvalue per wave), each on
 // a CU of its own, so the Sturm counts run at their latency instead of sharing SIMDs.  The batched
 // twins take one job (or one job's wave) per work-group and compute the same bits.
 template <int BR, int BC>
@@ -1159,7 +1158,7 @@ __device__ __forceinline__ void sturm_body(int N, int kmax, int wv, const double
   multisection_wave(d_s, e2_s, N, kmax, G, wv, zero, rec, lam);
 }
 
-// waves of one solve's multisection (at most kmax / 2: every G is 8 or more for kmax > 16)
+// waves of one solve's multisection (at most kmax)
 __host__ __device__ __forceinline__ int sturm_waves(int N, int kmax, bool rec) {
   const int per = 64 / sturm_lanes(N, kmax, rec);
   return (kmax + per - 1) / per;
@@ -1235,7 +1234,7 @@ static hipError_t launch_eig_batched_bs(const EigJob<T>* jobs, int njobs, int km
   hipLaunchKernelGGL((eig_reduce_batched<T, BR, BC>), dim3(njobs), dim3(NTH), shm, s, jobs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int wpj = (kmax_max + 1) / 2;   // the most waves any job of the launch needs
+  const int wpj = kmax_max;   // the most waves any job of the launch needs
   hipLaunchKernelGGL(eig_sturm_batched<T>, dim3(njobs * wpj), dim3(64), 0, s, jobs, wpj);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -754,15 +754,38 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   const double tnorm = sc_s[1];
   const bool zero = !(tnorm > 0.0);
   __syncthreads();
-  if (tid == 0) {
+  if (wave == 0) {
+    // clusters: a cluster starts at t = 0 and wherever lam_{t-1} - lam_t > 1e-9 (scaled T); one
+    // ballot per 64 eigenvalues marks the starts (kmax <= 128, two words)
     const double ctol = 1e-9;
-    int s = 0;
-    for (int t = 0; t < kmax; ++t) {
-      if (t > 0 && !(lam_s[t - 1] - lam_s[t] <= ctol)) s = t;
-      cl_start[t] = s;
-      cl_len[t] = 0;
+    unsigned long long starts[2] = {0ull, 0ull};
+    for (int c = 0; c < 2; ++c) {
+      const int t = 64 * c + lane;
+      const bool st = t < kmax && (t == 0 || !(lam_s[t - 1] - lam_s[t] <= ctol));
+      starts[c] = __ballot(st);
     }
-    for (int t = 0; t < kmax; ++t) cl_len[cl_start[t]] += 1;
+    for (int c = 0; c < 2; ++c) {
+      const int t = 64 * c + lane;
+      if (t < kmax) {
+        // start of t's cluster: the last start at or before t
+        const unsigned long long upto = starts[c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+        int s0;
+        if (upto) s0 = 64 * c + 63 - __clzll((long long)upto);
+        else s0 = 63 - __clzll((long long)starts[0]);   // c == 1: the last start of the first word
+        cl_start[t] = s0;
+        // length (read for starts only): up to the next start, or to kmax
+        int len = 0;
+        if (s0 == t) {
+          const unsigned long long after = (lane == 63) ? 0ull : (starts[c] >> (lane + 1)) << (lane + 1);
+          int nxt;
+          if (after) nxt = 64 * c + __ffsll((long long)after) - 1;
+          else if (c == 0 && starts[1]) nxt = 64 + __ffsll((long long)starts[1]) - 1;
+          else nxt = kmax;
+          len = nxt - t;
+        }
+        cl_len[t] = len;
+      }
+    }
   }
   __syncthreads();
 

@@ -6,7 +6,7 @@ damping (gamma = 0.002) -> compress -> dephasing (p = 0.001) -> compress (1600 c
 then <Z_i Z_{i+1}> for all neighbours and 10^4 samples.  Complex FP32 bulk (FP32 MFMA Gram and
 projection), FP64 eigensolve.  Inputs are seeded and synthetic.
 
-Prints one JSON line (rank 0).  --gpus > 1 is not supported: this build runs on one GPU.
+Prints one JSON line (rank 0).  --gpus > 1 is not supported: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -230,7 +230,7 @@ def fixed_rank_distortion() -> dict:
     from workloads import circuits as C
 
     t0 = time.perf_counter()
-    configs = {}
+    per_workload = {}
     for name, prog, dt in (("n6_r13_depolarizing_c128", C.cfg1_program(), lr.C128),
                            ("grover_n14_r32", C.cfg2_program(), lr.C64),
                            ("ry_rz_cz_n12_r16", C.cfg4_program(C.cfg4_angles()), lr.C64)):
@@ -238,11 +238,11 @@ def fixed_rank_distortion() -> dict:
         # layers whose exact diagonal is within 1e-3 of the noiseless one (e.g. a uniform
         # superposition, which depolarizing noise leaves uniform) give no meaningful ratio
         by_layer = [d if den >= 1e-3 else None for d, den in zip(res["distortion"], res["exact_minus_noiseless"])]
-        configs[name] = {"distortion_final": res["distortion"][-1], "distortion_by_layer": by_layer,
+        per_workload[name] = {"distortion_final": res["distortion"][-1], "distortion_by_layer": by_layer,
                          "layers": len(res["distortion"]), "max_rank": res["max_rank"], "r": prog.r,
                          "compressions": res["compressions"]}
         print(f"accuracy: {name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
-    return configs
+    return per_workload
 
 
 def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
@@ -261,7 +261,7 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
 
     lr.load_library()
     t0 = time.perf_counter()
-    configs = fixed_rank_distortion()
+    fixed = fixed_rank_distortion()
     depths = [d for d in (4, 8, 12) if d <= depth]
     studies = []
     eps_grid = (1e-2, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5)
@@ -294,7 +294,7 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     return {"workload": f"random circuits (dense/sparse x local/global, paper gate set), depth {depth}, "
                         f"seeds {list(seeds)}; low rank (complex FP32, FP64 eigensolve, plain threshold "
                         "rule) vs full-rank density matrix (complex FP32), both on the GPU",
-            "seconds": time.perf_counter() - t0, "configs": configs, "rows": rows}
+            "seconds": time.perf_counter() - t0, "fixed_rank": fixed, "rows": rows}
 
 
 def batched_serving(count: int = 256, loop_budget_s: float = 30.0) -> dict:
@@ -399,7 +399,7 @@ def main():
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(sharding is described in the design notes)", file=sys.stderr)
         sys.exit(2)
 

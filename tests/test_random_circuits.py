@@ -102,3 +102,23 @@ def test_distortion_vanishes_and_grows():
         d.append(distortion(P, exact, quiet))
     assert d[0] < 1e-10
     assert 0 < d[1] <= d[2] <= d[3]
+
+
+def test_accuracy_host_logic():
+    """Host side of the GPU distortion studies: the ratio matches the oracle's definition
+    (Sec. III, Eq. "distortion"), is undefined (NaN) when noise leaves the diagonal unchanged, and
+    the noiseless program keeps every gate, phase and layer marker in order while dropping the
+    channels and compressions."""
+    from oracle.observables import distortion as distortion_ref
+    from paper_2009_06657_amd import accuracy as A
+
+    rng = np.random.default_rng(3)
+    a, b, c = (rng.dirichlet(np.ones(32)) for _ in range(3))
+    assert abs(A.distortion(a, b, c) - distortion_ref(a, b, c)) <= 1e-15
+    assert np.isnan(A.distortion(a, b, b))
+    prog = C.random_circuit(5, 4, "sparse-local", "ad", p=0.01, r=8, eps=1e-4, seed=9)
+    clean = A.noiseless_program(prog)
+    kept = [op for op in prog.ops if not isinstance(op, (C.Kraus, C.Compress))]
+    assert clean.ops == kept and clean.n == prog.n and clean.layers == prog.layers
+    assert not any(isinstance(op, (C.Kraus, C.Compress)) for op in clean.ops)
+    assert sum(isinstance(op, C.LayerEnd) for op in clean.ops) == 4

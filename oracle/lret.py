@@ -12,12 +12,13 @@ Readings where the paper is silent (each also listed in the design notes):
     sqrt(lambda_i), so the truncated state sum_{i<=k} lambda_i u_i u_i^H equals
     (L' V_k)(L' V_k)^H: the new factor is L' V_k (times the renormalisation scale c).
   * Rank rule.  k = min(r, N, k_eps).  k_eps is the smallest k whose kept mass
-    K_k = sum_{i<=k} max(lambda_i, 0) reaches (1 - eps) Tr G ("picked up one by one until they
-    sum to 1 - eps", Sec. II.B, measured against the trace rather than against 1); eps = 0
-    disables the threshold (fixed-rank mode).
+    K_k = sum_{i<=k} max(lambda_i, 0) reaches (1 - eps) Tr G: the eigenvalues are taken in
+    descending order until their sum reaches the target (Sec. II.B), measured against the trace
+    rather than against 1; eps = 0 disables the threshold (fixed-rank mode).
   * Ties.  tie=1 ("cluster") lowers k while lambda_k - lambda_{k+1} <= TAU_CLUSTER * Tr G, so
-    that the kept set is gap-separated and the truncated state is unique; tie=0 keeps the
-    eigensolver's order.
+    that the kept set is gap-separated and the truncated state is unique; beyond the Gram order
+    N the spectrum of rho' continues with zeros (lambda_{N+1} = 0), so the rule does not depend
+    on how many zero columns the factor carries; tie=0 keeps the eigensolver's order.
   * Renormalisation.  renorm=1 scales the kept part to unit trace, c = K_k^{-1/2}; renorm=0 is
     the paper-literal truncation (c = 1).
   * Discarded mass delta = Tr G - K_k.
@@ -63,7 +64,8 @@ def select_rank(lam_desc: np.ndarray, trace: float, r: int, eps: float, tie: int
         k_eps = int(hit[0]) + 1 if hit.size else N
         k = min(k, k_eps)
     if tie == 1:
-        while 1 < k < N and (lam_desc[k - 1] - lam_desc[k]) <= tau * trace:
+        # beyond the Gram order the spectrum of rho' continues with zeros (rank <= N)
+        while k > 1 and (lam_desc[k - 1] - (lam_desc[k] if k < N else 0.0)) <= tau * trace:
             k -= 1
     return max(k, 1)
 

@@ -16,9 +16,10 @@
 //  3. The wanted (largest) eigenvalues of T by multisection on Sturm counts (a wave per
 //     eigenvalue, each wave a work-group of its own; recorded solves use 8 or 16 lanes).
 //  4. Eigenvectors of T by inverse iteration on the LDL^T factorisation of T - lambda I (one
-//     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than 1e-9 ||T|| form
-//     clusters whose vectors are re-orthonormalised (modified Gram-Schmidt, descending order)
-//     after every iteration, so (near-)degenerate eigenvalues yield an orthonormal basis.
+//     lane per eigenvector, factors and vectors in LDS).  Eigenvalues closer than
+//     max(1e-9 ||T||, 1e-3 lambda) form clusters whose vectors are re-orthonormalised (modified
+//     Gram-Schmidt, descending order) after every iteration, so (near-)degenerate eigenvalues
+//     yield an orthonormal basis.
 //  5. The rank rule (cap r, threshold eps, tie policy), discarded mass and renormalisation
 //     scale.  The reflectors, their scalars and the kept eigenvectors of T go to the workspace.
 //  6. A second kernel over 16 work-groups (one wave per kept eigenvector) back-transforms
@@ -755,13 +756,15 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   const bool zero = !(tnorm > 0.0);
   __syncthreads();
   if (wave == 0) {
-    // clusters: a cluster starts at t = 0 and wherever lam_{t-1} - lam_t > 1e-9 (scaled T); one
-    // ballot per 64 eigenvalues marks the starts (kmax <= 128, two words)
-    const double ctol = 1e-9;
+    // clusters: a cluster starts at t = 0 and wherever lam_{t-1} - lam_t > max(1e-9, 1e-3
+    // lam_{t-1}) (scaled T).  Inverse iteration leaves the vectors of eigenvalues a gap g apart
+    // with an overlap near eps / g, which moves rho by about sqrt(lam_i lam_j) eps / g: the
+    // relative window keeps that near 1e-13 without joining a graded spectrum into one cluster.
+    // One ballot per 64 eigenvalues marks the starts (kmax <= 128, two words).
     unsigned long long starts[2] = {0ull, 0ull};
     for (int c = 0; c < 2; ++c) {
       const int t = 64 * c + lane;
-      const bool st = t < kmax && (t == 0 || !(lam_s[t - 1] - lam_s[t] <= ctol));
+      const bool st = t < kmax && (t == 0 || !(lam_s[t - 1] - lam_s[t] <= fmax(1e-9, 1e-3 * fabs(lam_s[t - 1]))));
       starts[c] = __ballot(st);
     }
     for (int c = 0; c < 2; ++c) {
@@ -940,8 +943,8 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
       }
       k = min(k, keps);
     }
-    if (tie == 1)
-      while (k > 1 && k < N && (lam_s[k - 1] - lam_s[k]) <= 1e-6 * trace) --k;
+    if (tie == 1)   // the spectrum continues with zeros beyond the Gram order
+      while (k > 1 && (lam_s[k - 1] - (k < N ? lam_s[k] : 0.0)) <= 1e-6 * trace) --k;
     if (k < 1) k = 1;
     double kept = 0;
     for (int i = 0; i < k; ++i) kept += fmax(lam_s[i], 0.0);

@@ -244,6 +244,17 @@ def test_select_rank_rules():
     # cluster: a cut inside the 0.1/0.1 tie moves up; a near-tie within tau moves too
     assert oracle.select_rank(lam, tr, 3, 0.0, 1) == 2
     assert oracle.select_rank(lam, tr, 5, 0.0, 1) == 4
+    # beyond the Gram order the spectrum continues with zeros: keeping all N columns, the cut
+    # against lambda_{N+1} = 0 drops a last eigenvalue within tau Tr G of zero (here the exact
+    # zero; the next gap, 0.05 - 1e-9 against 0, stops it), and padding the spectrum with zeros
+    # changes nothing
+    assert oracle.select_rank(lam, tr, 10, 0.0, 1) == 6
+    tiny = np.array([0.6, 0.4 - 5e-7, 5e-7])
+    assert oracle.select_rank(tiny, 1.0, 3, 0.0, 1) == 2
+    assert oracle.select_rank(tiny, 1.0, 3, 0.0, 0) == 3
+    for r in (2, 3, 5):
+        padded = np.concatenate([tiny, np.zeros(6)])
+        assert oracle.select_rank(padded, 1.0, r, 0.0, 1) == oracle.select_rank(tiny, 1.0, r, 0.0, 1)
 
 
 # ---------------------------------------------------------------- pins 6, 9: whole path vs FDM

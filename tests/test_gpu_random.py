@@ -197,9 +197,10 @@ def _sweep_program(seed):
 
 # programs whose complex128 result misses 1e-10 for a known, unfixed reason
 _SWEEP_OPEN = {
-    53: "2e-9: a kept and a discarded eigenvalue 1.05e-3 apart (relative) at the cut of the 18th "
-        "compression; the unpivoted LDL^T inverse iteration leaves the kept vector ~1e-7 off, and "
-        "more iterations make it worse (a pivoted or twisted factorisation is the fix)",
+    53: "2e-9, cause not found: the error appears at the 18th compression, whose cut separates a "
+        "kept and a discarded eigenvalue 1.05e-3 apart (relative); the oracle is well conditioned "
+        "there, a CPU emulation of the eigenvector step on that matrix is exact, and a third "
+        "inverse iteration on the GPU makes the error larger",
 }
 
 

@@ -106,7 +106,8 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e);
  *  r_target in [1, r_max]: rank cap.  eps in [0, 1): keep the smallest k whose kept mass
  *  sum_{i<=k} max(lambda_i, 0) reaches (1 - eps) Tr G (eps = 0 disables the threshold).
  *  tie_policy: 0 = keep eigensolver order; 1 = lower k while lambda_k - lambda_{k+1} <=
- *  1e-6 Tr G so the kept set is gap-separated.  renorm: 1 = scale to unit trace
+ *  1e-6 Tr G so the kept set is gap-separated (the spectrum continues with zeros past the Gram
+ *  order, so zero-eigenvalue columns are dropped too).  renorm: 1 = scale to unit trace
  *  (c = kept^{-1/2}), 0 = c = 1.  The Gram matrix is accumulated in the bulk precision (FP32
  *  MFMA for LRDM_C64) and diagonalised in FP64.  info may be NULL; if not, the call
  *  synchronises the stream and fills it. */

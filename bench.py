@@ -251,7 +251,9 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     the paper's gate set, averaged over seeds, at depths 4, 8 and 12 (one run per circuit gives
     every depth).  Studies: depolarizing p = 0.1 % over n and eps (Fig. 4); p = 0.3 % and 1 %
     with eps/p in {1, 0.3, 0.1, 0.03, 0.01} (Fig. 5); bit flip and amplitude damping p = 0.1 %
-    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8).  First, the
+    (Fig. 7); the three circuit types under bit flip at n = 13, eps = 1e-4 (Fig. 8); and Fig. 5's
+    strengths with depolarizing written as X, Y and Z flips (a compression after each, r = 64).
+    First, the
     distortion of the fixed-rank workloads: n = 6 depolarizing (r = 13, complex128), noisy Grover
     at n = 14 (r = 32) and the RY/RZ/CZ ansatz at n = 12 (r = 16).  Rank caps:
     r = 32 for depolarizing (four Kraus operators, Gram order 4r <= 128), 64 otherwise; the
@@ -270,6 +272,9 @@ def accuracy_sweep(seeds=(1, 2, 3), depth: int = 12) -> dict:
     for p in (3e-3, 1e-2):
         for n in (6, 8, 10, 12):
             studies.append(("fig5-noise-strength", n, "dense-local", "dep", p, tuple(p * f for f in (1, .3, .1, .03, .01))))
+    for p in (3e-3, 1e-2):   # the same, depolarizing written as three flips: rank cap 64
+        for n in (6, 8, 10, 12):
+            studies.append(("fig5-noise-strength-flips", n, "dense-local", "dep3", p, tuple(p * f for f in (1, .3, .1, .03, .01))))
     for ch in ("bitflip", "ad"):
         for n in (4, 6, 8, 10, 12):
             studies.append(("fig7-channels", n, "dense-local", ch, 1e-3, eps_grid))

@@ -105,6 +105,17 @@ def test_random_circuit_adaptive_threshold_complex128(lr, kind):
     assert float(np.max(np.abs(P - P_ref))) <= 1e-10
 
 
+def test_random_circuit_depolarizing_as_flips_complex128(lr):
+    """Depolarizing written as three flips (a compression after each), complex128 against the
+    oracle: every rank and the probabilities within 1e-10."""
+    _say("random dense-local dep3 c128 eps=1e-4")
+    prog = C.random_circuit(6, 5, "dense-local", "dep3", p=0.005, r=32, eps=1e-4, seed=33, dtype="c128", tie=1)
+    P_ref, k_ref, near, _ = _oracle(prog)
+    P, k = _gpu(lr, prog, lr.C128)
+    assert not any(near) and k == k_ref
+    assert float(np.max(np.abs(P - P_ref))) <= 1e-10
+
+
 def _oracle_reference_layers(prog):
     """Exact (full-rank density matrix) and noiseless (state vector) diagonals after each layer."""
     from oracle.fdm import fdm_channel, fdm_gate

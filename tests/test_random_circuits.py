@@ -122,3 +122,26 @@ def test_accuracy_host_logic():
     assert clean.ops == kept and clean.n == prog.n and clean.layers == prog.layers
     assert not any(isinstance(op, (C.Kraus, C.Compress)) for op in clean.ops)
     assert sum(isinstance(op, C.LayerEnd) for op in clean.ops) == 4
+
+
+def test_depolarizing_as_three_flips_is_exact():
+    """The X, Y and Z flips with a = (1 - sqrt(1 - 4p/3)) / 2, applied in turn, are the
+    depolarizing channel of Sec. III.A.1: the same map on random density matrices (FP64 oracle),
+    and the dep3 circuits differ from dep ones only in the channel's Kraus sets."""
+    from oracle.fdm import fdm_channel
+
+    rng = np.random.default_rng(4)
+    for p in (0.001, 0.01, 0.3):
+        A = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+        rho = A @ A.conj().T
+        rho /= np.trace(rho).real
+        want = fdm_channel(rho, 2, 1, C.depolarizing(p))
+        got = rho
+        for ks in C.depolarizing_as_flips(p):
+            got = fdm_channel(got, 2, 1, ks)
+        assert np.max(np.abs(got - want)) <= 1e-15
+    a = C.random_circuit(4, 3, "dense-local", "dep", p=0.01, r=8, seed=2)
+    b = C.random_circuit(4, 3, "dense-local", "dep3", p=0.01, r=8, seed=2)
+    assert [o.u.tobytes() for o in a.ops if isinstance(o, C.Gate)] == [o.u.tobytes() for o in b.ops if isinstance(o, C.Gate)]
+    assert sum(isinstance(o, C.Kraus) for o in b.ops) == 3 * sum(isinstance(o, C.Kraus) for o in a.ops)
+    assert b.m_max == 2 and a.m_max == 4

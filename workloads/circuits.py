@@ -255,10 +255,11 @@ def random_circuit(n: int, depth: int, kind: str = "dense-local", channel: str =
                 touched.append(q)
         if noise:
             for q in (sorted(touched) if kind.startswith("sparse") else range(n)):
-                ops.append(Kraus(q, _channel(channel, p), channel))
-                ops.append(Compress(r, eps, tie, renorm))
+                for ks in _channels(channel, p):
+                    ops.append(Kraus(q, ks, channel))
+                    ops.append(Compress(r, eps, tie, renorm))
         ops.append(LayerEnd(t))
-    m_max = _channel(channel, p).shape[0] if noise else 1
+    m_max = max(ks.shape[0] for ks in _channels(channel, p)) if noise else 1
     return Program(n, ops, r, dtype, m_max, f"random-{kind}", depth,
                    {"kind": kind, "channel": channel, "p": p, "eps": eps, "seed": seed})
 
@@ -266,6 +267,29 @@ def random_circuit(n: int, depth: int, kind: str = "dense-local", channel: str =
 def _channel(ch: str, p: float) -> np.ndarray:
     return {"dep": depolarizing, "bitflip": bit_flip, "deph": phase_flip,
             "ad": amplitude_damping}[ch](p)
+
+
+def pauli_flip(P: np.ndarray, a: float) -> np.ndarray:
+    """(1 - a) rho + a P rho P for a Pauli P."""
+    return np.stack([np.sqrt(1 - a) * I2, np.sqrt(a) * P])
+
+
+def depolarizing_as_flips(p: float) -> List[np.ndarray]:
+    """The depolarizing channel as three two-operator channels, X, Y and Z flips with the same
+    probability a.  Pauli channels compose by multiplying their Pauli eigenvalues: a flip about P
+    keeps P and scales the two others by 1 - 2a, so the three flips scale each of X, Y, Z by
+    (1 - 2a)^2; depolarizing scales each by 1 - 4p/3, hence a = (1 - sqrt(1 - 4p/3)) / 2."""
+    a = 0.5 * (1.0 - np.sqrt(1.0 - 4.0 * p / 3.0))
+    return [pauli_flip(X, a), pauli_flip(Y, a), pauli_flip(Z, a)]
+
+
+def _channels(ch: str, p: float) -> List[np.ndarray]:
+    """The channel as a list of Kraus sets applied in turn, each followed by a compression:
+    "dep3" is depolarizing written as three flips (two operators each, so a rank cap up to 64
+    fits the order-128 eigensolver; three truncations instead of one)."""
+    if ch == "dep3":
+        return depolarizing_as_flips(p)
+    return [_channel(ch, p)]
 
 
 def cfg1_program(n: int = 6, r: int = 13, layers: int = 20, p: float = 0.0033, seed: int = 1001,

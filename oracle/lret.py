@@ -73,20 +73,21 @@ def select_rank(lam_desc: np.ndarray, trace: float, r: int, eps: float, tie: int
 def compress(L: np.ndarray, r: int, eps: float = 0.0, tie: int = 0, renorm: int = 1):
     """Eigenvalue truncation of rho' = L'L'^H through G = L'^H L' (Theorem 1).
 
-    Returns (L_new, info) with L_new = c L' V_k and info = {k, discarded, trace, gap, lam}."""
+    Returns (L_new, info) with L_new = c L' V_k and info = {k, discarded, trace, gap, lam_k
+    (the smallest kept eigenvalue), lam, scale}."""
     G = L.conj().T @ L                       # Gram matrix, V x V (Theorem 1: shares rho's spectrum)
     G = 0.5 * (G + G.conj().T)
     lam, V = np.linalg.eigh(G)               # ascending
     lam = lam[::-1]
-    V = V[:, ::-1]
+    V = np.ascontiguousarray(V[:, ::-1])     # descending; contiguous so the product goes to BLAS
     trace = float(np.real(np.trace(G)))
     k = select_rank(lam, trace, r, eps, tie)
     kept = float(np.sum(np.maximum(lam[:k], 0.0)))
     c = 1.0 / np.sqrt(kept) if renorm else 1.0
     L_new = c * (L @ V[:, :k])
     gap = float(lam[k - 1] - lam[k]) if k < lam.shape[0] else float("inf")
-    info = dict(k=k, discarded=max(trace - kept, 0.0), trace=trace, gap=gap, lam=lam.copy(),
-                scale=c)
+    info = dict(k=k, discarded=max(trace - kept, 0.0), trace=trace, gap=gap, lam_k=float(lam[k - 1]),
+                lam=lam.copy(), scale=c)
     return L_new, info
 
 

@@ -37,15 +37,25 @@ def lr():
     return lr
 
 
-def _oracle(prog):
-    """The oracle's steps, keeping each compression's rank and whether it sits on the threshold."""
+def _oracle(prog, perturb=0.0, pseed=0, stop=None):
+    """The oracle's steps, keeping each compression's rank and whether it sits on the threshold.
+    perturb > 0 adds a seeded relative perturbation of that size to every entry of the factor
+    before each compression (rounding-sized noise: how far it moves the result measures the
+    program's conditioning at that precision); stop = s returns the factor just before the
+    s-th compression's channel instead (with the channel op)."""
     L = OL.init_state(prog.n)
     ranks, borderline, layers = [], [], []
+    rng = np.random.default_rng(pseed)
     for op in prog.ops:
         if isinstance(op, C.Gate):
             L = OL.apply_gate(L, prog.n, op.qubits, op.u)
         elif isinstance(op, C.Kraus):
+            if stop is not None and len(ranks) == stop:
+                return L, op
             L = OL.kraus_expand(L, prog.n, op.qubit, op.ops)
+            if perturb > 0:
+                g = rng.standard_normal(L.shape) + 1j * rng.standard_normal(L.shape)
+                L = L + perturb * np.abs(L) * g / np.sqrt(2.0)
         elif isinstance(op, C.Compress):
             L, info = OL.compress(L, op.r, op.eps, op.tie, op.renorm)
             lam, tr = info["lam"], info["trace"]
@@ -206,49 +216,93 @@ def _sweep_program(seed):
     return prog
 
 
-# programs whose result is too ill-conditioned for the 1e-10 bar (reason given)
-_SWEEP_OPEN = {
-    53: "ill-conditioned as posed: its fixed-rank cuts at compressions 11, 13, 15 and 17 each "
-        "separate two eigenvalues near 0.013 only 3.5e-6 to 1.4e-5 apart, and every such cut "
-        "multiplies a perturbation of rho by about lambda / gap; rounding differences reach 8e-9 "
-        "in the coherences before the 18th compression (the diagonals still agree to 2e-15), "
-        "while the device compresses that input exactly (checked against the oracle to 6e-17)",
-}
+# rounding-sized relative perturbation of the factor for the conditioning check: FP64 rounding
+# of the complex128 factor and of its FP64 Gram matrix over up to 2^8 rows
+_ETA = {"c128": 1e-15, "c64": 1e-7}
+_BAR = {"c128": 1e-10, "c64": 1e-5}
+
+
+def _conditioning(prog, P_ref):
+    """How far rounding-sized noise moves the oracle's probabilities: the largest change over two
+    seeded perturbed runs (relative size _ETA before every compression)."""
+    spread = 0.0
+    for ps in (1, 2):
+        P_pert, _, _, _ = _oracle(prog, perturb=_ETA[prog.dtype], pseed=ps)
+        spread = max(spread, float(np.max(np.abs(P_pert - P_ref))))
+    return spread
+
+
+def _check_sweep_program(lr, seed):
+    """One sweep program against the oracle.  Returns (status, err) with status 'ok', 'threshold'
+    (a cut on the eps threshold: compared up to that cut) or 'ill' (rounding-sized noise moves the
+    oracle's own result by more than a quarter of the bar: compared against that envelope)."""
+    prog = _sweep_program(seed)
+    _say(f"sweep seed {seed}: n={prog.n} r={prog.r} {prog.meta} {prog.dtype}")
+    P_ref, k_ref, near, _ = _oracle(prog)
+    P, k = _gpu(lr, prog, lr.C128 if prog.dtype == "c128" else lr.C64)
+    assert len(k) == len(k_ref)
+    if any(near):
+        # after a cut on the threshold both sides hold valid but different states; every sweep
+        # program uses the tie rule, which drops zero-eigenvalue columns on both sides (the
+        # spectrum continues with zeros beyond the Gram order), so ranks up to there are unique
+        first = near.index(True)
+        assert k[:first] == k_ref[:first], (seed, k, k_ref)
+        return "threshold", 0.0
+    assert k == k_ref, (seed, k, k_ref)
+    err = float(np.max(np.abs(P - P_ref)))
+    _say(f"  max|dP| {err:.2e}")
+    if err <= _BAR[prog.dtype]:
+        return "ok", err
+    spread = _conditioning(prog, P_ref)
+    _say(f"  rounding-sized noise moves the oracle's Prob by {spread:.2e}")
+    assert spread > _BAR[prog.dtype] / 4, (seed, err, spread)   # a miss on a well-conditioned program fails
+    assert err <= 4 * spread, (seed, err, spread)
+    return "ill", err
 
 
 @pytest.mark.parametrize("block", range(4))
 def test_random_program_sweep(lr, block):
     """Sixty seeded random programs against the oracle: the probabilities within 1e-5
     (complex64) or 1e-10 (complex128) and, where the threshold rule decides (eps > 0), every rank
-    equal; a program with a cut on the threshold is compared up to that cut only."""
+    equal; a program with a cut on the threshold is compared up to that cut only.  A program
+    that misses the bar must be ill-conditioned at the bulk precision (rounding-sized noise
+    moves the oracle's own probabilities by more than a quarter of the bar), and then its
+    result must lie within four times that spread; at most two programs per block may take
+    either exception."""
     worst = {"c64": 0.0, "c128": 0.0}
-    skipped = 0
-    failures = []
+    special = []
     for seed in range(15 * block, 15 * block + 15):
-        if seed in _SWEEP_OPEN:
-            _say(f"sweep seed {seed}: skipped, {_SWEEP_OPEN[seed]}")
-            continue
-        prog = _sweep_program(seed)
-        _say(f"sweep seed {seed}: n={prog.n} r={prog.r} {prog.meta} {prog.dtype}")
-        P_ref, k_ref, near, _ = _oracle(prog)
-        P, k = _gpu(lr, prog, lr.C128 if prog.dtype == "c128" else lr.C64)
-        assert len(k) == len(k_ref)
-        # every sweep program uses the tie rule, which drops zero-eigenvalue columns on both
-        # sides (the spectrum continues with zeros beyond the Gram order), so ranks are unique
-        check_k = True
-        if any(near):
-            # after a cut on the threshold both sides hold valid but different states
-            first = near.index(True)
-            assert not check_k or k[:first] == k_ref[:first], (seed, k, k_ref)
-            skipped += 1
-            continue
-        err = float(np.max(np.abs(P - P_ref)))
-        worst[prog.dtype] = max(worst[prog.dtype], err)
-        assert not check_k or k == k_ref, (seed, k, k_ref)
-        _say(f"  max|dP| {err:.2e}")
-        if err > 1e-10:
-            failures.append((seed, err))
-    assert not failures, failures
+        status, err = _check_sweep_program(lr, seed)
+        dt = _sweep_program(seed).dtype
+        if status == "ok":
+            worst[dt] = max(worst[dt], err)
+        else:
+            special.append((seed, status))
     _say(f"  block {block}: worst |dP| complex64 {worst['c64']:.2e}, complex128 {worst['c128']:.2e}, "
-         f"{skipped} program(s) with a cut on the threshold")
-    assert skipped <= 2
+         f"other cases {special}")
+    assert len(special) <= 2
+
+
+def test_sweep_program_53_ill_conditioned(lr):
+    """Sweep program 53 (n = 6, complex128) misses the 1e-10 bar: its fixed-rank cuts at
+    compressions 11, 13, 15 and 17 each separate two eigenvalues near 0.013 only 3.5e-6 to 1.4e-5
+    apart, so each cut turns a perturbation of rho by about lambda / gap.  Checked here: the
+    oracle itself is that sensitive (rounding-sized noise moves its probabilities by more than a
+    quarter of the bar), the device result lies inside that envelope, and the device compresses
+    the oracle's own input to the 18th compression exactly (complex128, 1e-13 on rho)."""
+    status, err = _check_sweep_program(lr, 53)
+    assert status == "ill", status
+    prog = _sweep_program(53)
+    L_in, chan = _oracle(prog, stop=17)
+    comp = [op for op in prog.ops if isinstance(op, C.Compress)][17]
+    ref, _ = OL.compress(OL.kraus_expand(L_in, prog.n, chan.qubit, chan.ops), comp.r, comp.eps, comp.tie, comp.renorm)
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C128, prog.m_max)
+    dm.set_L(L_in)
+    dm.apply_kraus(chan.qubit, chan.ops)
+    dm.compress(comp.r, comp.eps, comp.tie, comp.renorm)
+    L = dm.get_L()
+    rho, rho_ref = L @ L.conj().T, ref @ ref.conj().T
+    d = float(np.max(np.abs(rho - rho_ref)))
+    _say(f"  single compression of the oracle's input: max|d rho| {d:.2e}")
+    assert d <= 1e-13
+    dm.close()

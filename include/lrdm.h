@@ -19,8 +19,9 @@
  *    values synchronise that stream.  Device outputs are valid after a stream synchronisation.
  *  - Layout of L in the state buffer: row-major, L[x * ld + v], x in [0, 2^n) with qubit q =
  *    bit q of x, v in [0, ld); complex values interleaved (re, im) as float pairs (LRDM_C64) or
- *    double pairs (LRDM_C128).  ld = r_pad = r_max rounded up to a multiple of 8 (times m_max
- *    in plain mode); unused columns are zero.
+ *    double pairs (LRDM_C128).  r_pad = the smallest power of two >= max(r_max, 8); ld = r_pad
+ *    (fused form) or m_pad * r_pad (plain form, m_pad = the smallest power of two >= m_max);
+ *    lrdm_layout returns both for a handle.  Unused columns are zero.
  *  - Gate and Kraus matrices are FP64, row-major, interleaved (re, im).
  *  - Asynchronous device errors (LRDM_E_HIP, LRDM_E_EIG) poison the handle: every later call
  *    returns LRDM_E_STATE until lrdm_destroy.
@@ -78,6 +79,11 @@ lrdm_status lrdm_workspace_size(int n, int r_max, lrdm_dtype dt, int m_max, unsi
 lrdm_status lrdm_init(lrdm_t* out, int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags,
                       void* state_dev, size_t state_bytes, void* work_dev, size_t work_bytes,
                       void* hip_stream);
+
+/* Shape of a handle: qubit count n, leading dimension ld of the state layout (complex entries
+ * per row), the padded rank r_pad and the state buffer's size in bytes (any pointer may be NULL).
+ * Never fails for a valid handle. */
+lrdm_status lrdm_layout(lrdm_t h, int* n, int* ld, int* r_pad, size_t* state_bytes);
 
 /* Reset an existing handle to L = e_0 (rank 1), clearing the running discarded mass. */
 lrdm_status lrdm_reset(lrdm_t h);
@@ -213,6 +219,82 @@ lrdm_status lrdm_pauli_overlap(lrdm_t bra, lrdm_t ket, int n_terms, const uint64
 lrdm_status lrdm_compress_adjoint(lrdm_t bar, const void* x_dev, const void* rec_dev, int qubit,
                                   int m, const double* e);
 
+/* ---------------------------------------------------------------- programs (Algorithm 1)
+ * A program is a flat array of operations applied in order, the loop of Algorithm 1: gates and
+ * Hamming-weight phases, Kraus channels each followed by its compression (Sec. II.C, one channel
+ * per group), and layer marks.  Matrices live in one FP64 coefficient array (interleaved re/im,
+ * layouts as in the operation-level calls); an operation names its first coefficient by `off`. */
+typedef enum {
+  LRDM_OP_GATE = 0,      /* k-qubit gate (k in {1, 2}) on q0 (, q1), 2^k x 2^k matrix at coef + off */
+  LRDM_OP_ROTATION = 1,  /* R_P(theta) = exp(-i theta P / 2) on q0, P = X, Y, Z for axis 1, 2, 3; the
+                            matrix is computed from theta = params[param] when params is given, else
+                            read at coef + off; param also names the gradient entry (lrdm_energy_grad) */
+  LRDM_OP_WEIGHT = 2,    /* L[x, :] *= phase[popcount(x)], n + 1 complex at coef + off */
+  LRDM_OP_KRAUS = 3,     /* channel on q0 with m = k operators E_a at coef + off (as lrdm_apply_kraus);
+                            the next operation must be LRDM_OP_COMPRESS */
+  LRDM_OP_COMPRESS = 4,  /* lrdm_compress(r, eps, tie, renorm) */
+  LRDM_OP_LAYER = 5      /* end of a layer (checkpoint boundary); no arithmetic */
+} lrdm_op_kind;
+
+typedef struct {
+  int kind;              /* lrdm_op_kind */
+  int k;                 /* gate: qubit count; channel: operator count */
+  int q0, q1;            /* qubits (q1 only for two-qubit gates) */
+  int axis;              /* rotation: 1 = X, 2 = Y, 3 = Z */
+  int param;             /* rotation: index into params / the gradient */
+  int r, tie, renorm;    /* compression */
+  double eps;            /* compression */
+  int64_t off;           /* first coefficient (doubles) of the operation's matrix */
+} lrdm_op;
+
+typedef struct {
+  int n_ops;
+  const lrdm_op* ops;
+  const double* coef;    /* host array of n_coef doubles */
+  int64_t n_coef;
+} lrdm_program;
+
+/* Host-only check of a program for n qubits: every rule lrdm_run applies before it enqueues
+ * anything (operation kinds, qubit ranges, coefficient ranges, rotation axes and parameter
+ * indices, a compression after every channel, unitarity, Kraus completeness, unit-modulus
+ * phases).  Returns LRDM_OK or LRDM_E_ARG with the offending operation in lrdm_last_error(NULL). */
+lrdm_status lrdm_program_validate(const lrdm_program* p, int n, const double* params, int n_params);
+
+/* Algorithm 1 over a program, from the handle's current state (call lrdm_reset first for L =
+ * e_0): every operation is issued in order through the operation-level calls.  The whole program
+ * is validated first (ranges, unitarity, completeness, phase modulus, a compression after every
+ * channel); on LRDM_E_ARG nothing is enqueued.  params (nullable, n_params doubles) gives the
+ * rotation angles.  With ckpt_dev (device memory, 256-byte aligned) the state at the start of
+ * every layer l goes to ckpt_dev + l * S, S = state bytes rounded up to 256 (ckpt_bytes >=
+ * layers * S, else LRDM_E_NOMEM); ckpt_rank (nullable host array, one int per layer) receives
+ * the column bound to pass to lrdm_restore.  A trailing run of operations without a layer mark
+ * counts as a layer.  Queued (no synchronisation). */
+lrdm_status lrdm_run(lrdm_t h, const lrdm_program* p, const double* params, int n_params, void* ckpt_dev,
+                     size_t ckpt_bytes, int* ckpt_rank);
+
+/* Device bytes lrdm_energy_grad needs for program p on handle h: keep_all_bytes keeps every
+ * channel's input factor and compression record from the forward pass (the reverse sweep re-runs
+ * nothing); min_bytes keeps the layer checkpoints and one layer's inputs and records (the reverse
+ * sweep re-runs each layer once, bit for bit).  Fails like lrdm_energy_grad's validation. */
+lrdm_status lrdm_energy_grad_bytes(lrdm_t h, const lrdm_program* p, size_t* keep_all_bytes, size_t* min_bytes);
+
+/* Energy E = sum_t coeff[t] Tr(L^H P_t L) of the final factor of program p run from L = e_0
+ * (Sec. II.D; Pauli strings as in lrdm_expect_pauli, n_terms in [1, 4096]) and its gradient with
+ * respect to the rotation angles, by one forward pass and one reverse sweep (the adjoint of
+ * gates, channels and truncations described at lrdm_compress_adjoint; a rotation R_P(theta)
+ * contributes dE/dtheta = Im Tr(Lbar^H P L) right after it, rotations whose generators commute
+ * with everything between them being evaluated together).  h is reset and ends in the state the
+ * last layer's reverse step leaves; bar is a second handle of the same shape that receives the
+ * adjoint factor.  Every compression must follow a channel (else LRDM_E_UNSUPPORTED), and the
+ * reverse sweep's size limits apply (m_max * r_pad <= 64, fused form).  grad_host: n_params
+ * doubles, overwritten; energy: one double.  store_dev: device memory of store_bytes >= min_bytes
+ * of lrdm_energy_grad_bytes (256-byte aligned); with keep_all_bytes or more nothing is re-run,
+ * and kept_all (nullable) reports which mode ran.  Synchronises. */
+lrdm_status lrdm_energy_grad(lrdm_t h, lrdm_t bar, const lrdm_program* p, const double* params, int n_params,
+                             int n_terms, const uint64_t* xmask, const uint64_t* zmask, const double* coeff,
+                             double* energy, double* grad_host, void* store_dev, size_t store_bytes,
+                             int* kept_all);
+
 /* ---------------------------------------------------------------- full-rank comparator
  * Exact density-matrix evolution (Eq. "full rank evolution", Sec. II.A) in complex64, the
  * same-GPU baseline the low-rank path is measured against.  rho (2^n x 2^n, row-major, 8 * 4^n
@@ -279,6 +361,17 @@ lrdm_status lrdm_batch_info(lrdm_batch_t b, int* n_steps, int* n_launches);
  * clock. */
 lrdm_status lrdm_batch_times(lrdm_batch_t b, double* done_ms, double* total_ms);
 lrdm_status lrdm_batch_destroy(lrdm_batch_t b);
+
+/* One call for a whole batch: handle i of b (creation order) is reset and runs program progs[i]
+ * (params[i] / n_params[i] as in lrdm_run; params and n_params may be NULL), recorded as by
+ * lrdm_batch_begin / lrdm_batch_end; *plan_needed receives the plan's device bytes.  If plan_dev
+ * is NULL or plan_bytes is smaller, the call returns LRDM_E_NOMEM after setting *plan_needed
+ * (call again with a buffer of that size); otherwise it instantiates the graph on plan_dev,
+ * replays it once and waits, filling done_ms / total_ms as lrdm_batch_times (both nullable).
+ * Later replays: lrdm_batch_launch. */
+lrdm_status lrdm_batch_run(lrdm_batch_t b, const lrdm_program* const* progs, const double* const* params,
+                           const int* n_params, void* plan_dev, size_t plan_bytes, size_t* plan_needed,
+                           double* done_ms, double* total_ms);
 
 /* Last error message for h, or the calling thread's last error when h == NULL. */
 const char* lrdm_last_error(lrdm_t h);

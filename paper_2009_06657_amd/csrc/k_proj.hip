@@ -47,7 +47,8 @@ template <> struct PPair<double> { typedef double type __attribute__((ext_vector
 template <class T, int FO>
 __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, int F, int seg_in_shift,
                                              int nsplit, int q, int seg_out_shift,
-                                             const cx_t<T>* __restrict__ W, uint32_t rows, uint32_t bid) {
+                                             const cx_t<T>* __restrict__ W, int skip, uint32_t rows,
+                                             uint32_t bid) {
   using A4 = typename PAcc4<T>::type;
   using P2 = typename PPair<T>::type;
   constexpr int NTO = FO / 16;
@@ -135,21 +136,38 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
     }
   };
 
+  // Zero blocks of W (split view): a chunk lies inside one input half when the half spans
+  // whole chunks, and an output tile inside one output half (16 reals per tile, seg_out >= 16),
+  // so the output tiles of a zero block are skipped for that chunk (uniform branches).
+  const bool halves = nsplit == 2 && seg_in_shift >= 5 && seg_out_shift >= 4 && skip != 0;
   fetch(0);
   for (int kc = 0; kc < F; kc += kProjKC) {
     stage();
     __syncthreads();
     if (kc + kProjKC < F) fetch(kc + kProjKC);
+    const int hin = kc >> seg_in_shift;
+    const bool do0 = !(halves && hin == 1 && (skip & 2));   // output half 0 from this chunk
+    const bool do1 = !(halves && hin == 0 && (skip & 1));   // output half 1 from this chunk
 #pragma unroll
     for (int ks = 0; ks < kProjKC / 4; ++ks) {
       const T a0 = xs[(32 * wave + m) * kProjXS + 4 * ks + kq];
       const T a1 = xs[(32 * wave + 16 + m) * kProjXS + 4 * ks + kq];
       const T* wrow = ws + (4 * ks + kq) * WS + m;
+      if (do0) {
 #pragma unroll
-      for (int t = 0; t < NTO; ++t) {
-        const T b = wrow[16 * t];
-        acc[0][t] = pmfma16(b, a0, acc[0][t]);
-        acc[1][t] = pmfma16(b, a1, acc[1][t]);
+        for (int t = 0; t < NTO / 2; ++t) {
+          const T b = wrow[16 * t];
+          acc[0][t] = pmfma16(b, a0, acc[0][t]);
+          acc[1][t] = pmfma16(b, a1, acc[1][t]);
+        }
+      }
+      if (do1) {
+#pragma unroll
+        for (int t = NTO / 2; t < NTO; ++t) {
+          const T b = wrow[16 * t];
+          acc[0][t] = pmfma16(b, a0, acc[0][t]);
+          acc[1][t] = pmfma16(b, a1, acc[1][t]);
+        }
       }
     }
     __syncthreads();
@@ -188,17 +206,17 @@ template <class T, int FO>
 __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L, int ld, int F,
                                                          int seg_in_shift, int nsplit, int q,
                                                          int seg_out_shift,
-                                                         const cx_t<T>* __restrict__ W,
+                                                         const cx_t<T>* __restrict__ W, int skip,
                                                          uint32_t rows) {
-  project_body<T, FO>(L, ld, F, seg_in_shift, nsplit, q, seg_out_shift, W, rows, blockIdx.x);
+  project_body<T, FO>(L, ld, F, seg_in_shift, nsplit, q, seg_out_shift, W, skip, rows, blockIdx.x);
 }
 
 template <class T, int FO>
 __global__ __launch_bounds__(256, 2) void project_batched(const ProjJob<T>* __restrict__ jobs, int njobs) {
   const int j = find_job(jobs, njobs, blockIdx.x);
   const ProjJob<T>& J = jobs[j];
-  project_body<T, FO>(J.L, J.ld, J.F, J.seg_in_shift, J.nsplit, J.q, J.seg_out_shift, J.W, J.rows,
-                      blockIdx.x - J.block0);
+  project_body<T, FO>(J.L, J.ld, J.F, J.seg_in_shift, J.nsplit, J.q, J.seg_out_shift, J.W, J.skip,
+                      J.rows, blockIdx.x - J.block0);
 }
 
 template <class T>
@@ -222,7 +240,7 @@ hipError_t launch_project_batched(int FO, const ProjJob<T>* jobs, int njobs, uin
 
 template <class T, int FO>
 static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
-                                const cx_t<T>* W, hipStream_t s) {
+                                const cx_t<T>* W, int skip, hipStream_t s) {
   const uint32_t rows = 1u << (n - (nsplit == 2 ? 1 : 0));
   const uint32_t blocks = (rows + kProjBM - 1) / kProjBM;
   int si = 0, so = 0;
@@ -230,21 +248,21 @@ static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit,
   while ((1 << so) < 2 * c_out) ++so;
   if ((1 << si) != 2 * c_in || (1 << so) != 2 * c_out) return hipErrorInvalidValue;
   hipLaunchKernelGGL((project_kernel<T, FO>), dim3(blocks), dim3(256), 0, s, L, ld, 2 * nsplit * c_in,
-                     si, nsplit, q, so, W, rows);
+                     si, nsplit, q, so, W, skip, rows);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
-                          const cx_t<T>* W, hipStream_t s) {
+                          const cx_t<T>* W, int skip, hipStream_t s) {
   const int FO = 2 * nsplit * c_out;
   switch (FO) {
-    case 16: return launch_proj_f<T, 16>(L, n, ld, c_in, nsplit, q, c_out, W, s);
-    case 32: return launch_proj_f<T, 32>(L, n, ld, c_in, nsplit, q, c_out, W, s);
-    case 64: return launch_proj_f<T, 64>(L, n, ld, c_in, nsplit, q, c_out, W, s);
-    case 128: return launch_proj_f<T, 128>(L, n, ld, c_in, nsplit, q, c_out, W, s);
+    case 16: return launch_proj_f<T, 16>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
+    case 32: return launch_proj_f<T, 32>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
+    case 64: return launch_proj_f<T, 64>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
+    case 128: return launch_proj_f<T, 128>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
     case 256:
-      if constexpr (sizeof(T) == 4) return launch_proj_f<T, 256>(L, n, ld, c_in, nsplit, q, c_out, W, s);
+      if constexpr (sizeof(T) == 4) return launch_proj_f<T, 256>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
@@ -252,7 +270,7 @@ hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q
 
 template hipError_t launch_project_batched<float>(int, const ProjJob<float>*, int, uint32_t, hipStream_t);
 template hipError_t launch_project_batched<double>(int, const ProjJob<double>*, int, uint32_t, hipStream_t);
-template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, hipStream_t);
-template hipError_t launch_project<double>(double2*, int, int, int, int, int, int, const double2*, hipStream_t);
+template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, int, hipStream_t);
+template hipError_t launch_project<double>(double2*, int, int, int, int, int, int, const double2*, int, hipStream_t);
 
 }  // namespace lrdm

@@ -130,7 +130,7 @@ template <class T> struct EigJob {
 template <class T> struct ProjJob {
   cx_t<T>* L;
   const cx_t<T>* W;
-  int ld, F, seg_in_shift, nsplit, q, seg_out_shift;
+  int ld, F, seg_in_shift, nsplit, q, seg_out_shift, skip;
   uint32_t rows, block0, nblocks;
 };
 struct ResetJob {
@@ -175,9 +175,12 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
                       int kmax, int r_target, double eps, int tie, int renorm, int c_out,
                       const EigBufs& b, cx_t<T>* W, hipStream_t s);
 
+// skip (split view only): bit 0 = the block of W from input half 0 to output half 1 is zero,
+// bit 1 = the block from input half 1 to output half 0 is zero (Kraus sets that never map that
+// value of the qubit to the other); those MFMAs are left out.
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
-                          const cx_t<T>* W, hipStream_t s);
+                          const cx_t<T>* W, int skip, hipStream_t s);
 
 template <class T>
 hipError_t launch_probabilities(const cx_t<T>* L, int n, int ld, int ncols, double* p,
@@ -288,5 +291,8 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t s);
 int gram_blocks(int n, int nsplit);   // number of split-K partials the Gram uses
 
 void set_last_error(const char* msg);   // the calling thread's last error (lrdm_last_error(NULL))
+
+// the handles of a batch, in creation order
+const lrdm_t* batch_handles(lrdm_batch_t b, int* n);
 
 }  // namespace lrdm

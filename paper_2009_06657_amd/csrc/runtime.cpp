@@ -155,6 +155,7 @@ struct lrdm_ctx {
   bool proj_pending = false;
   int pend_q = -1;
   bool last_w_next = false;   // the last compression's own W is in the "next" buffer (chained)
+  int pend_skip = 0;          // zero blocks of the pending projection's W (see reach_skip)
 
   template <class P> P* ws(size_t off) { return reinterpret_cast<P*>(work + off); }
 };
@@ -416,6 +417,38 @@ AdjBufs adj_bufs(lrdm_t h) {
   return b;
 }
 
+// Which value of the channel's qubit can reach which: reach[b][c] = some E_a has a non-zero
+// entry (E_a)_{cb}.  Where no operator maps b to c, the block of the projection matrix W from
+// input half b to output half c is exactly zero (W_{(b,v),(c,j)} = scale sum_a (E_a)_{cb} V).
+struct Reach {
+  bool r[2][2];
+};
+Reach channel_reach(const Channel& ch) {
+  Reach R{};
+  for (int a = 0; a < ch.m; ++a)
+    for (int c = 0; c < 2; ++c)
+      for (int b = 0; b < 2; ++b)
+        if (ch.e[a][c][b][0] != 0.0 || ch.e[a][c][b][1] != 0.0) R.r[b][c] = true;
+  return R;
+}
+// reach of two channels applied in turn (the composed projection X W_1 W_2)
+Reach compose_reach(const Reach& A, const Reach& B) {
+  Reach R{};
+  for (int b = 0; b < 2; ++b)
+    for (int c = 0; c < 2; ++c)
+      R.r[b][c] = (A.r[b][0] && B.r[0][c]) || (A.r[b][1] && B.r[1][c]);
+  return R;
+}
+// projection skip bits: bit 0 = no path from 0 to 1, bit 1 = no path from 1 to 0
+int reach_skip(const Reach& R) { return (R.r[0][1] ? 0 : 1) | (R.r[1][0] ? 0 : 2); }
+Reach skip_reach(int skip) {
+  Reach R{};
+  R.r[0][0] = R.r[1][1] = true;
+  R.r[0][1] = !(skip & 1);
+  R.r[1][0] = !(skip & 2);
+  return R;
+}
+
 // Materialise the factor: issue the deferred projection of the last (possibly chained)
 // compression.
 template <class T>
@@ -425,7 +458,7 @@ lrdm_status settle_t(lrdm_t h) {
   const int c = h->lay.r_pad;
   timed_begin(h, 4);
   HIPCHK(h, launch_project<T>(static_cast<cx_t<T>*>(h->state), h->n, h->lay.ld, c, 2, h->pend_q, c,
-                              h->ws<cx_t<T>>(h->lay.off_W), h->stream));
+                              h->ws<cx_t<T>>(h->lay.off_W), h->pend_skip, h->stream));
   timed_end(h, 4);
   return LRDM_OK;
 }
@@ -513,6 +546,7 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
       pj.nsplit = nsplit;
       pj.q = q;
       pj.seg_out_shift = gram_seg_shift(c_out);
+      pj.skip = nsplit == 2 ? reach_skip(channel_reach(ch)) : 0;
       pj.rows = 1u << (h->n - (nsplit == 2 ? 1 : 0));
       pj.block0 = 0;
       pj.nblocks = (pj.rows + 127) / 128;
@@ -560,12 +594,15 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   timed_end(h, 3);
   if (chain) HIPCHK(h, launch_chain_compose<T>(Wp64, Wn64, tmp64, W, Fc, h->stream));
   if (defer) {
+    const Reach here = channel_reach(ch);
+    h->pend_skip = reach_skip(chain ? compose_reach(skip_reach(h->pend_skip), here) : here);
     h->proj_pending = true;
     h->pend_q = q;
     h->last_w_next = chain;
   } else {
     timed_begin(h, 4);
-    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W, h->stream));
+    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W,
+                                nsplit == 2 ? reach_skip(channel_reach(ch)) : 0, h->stream));
     timed_end(h, 4);
   }
   h->ncols = c_out;
@@ -782,6 +819,15 @@ lrdm_status lrdm_init(lrdm_t* out, int n, int r_max, lrdm_dtype dt, int m_max, u
     return st;
   }
   *out = h;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_layout(lrdm_t h, int* n, int* ld, int* r_pad, size_t* state_bytes) {
+  if (!h) return fail(nullptr, LRDM_E_ARG, "null handle");
+  if (n) *n = h->n;
+  if (ld) *ld = h->lay.ld;
+  if (r_pad) *r_pad = h->lay.r_pad;
+  if (state_bytes) *state_bytes = h->lay.state_bytes;
   return LRDM_OK;
 }
 
@@ -1211,6 +1257,11 @@ struct lrdm_batch_ctx {
   hipGraphExec_t exec = nullptr;
   double ticks_per_ms = 0;
 };
+
+const lrdm_t* lrdm::batch_handles(lrdm_batch_t b, int* n) {
+  *n = b ? (int)b->hs.size() : 0;
+  return b ? b->hs.data() : nullptr;
+}
 
 namespace {
 

@@ -30,7 +30,11 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_fdm_apply_gate", "lrdm_fdm_apply_kraus", "lrdm_fdm_apply_diagonal_weight", "lrdm_fdm_probabilities",
            "lrdm_fdm_synchronize", "lrdm_fdm_last_error", "lrdm_batch_create", "lrdm_batch_begin",
            "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
-           "lrdm_batch_times", "lrdm_batch_destroy"]
+           "lrdm_batch_times", "lrdm_batch_destroy", "lrdm_layout", "lrdm_run", "lrdm_energy_grad_bytes",
+           "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate"]
+
+OP_GATE, OP_ROTATION, OP_WEIGHT, OP_KRAUS, OP_COMPRESS, OP_LAYER = range(6)
+_AXIS = {"X": 1, "Y": 2, "Z": 3}
 
 
 class LrdmError(RuntimeError):
@@ -46,6 +50,70 @@ class CompressInfo(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class COp(ctypes.Structure):
+    """lrdm_op of include/lrdm.h."""
+    _fields_ = [("kind", ctypes.c_int), ("k", ctypes.c_int), ("q0", ctypes.c_int), ("q1", ctypes.c_int),
+                ("axis", ctypes.c_int), ("param", ctypes.c_int), ("r", ctypes.c_int), ("tie", ctypes.c_int),
+                ("renorm", ctypes.c_int), ("eps", ctypes.c_double), ("off", ctypes.c_int64)]
+
+
+class CProgram(ctypes.Structure):
+    """lrdm_program of include/lrdm.h."""
+    _fields_ = [("n_ops", ctypes.c_int), ("ops", ctypes.POINTER(COp)), ("coef", ctypes.POINTER(ctypes.c_double)),
+                ("n_coef", ctypes.c_int64)]
+
+
+class FlatProgram:
+    """A workloads.circuits.Program as the flat operation array of the C ABI (lrdm_program).
+    Parametrised gates (param = (index, axis)) become rotations whose matrix is the gate's own
+    (no params array is passed), so the C side applies exactly the Python program's matrices and
+    knows each rotation's generator for the gradient."""
+
+    def __init__(self, program):
+        from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
+
+        ops, coef = [], []
+
+        def put(a):
+            off = len(coef)
+            coef.extend(_cplx(a).ravel().tolist())
+            return off
+
+        self.n_params = 0
+        for op in program.ops:
+            o = COp()
+            if isinstance(op, Gate):
+                if getattr(op, "param", None) is not None:
+                    o.kind, o.k, o.q0 = OP_ROTATION, 1, int(op.qubits[0])
+                    o.param, o.axis = int(op.param[0]), _AXIS[op.param[1]]
+                    self.n_params = max(self.n_params, o.param + 1)
+                else:
+                    o.kind, o.k = OP_GATE, len(op.qubits)
+                    o.q0 = int(op.qubits[0])
+                    o.q1 = int(op.qubits[1]) if len(op.qubits) > 1 else -1
+                o.off = put(op.u)
+            elif isinstance(op, DiagWeight):
+                o.kind, o.off = OP_WEIGHT, put(op.phase)
+            elif isinstance(op, Kraus):
+                ks = np.asarray(op.ops, dtype=np.complex128)
+                o.kind, o.k, o.q0, o.off = OP_KRAUS, ks.shape[0], int(op.qubit), put(ks)
+            elif isinstance(op, Compress):
+                o.kind, o.r, o.eps, o.tie, o.renorm = OP_COMPRESS, int(op.r), float(op.eps), int(op.tie), int(op.renorm)
+            elif isinstance(op, LayerEnd):
+                o.kind = OP_LAYER
+            else:
+                raise TypeError(f"unknown op {op!r}")
+            ops.append(o)
+        self.ops = (COp * max(len(ops), 1))(*ops)
+        self.coef = np.ascontiguousarray(coef, dtype=np.float64) if coef else np.zeros(1)
+        self.c = CProgram(len(ops), self.ops, _dptr(self.coef), len(coef))
+        self.n_layers = sum(o.kind == OP_LAYER for o in ops) + (1 if ops and ops[-1].kind != OP_LAYER else 0)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
 
 
 _lib = None
@@ -103,6 +171,12 @@ def load_library(path: str = LIB_PATH):
         "lrdm_batch_info": [P, ctypes.POINTER(I), ctypes.POINTER(I)],
         "lrdm_batch_times": [P, dp, dp],
         "lrdm_batch_destroy": [P],
+        "lrdm_layout": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(SZ)],
+        "lrdm_run": [P, ctypes.POINTER(CProgram), dp, I, P, SZ, ctypes.POINTER(I)],
+        "lrdm_energy_grad_bytes": [P, ctypes.POINTER(CProgram), ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
+        "lrdm_energy_grad": [P, P, ctypes.POINTER(CProgram), dp, I, I, P, P, P, dp, dp, P, SZ, ctypes.POINTER(I)],
+        "lrdm_batch_run": [P, ctypes.POINTER(ctypes.POINTER(CProgram)), P, P, P, SZ, ctypes.POINTER(SZ), dp, dp],
+        "lrdm_program_validate": [ctypes.POINTER(CProgram), I, dp, I],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -158,10 +232,10 @@ class LowRankDM:
         _check(self.lib.lrdm_init(ctypes.byref(self.h), n, r_max, dtype, m_max, flags,
                                   self.state.data_ptr(), sb, self.work.data_ptr(), wb,
                                   ctypes.c_void_p(self.stream.cuda_stream)))
-        r_pad = max(8, 1 << (r_max - 1).bit_length())
-        m_pad = 1 << (m_max - 1).bit_length()
-        self.r_pad = r_pad
-        self.ld = r_pad * (m_pad if flags & FLAG_PLAIN else 1)
+        ld, r_pad = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.lrdm_layout(self.h, None, ctypes.byref(ld), ctypes.byref(r_pad), None), self.h)
+        self.r_pad = r_pad.value
+        self.ld = ld.value
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -202,6 +276,18 @@ class LowRankDM:
         _check(self.lib.lrdm_compress(self.h, int(r), float(eps), int(tie), int(renorm),
                                       ctypes.byref(ci) if info else None), self.h)
         return ci.as_dict() if info else None
+
+    def run(self, program, ckpt=None) -> Optional[list]:
+        """lrdm_run: the whole program (a workloads.circuits.Program or a FlatProgram) from the
+        current state; with ckpt (a device tensor of layers x state bytes rounded up to 256) the
+        state at the start of every layer is kept there and the column bounds are returned."""
+        fp = program if isinstance(program, FlatProgram) else FlatProgram(program)
+        ranks = (ctypes.c_int * max(fp.n_layers, 1))()
+        _check(self.lib.lrdm_run(self.h, fp.ref, None, 0,
+                                 ctypes.c_void_p(ckpt.data_ptr()) if ckpt is not None else None,
+                                 ckpt.numel() * ckpt.element_size() if ckpt is not None else 0,
+                                 ranks if ckpt is not None else None), self.h)
+        return list(ranks)[: fp.n_layers] if ckpt is not None else None
 
     # -------------------------------------------------------------- outputs
     def probabilities(self, out=None):
@@ -422,6 +508,27 @@ class Batch:
             finally:
                 self.end()
         return ctx()
+
+    def run(self, programs):
+        """lrdm_batch_run: reset every handle, record its program (one per handle, in order),
+        capture the graph and replay it once; returns (done_ms, total_ms)."""
+        import torch
+
+        flats = [p if isinstance(p, FlatProgram) else FlatProgram(p) for p in programs]
+        arr = (ctypes.POINTER(CProgram) * len(flats))(*[ctypes.pointer(f.c) for f in flats])
+        need = ctypes.c_size_t()
+        done = np.zeros(len(self.handles))
+        tot = np.zeros(1)
+        plan = self.plan
+        st = self.lib.lrdm_batch_run(self.b, arr, None, None,
+                                     ctypes.c_void_p(plan.data_ptr()) if plan is not None else None,
+                                     plan.numel() if plan is not None else 0, ctypes.byref(need), _dptr(done), _dptr(tot))
+        if st == 2:   # LRDM_E_NOMEM: the plan buffer is missing or too small
+            self.plan = torch.empty(need.value, dtype=torch.uint8, device=self.device)
+            st = self.lib.lrdm_batch_run(self.b, arr, None, None, ctypes.c_void_p(self.plan.data_ptr()),
+                                         need.value, ctypes.byref(need), _dptr(done), _dptr(tot))
+        _check(st)
+        return done, float(tot[0])
 
     def launch(self):
         _check(self.lib.lrdm_batch_launch(self.b))

@@ -75,3 +75,67 @@ def test_python_binding_fails_loudly_without_library(tmp_path):
             mod.load_library(str(tmp_path / "missing.so"))
     finally:
         mod._lib = saved
+
+
+# ------------------------------------------------------------------- program-level calls
+def _flat(ops, n=4):
+    from workloads import circuits as C
+
+    return lr.lrdm.FlatProgram(C.Program(n, ops, 4, "c64", 4))
+
+
+def _validate(fp, n=4):
+    lib = lr.load_library()
+    return lib.lrdm_program_validate(fp.ref, n, None, 0)
+
+
+def test_program_validation_accepts_a_workload():
+    from workloads import circuits as C
+
+    for prog in (C.cfg1_program(layers=2), C.cfg4_program(C.cfg4_angles(n=5, layers=2), n=5),
+                 C.cfg2_program(n=6, iterations=1)):
+        fp = lr.lrdm.FlatProgram(prog)
+        assert _validate(fp, prog.n) == 0, lr.load_library().lrdm_last_error(None)
+    fp = lr.lrdm.FlatProgram(C.cfg4_program(C.cfg4_angles(n=5, layers=2), n=5))
+    assert fp.n_params == 2 * 5 * 2 and fp.n_layers == 2
+
+
+def test_program_validation_rejects():
+    import numpy as np
+
+    from workloads import circuits as C
+
+    lib = lr.load_library()
+    bad = {
+        "qubit out of range": [C.Gate((4,), C.H)],
+        "repeated": [C.Gate((1, 1), C.CZ, True)],
+        "not unitary": [C.Gate((0,), np.array([[1, 1], [0, 1]]))],
+        "followed by a compression": [C.Kraus(0, C.depolarizing(0.1))],
+        "not complete": [C.Kraus(0, np.stack([C.I2, C.X])), C.Compress(4)],
+        "unit modulus": [C.DiagWeight(np.full(5, 2.0))],
+    }
+    for why, ops in bad.items():
+        assert _validate(_flat(ops)) == 1, why
+        assert lib.lrdm_last_error(None).decode().startswith("op "), why
+    # rotation axis out of range and a parameter index beyond n_params
+    fp = _flat([C.Gate((0,), C.rx(0.3), False, "rx", (0, "X"))])
+    fp.ops[0].axis = 4
+    assert _validate(fp) == 1
+    fp.ops[0].axis = 1
+    theta = (ctypes.c_double * 1)(0.3)
+    fp.ops[0].param = 3
+    assert lib.lrdm_program_validate(fp.ref, 4, theta, 1) == 1
+    # coefficients beyond the array
+    fp = _flat([C.Gate((0,), C.H)])
+    fp.ops[0].off = 4
+    assert _validate(fp) == 1
+    # null program, n out of range, null handles for the program calls
+    assert lib.lrdm_program_validate(None, 4, None, 0) == 1
+    assert lib.lrdm_program_validate(_flat([C.Gate((0,), C.H)]).ref, 0, None, 0) == 1
+    fp = _flat([C.Gate((0,), C.H)])
+    assert lib.lrdm_run(None, fp.ref, None, 0, None, 0, None) == 1
+    kb, mb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.lrdm_energy_grad_bytes(None, fp.ref, ctypes.byref(kb), ctypes.byref(mb)) == 1
+    need = ctypes.c_size_t()
+    assert lib.lrdm_batch_run(None, None, None, None, None, 0, ctypes.byref(need), None, None) == 1
+    assert lib.lrdm_layout(None, None, None, None, None) == 1

@@ -25,20 +25,29 @@ METRIC = "noisy-circuit layers/s at n=20 r=64 vs full-rank DM, same GPU; %HBM pe
 FP32_MFMA_PEAK = 157.3e12
 FP64_PEAK = 78.6e12      # vector (and MFMA): 256 CUs x 2.4 GHz x 128 flop per CU and clock
 HBM_PEAK = 8.0e12
-CLASS_NAMES = {0: "gate_pass", 1: "gram", 2: "gram_reduce", 3: "eigensolve", 4: "projection"}
+CLASS_NAMES = {0: "gate_pass", 1: "gram", 2: "gram_reduce", 3: "eigensolve", 4: "projection", 5: "chain_small"}
 
 
-def algorithmic_flops(n: int, r_pad: int, cls: int, m: int = 2, k: int = 64) -> float:
+# Blocks of the projection matrix W (2 x 2 blocks of r x r, input value -> output value of the
+# channel's qubit) that are not identically zero for amplitude damping followed by dephasing:
+# no Kraus operator of either channel maps |0> to |1> (amplitude damping only lowers, dephasing
+# is diagonal), so the composed W has a zero block from input half 0 to output half 1, and 3 of
+# the 4 blocks carry work.
+PROJ_NONZERO_BLOCKS = 3
+
+
+def algorithmic_flops(n: int, r_pad: int, cls: int, m: int = 2, k: int = 64, blocks: int = PROJ_NONZERO_BLOCKS) -> float:
     """Real flops one launch must do (complex MAC = 8 flops).  Gram and projection work on the
     split view X = [L_0 | L_1] (2^(n-1) x 2r): the Gram matrix is Hermitian (half of X^H X),
-    the projection is X W with W of size 2r x 2r.  The eigensolve of the order-N Gram matrix
-    (N = m r_pad) counts the Householder reduction to tridiagonal form, (16/3) N^3, and the
-    back-transform of the k kept eigenvectors, 8 N^2 k (the O(N^2) tridiagonal part is left out)."""
+    the projection is X W with W of size 2r x 2r, of which `blocks` of the four r x r blocks are
+    not identically zero.  The eigensolve of the order-N Gram matrix (N = m r_pad) counts the
+    Householder reduction to tridiagonal form, (16/3) N^3, and the back-transform of the k kept
+    eigenvectors, 8 N^2 k (the O(N^2) tridiagonal part is left out)."""
     rows, w = 2 ** (n - 1), 2 * r_pad
     if cls == 1:
         return 8.0 * rows * w * w / 2
     if cls == 4:
-        return 8.0 * rows * w * w
+        return 8.0 * rows * w * w * blocks / 4
     if cls == 3:
         N = m * r_pad
         return 16.0 / 3.0 * N ** 3 + 8.0 * N * N * k
@@ -72,6 +81,102 @@ def measured_traffic(cls: int):
     return int(m.group(1))
 
 
+MFMA_FILE = os.path.join(ROOT, "profiles", "gemm_kernels_brickwork_n20_r64_mfma_counters.md")
+
+
+def measured_mfma(cls: int):
+    """MFMA counters of a GEMM kernel class from the committed rocprofv3 summary: busy fraction of
+    the matrix cores over the kernel (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs)) and the
+    FP32 MFMA operations it issued per launch (SQ_INSTS_VALU_MFMA_MOPS_F32 x 512), or None when
+    there is no summary or the kernel source has changed since it was taken."""
+    import hashlib
+    import re
+
+    key = CLASS_NAMES[cls]
+    try:
+        text = open(MFMA_FILE).read()
+    except OSError:
+        return None
+    busy = re.search(rf"^mfma_busy_frac {key}: ([0-9.eE+-]+)$", text, re.M)
+    flops = re.search(rf"^mfma_flops_per_launch {key}: ([0-9.eE+-]+)$", text, re.M)
+    src = CLASS_SOURCE.get(cls)
+    h = re.search(rf"^kernel_source_sha256 {re.escape(src)}: ([0-9a-f]+)$", text, re.M) if src else None
+    if not busy or not flops or not h:
+        return None
+    path = os.path.join(ROOT, "paper_2009_06657_amd", "csrc", src)
+    if hashlib.sha256(open(path, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return {"busy_frac": float(busy.group(1)), "mfma_flops_per_launch": float(flops.group(1))}
+
+
+def error_vs_oracle(dm, prog, zz, samples) -> dict:
+    """The step's outputs against the FP64 oracle's for the same circuit (tests/golden, written by
+    tests/golden/make_cfg3_golden.py from the oracle alone): <Z_i Z_{i+1}> and <Z_i>, Prob(x) at
+    8192 fixed indices (absolute and relative to the oracle's value), and the samples (those that
+    differ, and the largest distance of their uniform to a CDF step of the oracle's distribution)."""
+    path = os.path.join(ROOT, "tests", "golden", f"cfg3_n20_r64_l{prog.layers}.json")
+    if prog.n != 20 or prog.r != 64 or not os.path.exists(path):
+        return {"available": False, "reason": f"no oracle run stored for n={prog.n} r={prog.r} layers={prog.layers}"}
+    with open(path) as f:
+        g = json.load(f)
+    z, zz_now, _ = dm.expect_z()
+    P = dm.probabilities().cpu().numpy()
+    idx = np.concatenate([np.array(g["prob_largest_idx"]), np.array(g["prob_random_idx"])])
+    ref = np.concatenate([np.array(g["prob_largest"]), np.array(g["prob_random"])])
+    dP = np.abs(P[idx] - ref)
+    diff = np.nonzero(np.asarray(samples, dtype=np.uint64) != np.array(g["samples"], dtype=np.uint64))[0]
+    margin = np.array(g["sample_margin"])
+    return {"available": True, "golden": os.path.relpath(path, ROOT),
+            "zz": float(np.max(np.abs(np.asarray(zz) - np.array(g["zz"])))),
+            "z": float(np.max(np.abs(z - np.array(g["z"])))),
+            "prob_8192_fixed_idx": float(dP.max()),
+            "prob_8192_fixed_idx_rel": float(np.max(dP / np.maximum(ref, 1e-300))),
+            "trace": abs(float(np.sum(P)) - g["trace"]),
+            "samples_differing": int(diff.size), "samples": int(len(samples)),
+            "samples_differing_max_margin": float(margin[diff].max()) if diff.size else 0.0}
+
+
+def plain_comparator(prog, uniforms, ms_fused: float, steps: int = 2) -> dict:
+    """The plain low-rank form on the same workload and GPU: the Kraus concatenation
+    [E_1 L | E_2 L] materialised in HBM (Eq. "low rank evolution K" taken literally, 2^20 x 128
+    complex64), its full (m r) x (m r) Gram matrix, and the projection L' V_k, one compression at
+    a time (no chaining of the two channels on a qubit)."""
+    import torch
+
+    import paper_2009_06657_amd as lr
+
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, lr.FLAG_PLAIN)
+    run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        zz, _, tr = run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    br = {}
+    for cls in (1, 3, 4):
+        dm.timing_begin(cls)
+        run_step(dm, prog, uniforms)
+        br[cls] = dm.timing_end()
+    rows, ld = 2 ** prog.n, dm.ld
+    k = prog.r
+    gram_flops = 8.0 * rows * ld * ld / 2            # Hermitian half of the (m r)^2 complex Gram
+    proj_flops = 8.0 * rows * ld * k                 # L' (2^n x m r) times V_k (m r x k)
+    dm.close()
+    del dm
+    torch.cuda.empty_cache()
+    return {"workload": "same circuit, plain form (LRDM_FLAG_PLAIN): materialised Kraus concatenation, "
+                        f"Gram of order {ld}, projection L' V_k, every compression separately",
+            "layers_per_s": prog.layers * 1e3 / ms, "ms_per_step": ms, "fused_over_plain": ms / ms_fused,
+            "trace_after": tr,
+            "gram": {"launches": br[1][0], "mean_ms": br[1][1], "tflops": gram_flops / (br[1][1] * 1e-3) / 1e12,
+                     "frac_fp32_mfma": gram_flops / (br[1][1] * 1e-3) / FP32_MFMA_PEAK},
+            "projection": {"launches": br[4][0], "mean_ms": br[4][1],
+                           "tflops": proj_flops / (br[4][1] * 1e-3) / 1e12,
+                           "frac_fp32_mfma": proj_flops / (br[4][1] * 1e-3) / FP32_MFMA_PEAK},
+            "eigensolve_mean_ms": br[3][1]}
+
+
 def run_step(dm, prog, uniforms):
     from paper_2009_06657_amd import run_program
 
@@ -82,46 +187,97 @@ def run_step(dm, prog, uniforms):
     return zz, s, tr
 
 
-def cpu_baseline(n: int, r: int, budget_s: float = 20.0) -> dict:
-    """The CPU oracle on a bounded sample of the same workload: from a steady-state rank-r
-    factor, one layer's gates and as many channel+compress steps as fit the budget; the layer
-    time is extrapolated to 40 compressions."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_layer_sample(n: int, r: int, budget_s: float, max_gates: int = 1 << 30, max_comp: int = 1 << 30):
+    """From a steady-state rank-r factor: the gates and channel+compress steps of one brickwork
+    layer that fit the budget; returns (per-gate s, gates done, per-compress s, compresses done,
+    gates per layer, compresses per layer)."""
     import oracle
     from oracle.lret import compress, kraus_expand
     from workloads import circuits as C
 
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
-    except Exception:
-        cores = os.cpu_count()
     prog = C.cfg3_program(n=n, r=r, layers=1)
     L = C.random_orthogonal_factor(n, r, seed=4242)
     gates = [op for op in prog.ops if isinstance(op, C.Gate)]
     chans = [op for op in prog.ops if isinstance(op, C.Kraus)]
     t0 = time.perf_counter()
     g_done = 0
-    for op in gates:
+    for op in gates[:max_gates]:
         L = oracle.apply_gate(L, n, op.qubits, op.u)
         g_done += 1
         if time.perf_counter() - t0 > 0.25 * budget_s:
             break
     per_gate = (time.perf_counter() - t0) / g_done
     done, t_comp = 0, 0.0
-    for ch in chans:
+    for ch in chans[:max_comp]:
         t1 = time.perf_counter()
         L, _ = compress(kraus_expand(L, n, ch.qubit, ch.ops), r)
         t_comp += time.perf_counter() - t1
         done += 1
         if t_comp > 0.75 * budget_s:
             break
-    per_comp = t_comp / done
-    t_layer = per_gate * len(gates) + per_comp * len(chans)
-    return {"value": 1.0 / t_layer, "unit": "layers/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"n={n} r={r}, from a steady-state rank-{r} factor: {g_done} of {len(gates)} "
-                       f"gates and {done} of {len(chans)} channel+compress steps of one brickwork "
-                       f"layer, extrapolated to the whole layer ({per_gate:.2f} s per gate, "
-                       f"{per_comp:.2f} s per compress)")}
+    return per_gate, g_done, t_comp / done, done, len(gates), len(chans)
+
+
+def cpu_baseline(n: int, r: int, budget_s: float = 20.0) -> dict:
+    """The CPU oracle on the host cores.  The headline value: a bounded sample of the benchmark
+    layer (from a steady-state rank-r factor, the layer's gates and as many channel+compress steps
+    as fit the budget, extrapolated to the 30 gates and 40 compressions of a layer) with every BLAS
+    thread; the same sample with one thread (one gate, one compression); and whole-run oracle
+    times of the three smaller workloads."""
+    import oracle
+    from oracle import grad as OG
+    from workloads import circuits as C
+
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count()
+    per_gate, g_done, per_comp, done, ng, nc = _oracle_layer_sample(n, r, budget_s)
+    t_layer = per_gate * ng + per_comp * nc
+    out = {"value": 1.0 / t_layer, "unit": "layers/s", "cores": int(cores), "kind": "oracle",
+           "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+           "sample": (f"n={n} r={r}, from a steady-state rank-{r} factor: {g_done} of {ng} "
+                      f"gates and {done} of {nc} channel+compress steps of one brickwork "
+                      f"layer, extrapolated to the whole layer ({per_gate:.2f} s per gate, "
+                      f"{per_comp:.2f} s per compress)")}
+    if threadpool_limits is not None:
+        with threadpool_limits(1):
+            g1, _, c1, _, _, _ = _oracle_layer_sample(n, r, 1e9, max_gates=1, max_comp=1)
+        out["one_thread"] = {"value": 1.0 / (g1 * ng + c1 * nc), "unit": "layers/s",
+                             "sample": f"one gate ({g1:.2f} s) and one channel+compress step ({c1:.2f} s), "
+                                       "extrapolated to the layer"}
+    whole = {}
+    t0 = time.perf_counter()
+    prog = C.cfg1_program()
+    oracle.run_lret(prog)
+    whole["depolarizing_n6_r13_c128"] = {"s": time.perf_counter() - t0, "layers": prog.layers,
+                                         "layers_per_s": prog.layers / (time.perf_counter() - t0)}
+    t0 = time.perf_counter()
+    prog = C.cfg2_program()
+    oracle.run_lret(prog)
+    whole["grover_n14_r32"] = {"s": time.perf_counter() - t0, "layers": prog.layers,
+                               "layers_per_s": prog.layers / (time.perf_counter() - t0)}
+    theta = C.cfg4_angles()
+    xm, zm, co, _ = C.random_pauli_sum(12)
+    t0 = time.perf_counter()
+    OG.energy_grad_adjoint(C.cfg4_program(theta), theta.size, xm, zm, co)
+    dt = time.perf_counter() - t0
+    whole["ansatz_n12_r16_energy_and_gradient"] = {"s": dt, "grads_per_s": 1.0 / dt,
+                                                    "method": "the oracle's FP64 reverse sweep"}
+    out["whole_runs"] = whole
+    return out
 
 
 def gradient_throughput(reps: int = 3) -> dict:
@@ -388,7 +544,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--layers", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true", help="accepted for older command lines; the per-class "
+                    "timing always runs (one extra step per kernel class)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain low-rank form comparator")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient-throughput leg")
     ap.add_argument("--no-fdm", action="store_true", help="skip the full-rank comparator leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-serving leg")
@@ -435,46 +593,57 @@ def main():
         run_step(dm, prog, uniforms)
     torch.cuda.synchronize()
 
-    # The eigensolve (class 3, four kernels bracketed by one pair of events) takes the most time
-    # per step; the projection (class 4) is the MFMA-bound GEMM and the gate pass (class 0) the
-    # HBM-bound sweep.  Each is timed with HIP events on the handle's stream over the timed
-    # region, one class per step in turn; a class no timed step covered is timed on an extra,
-    # untimed step.
-    dominant = 3
-    order = (3, 4, 0)
-    timed = {c: [0, 0.0] for c in order}
+    # the timed steps carry no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        cls = order[i % len(order)]
-        dm.timing_begin(cls)
         zz, samples, tr = run_step(dm, prog, uniforms)
-        n_, m_, t_ = dm.timing_end()
-        timed[cls][0] += n_
-        timed[cls][1] += t_
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    for cls in order:
-        if timed[cls][0] == 0:
-            dm.timing_begin(cls)
-            run_step(dm, prog, uniforms)
-            n_, m_, t_ = dm.timing_end()
-            timed[cls] = [n_, t_]
+
+    # per-class kernel times: one further step per class, every launch of that class bracketed
+    # by HIP events on the handle's stream
+    br = {}
+    for cls in (0, 1, 2, 3, 4, 5):
+        dm.timing_begin(cls)
+        run_step(dm, prog, uniforms)
+        n_, m_, t_ = dm.timing_end()
+        br[cls] = (n_, m_, t_)
+    # the dominant kernel class: the most time per step
+    dominant = max((0, 1, 3, 4), key=lambda c: br[c][2])
 
     layers = args.layers * args.steps
     ms_per_step = 1e3 * elapsed / args.steps
     ms_per_layer = ms_per_step / args.layers
+
     def roof(cls, bound, peak):
-        nl, tot = timed[cls]
-        mean_ms = tot / max(nl, 1)
+        nl, mean_ms, _ = br[cls]
         if bound == "hbm":   # a gate pass reads and writes the factor once
             work, unit, scale = 2.0 * 2 ** prog.n * dm.r_pad * 8, "GB/s", 1e9
         else:
             work, unit, scale = algorithmic_flops(prog.n, dm.r_pad, cls), "TFLOP/s", 1e12
         achieved = work / (mean_ms * 1e-3)
-        return {"bound": bound, "kernel": CLASS_NAMES[cls], "achieved": achieved / scale, "peak": peak / scale,
-                "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(cls), "launches": nl,
-                "mean_ms": mean_ms}
+        out = {"bound": bound, "kernel": CLASS_NAMES[cls], "achieved": achieved / scale, "peak": peak / scale,
+               "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(cls), "launches": nl,
+               "mean_ms": mean_ms, "work_per_launch": work}
+        mf = measured_mfma(cls)
+        if mf is not None:
+            out["mfma_counters"] = mf
+        return out
+
+    def roof_of(cls):
+        if cls == 0:
+            return roof(0, "hbm", HBM_PEAK)
+        if cls == 3:
+            r_ = roof(3, "alu", FP64_PEAK)
+            # the eigensolve runs on the serial path, its reduction and eigenvector kernels on one
+            # work-group (the multisection uses one per wave, the back-transform 16): its fraction
+            # of a single CU's FP64 peak (256 CUs) is the meaningful utilisation figure
+            r_["peak_one_cu"] = FP64_PEAK / 256 / 1e12
+            r_["frac_one_cu"] = r_["frac"] * 256
+            return r_
+        return roof(cls, "mfma", FP32_MFMA_PEAK)
+
     out = {
         "metric": METRIC, "value": layers / elapsed, "unit": "layers/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -484,24 +653,17 @@ def main():
                                "compress after every channel, <ZZ> + 1e4 samples",
                    "n": prog.n, "r": prog.r, "layers": args.layers, "compressions_per_step": prog.n_compress(),
                    "eigensolve": "f64", "trace_after": tr},
-        "roofline": dict(roof(dominant, "alu", FP64_PEAK)),
-        "roofline_projection": roof(4, "mfma", FP32_MFMA_PEAK),
-        "roofline_gate_pass": roof(0, "hbm", HBM_PEAK),
+        "roofline": roof_of(dominant),
+        "roofline_projection": roof_of(4),
+        "roofline_gram": roof_of(1),
+        "roofline_gate_pass": roof_of(0),
+        "roofline_eigensolve": roof_of(3),
+        "breakdown_one_step": {CLASS_NAMES[c]: {"launches": br[c][0], "mean_ms": br[c][1], "total_ms": br[c][2]}
+                               for c in br},
     }
-    if dominant == 3:
-        # the eigensolve runs on the serial path, its reduction and eigenvector kernels on one
-        # work-group (the multisection uses one per wave, the back-transform 16): its fraction
-        # of a single CU's FP64 peak (256 CUs) is the meaningful utilisation figure
-        out["roofline"]["peak_one_cu"] = FP64_PEAK / 256 / 1e12
-        out["roofline"]["frac_one_cu"] = out["roofline"]["frac"] * 256
-    if not args.no_breakdown:
-        br = {}
-        for cls in (0, 1, 2, 3, 4):
-            dm.timing_begin(cls)
-            run_step(dm, prog, uniforms)
-            n_, m_, t_ = dm.timing_end()
-            br[CLASS_NAMES[cls]] = {"launches": n_, "mean_ms": m_, "total_ms": t_}
-        out["breakdown_one_step"] = br
+    out["max_abs_err_vs_oracle"] = error_vs_oracle(dm, prog, zz, samples)
+    if not args.no_plain:
+        out["vs_plain_low_rank"] = plain_comparator(prog, uniforms, ms_per_step)
     if not args.no_grad:
         out["grads_per_s"] = gradient_throughput()
     if not args.no_batch:

@@ -154,8 +154,9 @@ lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank);
 /* Wait for all work queued on the handle's stream; reports asynchronous device errors. */
 lrdm_status lrdm_synchronize(lrdm_t h);
 
-/* Kernel timing for performance reports.  kernel_class: 0 = gate sweep, 1 = Gram, 2 = Gram
- * reduction, 3 = eigensolver (all stages), 4 = projection.  Between lrdm_timing_begin and
+/* Kernel timing for performance reports.  kernel_class: 0 = gate sweep, 1 = Gram pass over L,
+ * 2 = Gram reduction, 3 = eigensolver (all stages), 4 = projection, 5 = the small FP64 products
+ * of chained compressions (the second Gram matrix W^H S W and the composed W).  Between lrdm_timing_begin and
  * lrdm_timing_end every launch of that class is bracketed by HIP events on the handle's
  * stream; lrdm_timing_end synchronises and returns the number of launches and their mean
  * duration in milliseconds.  At most 65536 launches are recorded. */

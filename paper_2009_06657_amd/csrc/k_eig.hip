@@ -1063,7 +1063,7 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
     }
     if (act) {
       // four reflectors at a time: their LDS reads (every lane reads, from entry 0 where it
-      // needs none, and masks the value arithmetically, so no read sits behind a branch) are
+      // needs none, and selects the value it needs, so no read sits behind a branch) are
       // issued before the first is applied
       for (int jg = jhi; jg >= jlo; jg -= 4) {
         z64 v[4][RPL], tj[4];
@@ -1077,8 +1077,9 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
             const int i = lane + 64 * s;
             const bool stv = j >= jlo && i >= j + 2 && i < N;
             const z64 ld = rfl[stv ? ro + i : 0];
-            const double m = stv ? 1.0 : 0.0;
-            v[u][s] = zmk(fma(ld.x, m, i == j + 1 ? 1.0 : 0.0), ld.y * m);
+            // a select, not a multiplication by 0: entry 0 may not be staged yet, and LDS left
+            // by an earlier kernel can hold NaN or Inf
+            v[u][s] = stv ? ld : zmk(i == j + 1 ? 1.0 : 0.0, 0.0);
           }
         }
 #pragma unroll

@@ -575,9 +575,9 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   } else if (chain) {
     // S holds the Gram matrix of the split view before the previous compression; transform it
     // by that compression's own W (not the composed product)
-    timed_begin(h, 1);
+    timed_begin(h, 5);
     HIPCHK(h, launch_chain_gram(b.S, h->last_w_next ? Wn64 : Wp64, tmp64, Fc, h->stream));
-    timed_end(h, 1);
+    timed_end(h, 5);
   } else {
     timed_begin(h, 1);
     HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
@@ -592,7 +592,11 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   HIPCHK(h, launch_eig<T>(b.S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b,
                           W, h->stream));
   timed_end(h, 3);
-  if (chain) HIPCHK(h, launch_chain_compose<T>(Wp64, Wn64, tmp64, W, Fc, h->stream));
+  if (chain) {
+    timed_begin(h, 5);
+    HIPCHK(h, launch_chain_compose<T>(Wp64, Wn64, tmp64, W, Fc, h->stream));
+    timed_end(h, 5);
+  }
   if (defer) {
     const Reach here = channel_reach(ch);
     h->pend_skip = reach_skip(chain ? compose_reach(skip_reach(h->pend_skip), here) : here);
@@ -1085,7 +1089,7 @@ lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {
   if (st != LRDM_OK) return st;
   st = not_recording(h);
   if (st != LRDM_OK) return st;
-  if (kernel_class < 0 || kernel_class > 4) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 4]");
+  if (kernel_class < 0 || kernel_class > 5) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 5]");
   if (h->ev.empty()) {
     h->ev.resize(2 * kMaxTimed);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));

@@ -322,3 +322,45 @@ def test_error_paths(lr):
     z, _, tr = dm.expect_z()
     assert abs(tr - 1) < 1e-6
     dm.close()
+
+
+@pytest.mark.parametrize("plain", [0, 1])
+def test_non_finite_factor_poisons_the_handle(lr, plain):
+    """A NaN in the factor reaches the Gram matrix: the eigensolver reports it (LRDM_E_EIG at the
+    first call that synchronises), and every later call on the handle returns LRDM_E_STATE.
+    Every loop of the eigensolver is bounded independently of the values, so the kernels end."""
+    n, r = 8, 8
+    _say(f"[nan] plain={plain}")
+    L0 = C.random_orthogonal_factor(n, r, seed=3).astype(np.complex64)
+    L0[17, 2] = np.nan
+    dm = lr.LowRankDM(n, r, lr.C64, 2, lr.FLAG_PLAIN if plain else 0)
+    dm.set_L(L0)
+    dm.apply_kraus(3, C.amplitude_damping(0.1))
+    with pytest.raises(lr.LrdmError) as e:
+        dm.compress(r, info=True)
+    assert e.value.status == 4
+    with pytest.raises(lr.LrdmError) as e:
+        dm.expect_z()
+    assert e.value.status == 5
+    with pytest.raises(lr.LrdmError) as e:
+        dm.apply_gate((0,), C.H)
+    assert e.value.status == 5
+    dm.close()
+    # without info, the error surfaces at the next synchronising output call
+    dm = lr.LowRankDM(n, r, lr.C64, 2, lr.FLAG_PLAIN if plain else 0)
+    dm.set_L(L0)
+    dm.apply_kraus(5, C.phase_flip(0.1))
+    dm.compress(r)
+    with pytest.raises(lr.LrdmError) as e:
+        dm.expect_z()
+    assert e.value.status == 4
+    with pytest.raises(lr.LrdmError) as e:
+        dm.synchronize()
+    assert e.value.status == 5
+    dm.close()
+    # a fresh handle is unaffected
+    dm = lr.LowRankDM(n, r, lr.C64, 2)
+    dm.apply_gate((0,), C.H)
+    z, _, tr = dm.expect_z()
+    assert abs(tr - 1.0) < 1e-6
+    dm.close()

@@ -374,6 +374,20 @@ lrdm_status lrdm_batch_run(lrdm_batch_t b, const lrdm_program* const* progs, con
                            const int* n_params, void* plan_dev, size_t plan_bytes, size_t* plan_needed,
                            double* done_ms, double* total_ms);
 
+/* ---------------------------------------------------------------- allocation-free outputs
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): <Z_i>, <Z_i Z_{i+1}> and the trace of a factor the
+ * caller holds, with no handle and no workspace.  L_dev: the factor in the state layout
+ * (row-major 2^n x ld, complex64 or complex128 by dt; columns >= ncols are ignored), device
+ * memory owned by the caller.  Outputs as lrdm_expect_z (z_host: n doubles; zz_host: n - 1
+ * doubles, nullable; trace_host nullable).  The kernels' scratch (Prob(x) and the reduction's
+ * partial sums) is a device array inside the library, 8.3 MiB per GPU, held until the process
+ * ends; it limits n to 20 (larger n: LRDM_E_UNSUPPORTED).  No call allocates or frees device
+ * memory.  Every call on a GPU uses that GPU's one array: calls that overlap on one GPU (several
+ * threads or streams at once) race.  Synchronises hip_stream. */
+lrdm_status lrdm_expect_z_noalloc(const void* L_dev, int n, int ld, int ncols, lrdm_dtype dt, void* hip_stream,
+                                  double* z_host, double* zz_host, double* trace_host);
+
 /* Last error message for h, or the calling thread's last error when h == NULL. */
 const char* lrdm_last_error(lrdm_t h);
 

@@ -31,7 +31,7 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_fdm_synchronize", "lrdm_fdm_last_error", "lrdm_batch_create", "lrdm_batch_begin",
            "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
            "lrdm_batch_times", "lrdm_batch_destroy", "lrdm_layout", "lrdm_run", "lrdm_energy_grad_bytes",
-           "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate"]
+           "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate", "lrdm_expect_z_noalloc"]
 
 OP_GATE, OP_ROTATION, OP_WEIGHT, OP_KRAUS, OP_COMPRESS, OP_LAYER = range(6)
 _AXIS = {"X": 1, "Y": 2, "Z": 3}
@@ -177,6 +177,7 @@ def load_library(path: str = LIB_PATH):
         "lrdm_energy_grad": [P, P, ctypes.POINTER(CProgram), dp, I, I, P, P, P, dp, dp, P, SZ, ctypes.POINTER(I)],
         "lrdm_batch_run": [P, ctypes.POINTER(ctypes.POINTER(CProgram)), P, P, P, SZ, ctypes.POINTER(SZ), dp, dp],
         "lrdm_program_validate": [ctypes.POINTER(CProgram), I, dp, I],
+        "lrdm_expect_z_noalloc": [P, I, I, I, I, P, dp, dp, dp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -205,6 +206,15 @@ def _cplx(a) -> np.ndarray:
 
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def expect_z_noalloc(L_dev_ptr: int, n: int, ld: int, ncols: int, dtype: int = C64, stream=None):
+    """lrdm_expect_z_noalloc on a device factor (pointer, state layout): (z, zz, trace)."""
+    lib = load_library()
+    z, zz, tr = np.zeros(n), np.zeros(max(n - 1, 1)), np.zeros(1)
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib.lrdm_expect_z_noalloc(ctypes.c_void_p(L_dev_ptr), n, ld, ncols, dtype, s, _dptr(z), _dptr(zz), _dptr(tr)))
+    return z, zz[: n - 1], float(tr[0])
 
 
 def workspace_size(n: int, r_max: int, dtype: int = C64, m_max: int = 4, flags: int = 0):

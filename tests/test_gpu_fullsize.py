@@ -15,9 +15,10 @@
 
 Tolerances (complex64 bulk, FP64 eigensolve): observables and probabilities 1e-5 absolute (the
 method's target).  Prob(x) of the n = 20 state (mean 1e-6) is also held to a relative bound,
-|dP| <= 2e-3 P + 1e-10: FP32 rounding of the factor perturbs each entry in proportion to it.
-A sample may differ only where u * CDF(last) lies within 1e-6 of a CDF step (relative): there
-the FP32 factor's probabilities legitimately move the step.
+|dP| <= 1e-3 P + 1e-10: FP32 rounding of the factor perturbs each entry in proportion to it
+(measured: 3.3e-6 after one layer, 7.7e-5 after four).  A sample may differ only where
+u * CDF(last) lies within 1e-7 of a CDF step (relative; measured mismatches sit within 2.2e-8):
+there the FP32 factor's probabilities legitimately move the step.
 """
 import copy
 import json
@@ -117,8 +118,8 @@ def test_brickwork_n20_r64_against_oracle(lr, layers):
          f"max rel dP {rel:.2e}  sample mismatches {mism.size} (margins {margin[mism].tolist()[:5]})")
     assert ed <= 1e-6 and et <= 1e-5
     assert max(ez) <= 1e-5 and max(ezz) <= 1e-5
-    assert np.all(dl <= 2e-3 * pl + 1e-10) and np.all(dr <= 2e-3 * pr + 1e-10)
-    assert np.all(margin[mism] < 1e-6)
+    assert np.all(dl <= 1e-3 * pl + 1e-10) and np.all(dr <= 1e-3 * pr + 1e-10)
+    assert np.all(margin[mism] < 1e-7)
     # the benchmark issues the same ops without per-compression info: identical results
     dm2 = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max)
     lr.run_program(dm2, prog)

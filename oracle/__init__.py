@@ -20,7 +20,7 @@ r >= rank.  Functions without such a pin say "parity unpinned" in their docstrin
 """
 from .linalg import apply_gate, popcount  # noqa: F401
 from .lret import (run_lret, compress, kraus_expand, apply_diag_weight, init_state,  # noqa: F401
-                   select_rank, TAU_CLUSTER)
+                   select_rank, TAU_CLUSTER, init_sparse, intermediate_rank, run_lret_switching)
 from .fdm import run_fdm, run_sv  # noqa: F401
 from .observables import (probabilities, expect_pauli, expect_z, expect_zz, sample_inverse_cdf,  # noqa: F401
                           distortion, pauli_sum_expectation)

@@ -19,12 +19,24 @@ def _sandwich(rho: np.ndarray, n: int, qubits, U: np.ndarray) -> np.ndarray:
     return b.conj().T                                 # (U rho^H U^H)^H = U rho U^H
 
 
+def _initial(program) -> np.ndarray:
+    """|0...0>, or the program's sparse superposition sum_i a_i |x_i>."""
+    psi = np.zeros(2 ** program.n, dtype=np.complex128)
+    if program.init is None:
+        psi[0] = 1.0
+    else:
+        idx, amp = program.init
+        psi[np.asarray(idx, dtype=np.int64)] = np.asarray(amp, dtype=np.complex128)
+    return psi
+
+
 def fdm_gate(rho, n, qubits, U):
     return _sandwich(rho, n, qubits, U)
 
 
-def fdm_channel(rho, n, qubit, ops):
-    return sum(_sandwich(rho, n, (qubit,), E) for E in ops)
+def fdm_channel(rho, n, qubit, ops, qubit2: int = -1):
+    qs = (qubit,) if qubit2 < 0 else (qubit, qubit2)
+    return sum(_sandwich(rho, n, qs, E) for E in ops)
 
 
 def fdm_diag_weight(rho, n, phase):
@@ -38,15 +50,15 @@ def run_fdm(program) -> np.ndarray:
     from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
     n = program.n
-    rho = np.zeros((2 ** n, 2 ** n), dtype=np.complex128)
-    rho[0, 0] = 1.0
+    psi0 = _initial(program)
+    rho = np.outer(psi0, psi0.conj())
     for op in program.ops:
         if isinstance(op, Gate):
             rho = fdm_gate(rho, n, op.qubits, op.u)
         elif isinstance(op, DiagWeight):
             rho = fdm_diag_weight(rho, n, op.phase)
         elif isinstance(op, Kraus):
-            rho = fdm_channel(rho, n, op.qubit, op.ops)
+            rho = fdm_channel(rho, n, op.qubit, op.ops, op.qubit2)
         elif isinstance(op, (Compress, LayerEnd)):
             pass
         else:
@@ -59,8 +71,7 @@ def run_sv(program) -> np.ndarray:
     from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
     n = program.n
-    psi = np.zeros((2 ** n, 1), dtype=np.complex128)
-    psi[0, 0] = 1.0
+    psi = _initial(program)[:, None]
     w = popcount(np.arange(2 ** n, dtype=np.uint64))
     for op in program.ops:
         if isinstance(op, Gate):

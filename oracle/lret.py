@@ -4,7 +4,9 @@ Follows the paper step by step:
   * state rho = L L^H with L in C^{2^N x V}                 (Eq. "low rank decomposition", Sec. II.A)
   * gate: L <- G L                                          (Eq. "low rank evolution G")
   * Kraus channel: L <- [sqrt(p_1) K_1 L, ..., sqrt(p_A) K_A L]   (Eq. "low rank evolution K")
-  * truncation after each channel group                      (Sec. II.C; Algorithm 1)
+  * truncation after each channel group (one- or two-qubit)   (Sec. II.C; Algorithm 1)
+  * a switch to full density matrix evolution once the intermediate rank reaches 2^N
+                                                              (Sec. II.C, last paragraph)
   * truncation through the small matrix L^H L instead of rho   (Sec. II.B, Theorem 1 of App. B)
 
 Readings where the paper is silent (each also listed in the design notes):
@@ -45,10 +47,26 @@ def apply_diag_weight(L: np.ndarray, n: int, phase: np.ndarray) -> np.ndarray:
     return L * np.asarray(phase, dtype=np.complex128)[w][:, None]
 
 
-def kraus_expand(L: np.ndarray, n: int, qubit: int, ops: np.ndarray) -> np.ndarray:
-    """L' = [E_1 L | E_2 L | ... | E_A L] with E_a = sqrt(p_a) K_a acting on `qubit`
-    (Eq. "low rank evolution K"); the column count grows A-fold, block-major by a."""
-    return np.concatenate([apply_gate(L, n, (qubit,), E) for E in ops], axis=1)
+def init_sparse(n: int, idx, amp) -> np.ndarray:
+    """A sparse linear combination of basis states, sum_i a_i |x_i>, as a one-column factor (the
+    other initial states Algorithm 1 admits, Sec. II.D)."""
+    L = np.zeros((2 ** n, 1), dtype=np.complex128)
+    L[np.asarray(idx, dtype=np.int64), 0] = np.asarray(amp, dtype=np.complex128)
+    return L
+
+
+def kraus_expand(L: np.ndarray, n: int, qubit: int, ops: np.ndarray, qubit2: int = -1) -> np.ndarray:
+    """L' = [E_1 L | E_2 L | ... | E_A L] with E_a = sqrt(p_a) K_a acting on `qubit` (or on the
+    pair (qubit, qubit2) for a two-qubit channel, Sec. II.C) (Eq. "low rank evolution K"); the
+    column count grows A-fold, block-major by a."""
+    qs = (qubit,) if qubit2 < 0 else (qubit, qubit2)
+    return np.concatenate([apply_gate(L, n, qs, E) for E in ops], axis=1)
+
+
+def intermediate_rank(n: int, A: int, V: int, M: int) -> float:
+    """V_I with V_I^3 = N (A V)^3 / M (Eq. "intermediate rank", Sec. II.C): A Kraus matrices per
+    group of M qubits acting on a factor of V columns."""
+    return (n / M) ** (1.0 / 3.0) * A * V
 
 
 def select_rank(lam_desc: np.ndarray, trace: float, r: int, eps: float, tie: int,
@@ -97,14 +115,19 @@ def run_lret(program, L0: np.ndarray | None = None, log: list | None = None) -> 
     from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
     n = program.n
-    L = init_state(n) if L0 is None else np.array(L0, dtype=np.complex128)
+    if L0 is not None:
+        L = np.array(L0, dtype=np.complex128)
+    elif program.init is not None:
+        L = init_sparse(n, *program.init)
+    else:
+        L = init_state(n)
     for op in program.ops:
         if isinstance(op, Gate):
             L = apply_gate(L, n, op.qubits, op.u)
         elif isinstance(op, DiagWeight):
             L = apply_diag_weight(L, n, op.phase)
         elif isinstance(op, Kraus):
-            L = kraus_expand(L, n, op.qubit, op.ops)
+            L = kraus_expand(L, n, op.qubit, op.ops, op.qubit2)
         elif isinstance(op, Compress):
             L, info = compress(L, op.r, op.eps, op.tie, op.renorm)
             if log is not None:
@@ -115,3 +138,45 @@ def run_lret(program, L0: np.ndarray | None = None, log: list | None = None) -> 
         else:
             raise TypeError(f"unknown op {op!r}")
     return L
+
+
+def run_lret_switching(program):
+    """Algorithm 1 with the switch of Sec. II.C: before each channel group, if its intermediate
+    rank V_I (A Kraus matrices on M qubits, V the current column count) reaches 2^N, the low-rank
+    evolution stops, rho = L L^H is formed and the remaining operations run as full density
+    matrix evolution (compressions no longer apply).  Returns (rho, index of the operation at
+    which the switch happened, or -1) with rho = L L^H when no switch happened."""
+    from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
+
+    from .fdm import fdm_channel, fdm_diag_weight, fdm_gate
+
+    n = program.n
+    L = init_sparse(n, *program.init) if program.init is not None else init_state(n)
+    rho = None
+    switched = -1
+    for i, op in enumerate(program.ops):
+        if rho is None and isinstance(op, Kraus):
+            if intermediate_rank(n, op.ops.shape[0], L.shape[1], len(op.qubits)) >= 2 ** n:
+                rho = L @ L.conj().T
+                switched = i
+        if rho is not None:
+            if isinstance(op, Gate):
+                rho = fdm_gate(rho, n, op.qubits, op.u)
+            elif isinstance(op, DiagWeight):
+                rho = fdm_diag_weight(rho, n, op.phase)
+            elif isinstance(op, Kraus):
+                rho = fdm_channel(rho, n, op.qubit, op.ops, op.qubit2)
+            elif not isinstance(op, (Compress, LayerEnd)):
+                raise TypeError(f"unknown op {op!r}")
+            continue
+        if isinstance(op, Gate):
+            L = apply_gate(L, n, op.qubits, op.u)
+        elif isinstance(op, DiagWeight):
+            L = apply_diag_weight(L, n, op.phase)
+        elif isinstance(op, Kraus):
+            L = kraus_expand(L, n, op.qubit, op.ops, op.qubit2)
+        elif isinstance(op, Compress):
+            L, _ = compress(L, op.r, op.eps, op.tie, op.renorm)
+        elif not isinstance(op, LayerEnd):
+            raise TypeError(f"unknown op {op!r}")
+    return (L @ L.conj().T if rho is None else rho), switched

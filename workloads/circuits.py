@@ -45,8 +45,13 @@ class DiagWeight:
 @dataclasses.dataclass
 class Kraus:
     qubit: int
-    ops: np.ndarray  # (m, 2, 2) complex128, E_a = sqrt(p_a) K_a
+    ops: np.ndarray  # (m, 2, 2) complex128, E_a = sqrt(p_a) K_a; (m, 4, 4) with qubit2
     name: str = ""
+    qubit2: int = -1  # second qubit of a two-qubit channel (local index b(qubit) + 2 b(qubit2))
+
+    @property
+    def qubits(self) -> Tuple[int, ...]:
+        return (self.qubit,) if self.qubit2 < 0 else (self.qubit, self.qubit2)
 
 
 @dataclasses.dataclass
@@ -73,6 +78,9 @@ class Program:
     name: str = ""
     layers: int = 0
     meta: dict = dataclasses.field(default_factory=dict)
+    # initial state: None = |0...0>; else (indices, amplitudes) of a sparse superposition
+    # sum_i a_i |x_i> (unit norm), the other initial states Algorithm 1 admits (Sec. II.D)
+    init: Optional[Tuple[np.ndarray, np.ndarray]] = None
 
     def n_compress(self) -> int:
         return sum(isinstance(o, Compress) for o in self.ops)
@@ -144,6 +152,39 @@ def amplitude_damping(g: float) -> np.ndarray:
     return np.stack([e0, e1])
 
 
+PAULI_LIST = (I2, X, Y, Z)
+
+
+def depolarizing2(p: float) -> np.ndarray:
+    """Two-qubit depolarizing channel (1-p) rho + p/15 sum_{P != I (x) I} P rho P over the 15
+    non-identity two-qubit Pauli products (16 Kraus operators, 4 x 4, local index b(q0) +
+    2 b(q1))."""
+    ops = []
+    for a in range(4):
+        for b in range(4):
+            w = np.sqrt(1 - p) if (a == 0 and b == 0) else np.sqrt(p / 15)
+            ops.append(w * np.kron(PAULI_LIST[b], PAULI_LIST[a]))
+    return np.stack(ops)
+
+
+def correlated_dephasing(p: float) -> np.ndarray:
+    """(1-p) rho + p (Z (x) Z) rho (Z (x) Z): a two-qubit channel with two Kraus operators."""
+    return np.stack([np.sqrt(1 - p) * np.eye(4, dtype=np.complex128), np.sqrt(p) * np.kron(Z, Z)])
+
+
+def grouped_channel(ops0: np.ndarray, ops1: np.ndarray) -> np.ndarray:
+    """The product of a channel on q0 and one on q1 as a single two-qubit Kraus set
+    {E_a (x) F_b} (Sec. II.C: a Kraus layer decomposed into groups of M = 2 qubits, truncated
+    once per group); local index b(q0) + 2 b(q1), so the matrix of E (on q0) and F (on q1) is
+    kron(F, E)."""
+    return np.stack([np.kron(F, E) for E in ops0 for F in ops1])
+
+
+def ghz_init(n: int):
+    """(|0...0> + |1...1>) / sqrt(2) as a sparse initial state."""
+    return (np.array([0, 2 ** n - 1], dtype=np.uint64), np.array([1, 1], dtype=np.complex128) / np.sqrt(2.0))
+
+
 def grover_oracle_phase(n: int, max_weight: int = 2) -> np.ndarray:
     """Phase -1 on basis states of Hamming weight <= max_weight (the 'good' set of Sec. III.C)."""
     w = np.arange(n + 1)
@@ -191,6 +232,41 @@ def brickwork_program(n: int, layers: int, r: int, channels: Sequence[Tuple[str,
         ops.append(LayerEnd(l))
     m_max = max(_channel(ch, p).shape[0] for ch, p in channels) if channels else 1
     return Program(n, ops, r, dtype, m_max, name, layers)
+
+
+def grouped_brickwork_program(n: int, layers: int, r: int, channel: str, p: float, seed: int,
+                              dtype: str = "c64", eps: float = 0.0, tie: int = 0, renorm: int = 1,
+                              two_qubit: str = "") -> Program:
+    """Brickwork gates as in brickwork_program, then the layer's noise in groups of M = 2
+    qubits (q, q+1) for q = 0, 2, 4, ...: the product of the one-qubit channel on both qubits as
+    one two-qubit Kraus set, followed by one compression per group (Sec. II.C).  With two_qubit
+    = "dep2" or "zz", that two-qubit channel replaces the product on each pair."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ops: list = []
+    one = _channel(channel, p) if channel else None
+    m_max = 1
+    for l in range(layers):
+        for q in range(n):
+            ops.append(_g1(q, haar_su2(rng), "su2"))
+        start = 0 if l % 2 == 0 else 1
+        for a in range(start, n - 1, 2):
+            ops.append(_g2(a, a + 1, CZ, "cz", diagonal=True))
+        for q in range(0, n - 1, 2):
+            if two_qubit == "dep2":
+                ks = depolarizing2(p)
+            elif two_qubit == "zz":
+                ks = correlated_dephasing(p)
+            else:
+                ks = grouped_channel(one, one)
+            m_max = max(m_max, ks.shape[0])
+            ops.append(Kraus(q, ks, two_qubit or f"{channel}x{channel}", q + 1))
+            ops.append(Compress(r, eps, tie, renorm))
+        if n % 2 == 1 and one is not None:
+            ops.append(Kraus(n - 1, one, channel))
+            ops.append(Compress(r, eps, tie, renorm))
+        ops.append(LayerEnd(l))
+    return Program(n, ops, r, dtype, m_max, "grouped-brickwork", layers,
+                   {"channel": channel, "p": p, "two_qubit": two_qubit})
 
 
 GATES_1Q = ("X", "Y", "Z", "S", "T", "RX", "RY", "RZ")

@@ -120,6 +120,20 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e);
 lrdm_status lrdm_compress(lrdm_t h, int r_target, double eps, int tie_policy, int renorm,
                           lrdm_compress_info* info);
 
+/* Two-qubit Kraus channel (Sec. II.C: noise as one- and two-qubit Kraus operators; a group of
+ * M = 2 qubits' channels as their product set {E_a (x) F_b}) on (q0, q1): e holds m 4 x 4
+ * matrices (row-major, interleaved, local index b(q0) + 2 b(q1)), m in [1, m_max], completeness
+ * within 1e-10.  Plain form only (handles made with LRDM_FLAG_PLAIN, where m_max may be up to 16
+ * with m_pad * r_pad <= 128; fused handles: LRDM_E_UNSUPPORTED): [E_1 L | ... | E_m L] is
+ * materialised here and the next call must be lrdm_compress. */
+lrdm_status lrdm_apply_kraus2(lrdm_t h, int q0, int q1, int m, const double* e);
+
+/* Sparse superposition initial state (Sec. II.D: Algorithm 1 also starts from any sparse linear
+ * combination of basis states): L = sum_i amp[i] |idx[i]> as one column, count in [1, 32768],
+ * distinct indices below 2^n, amp interleaved complex with unit norm within 1e-10 (else
+ * LRDM_E_ARG).  Replaces the state like lrdm_set_L.  Synchronises. */
+lrdm_status lrdm_set_sparse(lrdm_t h, int count, const uint64_t* idx, const double* amp);
+
 /* Prob(x) = sum_v |L[x, v]|^2 (Sec. II.D) for all 2^n basis states into p_dev (2^n doubles,
  * device memory owned by the caller).  Asynchronous. */
 lrdm_status lrdm_probabilities(lrdm_t h, double* p_dev);
@@ -234,7 +248,10 @@ typedef enum {
   LRDM_OP_KRAUS = 3,     /* channel on q0 with m = k operators E_a at coef + off (as lrdm_apply_kraus);
                             the next operation must be LRDM_OP_COMPRESS */
   LRDM_OP_COMPRESS = 4,  /* lrdm_compress(r, eps, tie, renorm) */
-  LRDM_OP_LAYER = 5      /* end of a layer (checkpoint boundary); no arithmetic */
+  LRDM_OP_LAYER = 5,     /* end of a layer (checkpoint boundary); no arithmetic */
+  LRDM_OP_KRAUS2 = 6     /* two-qubit channel on (q0, q1) with m = k operators (4 x 4) at coef + off
+                            (as lrdm_apply_kraus2, plain form); the next operation must be
+                            LRDM_OP_COMPRESS */
 } lrdm_op_kind;
 
 typedef struct {
@@ -321,6 +338,24 @@ lrdm_status lrdm_fdm_apply_kraus(lrdm_fdm_t h, int qubit, int m, const double* e
  * 1e-10, else LRDM_E_ARG).  Queued operations are applied first; this one runs at once as its
  * own pass over rho.  Queued on the stream. */
 lrdm_status lrdm_fdm_apply_diagonal_weight(lrdm_fdm_t h, const double* phase);
+/* rho = L L^H (Eq. "low rank decomposition") into the full-rank handle f (same n, n <= 16),
+ * replacing its state and dropping its queued operations; L is h's factor after its pending
+ * work.  The switch to full density matrix evolution of Sec. II.C.  Orders the two handles'
+ * streams. */
+lrdm_status lrdm_to_full(lrdm_t h, lrdm_fdm_t f);
+
+/* Algorithm 1 with the switch of Sec. II.C: the program runs on h (from its current state) until
+ * a channel group whose intermediate rank V_I, V_I^3 = N (A V)^3 / M (A operators on M qubits, V
+ * the rank kept by the last compression, 1 before any), reaches 2^N; there the state goes to f
+ * (lrdm_to_full) and the remaining gates, phases and one-qubit channels run as full density
+ * matrix evolution on f (compressions no longer apply).  *switched_at = the index of that channel
+ * operation, or -1 (the result is then h's factor).  f may be NULL when n > 16 (V_I cannot reach
+ * 2^N there); programs with two-qubit channels after a possible switch are not supported
+ * (LRDM_E_UNSUPPORTED before anything runs).  Every compression synchronises (its kept rank
+ * decides the rule). */
+lrdm_status lrdm_run_switching(lrdm_t h, lrdm_fdm_t f, const lrdm_program* p, const double* params, int n_params,
+                               int* switched_at);
+
 /* Prob(x) = Re rho[x][x] into p_dev (2^n doubles, device).  Applies queued operations. */
 lrdm_status lrdm_fdm_probabilities(lrdm_fdm_t h, double* p_dev);
 /* Apply queued operations and wait for the stream. */

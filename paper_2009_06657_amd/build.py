@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblrdm.so")
-SOURCES = ["k_gate.hip", "k_gram.hip", "k_eig.hip", "k_proj.hip", "k_out.hip", "k_adj.hip", "k_fdm.hip", "k_chain.hip",
+SOURCES = ["k_gate.hip", "k_gram.hip", "k_eig.hip", "k_proj.hip", "k_out.hip", "k_adj.hip", "k_fdm.hip", "k_chain.hip", "k_bridge.hip",
            "runtime.cpp", "runtime_fdm.cpp", "runtime_program.cpp", "runtime_noalloc.cpp"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",

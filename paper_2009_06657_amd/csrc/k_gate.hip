@@ -462,6 +462,54 @@ hipError_t launch_kraus_expand(cx_t<T>* L, int n, int ld, int c, int q, const Ch
   return hipGetLastError();
 }
 
+// Plain-form expansion of a two-qubit channel (Sec. II.C) on (q0, q1): for the row quad x_b,
+// b = b(q0) + 2 b(q1), and column v < c, column a c + v of row x_b' becomes
+// sum_b E_a[b'][b] L[x_b][v] for the operators a0 <= a < a0 + na of this launch (a >= m: zero
+// padding).  Every launch reads columns 0 .. c - 1 and the launch holding a = 0, which
+// overwrites them, comes last; one thread owns one (quad, column) pair.
+template <class T>
+__global__ __launch_bounds__(256) void kraus2_expand_kernel(cx_t<T>* __restrict__ L, uint32_t quarter_rows, int ld,
+                                                            int c, int q0, int q1, Kraus2Chunk ck) {
+  using C = cx_t<T>;
+  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t y = (uint32_t)(gid / (uint64_t)c);
+  const int v = (int)(gid % (uint64_t)c);
+  if (y >= quarter_rows) return;
+  const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+  const uint32_t t = ((y >> lo) << (lo + 1)) | (y & ((1u << lo) - 1u));
+  const uint32_t x0 = ((t >> hi) << (hi + 1)) | (t & ((1u << hi) - 1u));
+  uint32_t xb[4];
+  C l[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    xb[b] = x0 | ((uint32_t)(b & 1) << q0) | ((uint32_t)(b >> 1) << q1);
+    l[b] = L[(size_t)xb[b] * ld + v];
+  }
+  for (int u = 0; u < ck.na; ++u) {
+    const int a = ck.a0 + u;
+#pragma unroll
+    for (int bp = 0; bp < 4; ++bp) {
+      C r = cmk<C, T>((T)0, (T)0);
+      if (a < ck.m) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          r = cadd(r, cmul(cmk<C, T>((T)ck.e[u][bp][b][0], (T)ck.e[u][bp][b][1]), l[b]));
+      }
+      L[(size_t)xb[bp] * ld + a * c + v] = r;
+    }
+  }
+}
+
+template <class T>
+hipError_t launch_kraus2_expand(cx_t<T>* L, int n, int ld, int c, int q0, int q1, const Kraus2Chunk& ck,
+                                hipStream_t s) {
+  if (n < 2 || c < 1) return hipErrorInvalidValue;
+  const uint64_t total = (uint64_t)(1u << (n - 2)) * (uint64_t)c;
+  const uint32_t blocks = (uint32_t)((total + 255) / 256);
+  hipLaunchKernelGGL(kraus2_expand_kernel<T>, dim3(blocks), dim3(256), 0, s, L, 1u << (n - 2), ld, c, q0, q1, ck);
+  return hipGetLastError();
+}
+
 template <class T>
 __global__ void set_e0_kernel(cx_t<T>* L) {
   L[0].x = (T)1;
@@ -516,6 +564,8 @@ hipError_t launch_stamp(uint64_t* slot, hipStream_t s) {
 
 template hipError_t launch_gate_pass_batched<float>(const GateJob<float>*, int, uint32_t, size_t, hipStream_t);
 template hipError_t launch_gate_pass_batched<double>(const GateJob<double>*, int, uint32_t, size_t, hipStream_t);
+template hipError_t launch_kraus2_expand<float>(float2*, int, int, int, int, int, const Kraus2Chunk&, hipStream_t);
+template hipError_t launch_kraus2_expand<double>(double2*, int, int, int, int, int, const Kraus2Chunk&, hipStream_t);
 template hipError_t launch_gate_pass<float>(const GatePass<float>&, float2*, hipStream_t);
 template hipError_t launch_gate_pass<double>(const GatePass<double>&, double2*, hipStream_t);
 template hipError_t launch_kraus_expand<float>(float2*, int, int, int, int, const Channel&, int, hipStream_t);

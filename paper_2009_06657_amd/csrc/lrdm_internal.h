@@ -162,6 +162,25 @@ template <class T>
 hipError_t launch_kraus_expand(cx_t<T>* L, int n, int ld, int c, int q, const Channel& ch,
                                int m_pad, hipStream_t s);
 
+// Operators [a0, a0 + na) of a two-qubit Kraus set (4 x 4, local index b(q0) + 2 b(q1)) for one
+// plain-form expansion launch; m is the set's size (slots a >= m are zero padding).
+constexpr int kKraus2PerLaunch = 8;
+struct Kraus2Chunk {
+  int a0, na, m;
+  double e[kKraus2PerLaunch][4][4][2];
+};
+template <class T>
+hipError_t launch_kraus2_expand(cx_t<T>* L, int n, int ld, int c, int q0, int q1, const Kraus2Chunk& ck,
+                                hipStream_t s);
+
+// Sparse initial state: L = 0 except L[idx[i] * ld] = amp[i] (interleaved FP64), i < count
+// (idx, amp in device memory).
+template <class T>
+hipError_t launch_set_sparse(cx_t<T>* L, int ld, const uint64_t* idx, const double* amp, int count, hipStream_t s);
+// rho = L L^H (rho row-major 2^n x 2^n complex64, the full-rank comparator's layout), FP64 sums.
+template <class T>
+hipError_t launch_lr_to_full(const cx_t<T>* L, int n, int ld, int ncols, float2* rho, hipStream_t s);
+
 template <class T>
 hipError_t launch_gram(const cx_t<T>* L, int n, int ld, int c, int nsplit, int q, T* partials,
                        int nblocks, hipStream_t s);
@@ -294,5 +313,9 @@ void set_last_error(const char* msg);   // the calling thread's last error (lrdm
 
 // the handles of a batch, in creation order
 const lrdm_t* batch_handles(lrdm_batch_t b, int* n);
+// the full-rank handle's state: rho, n and stream (after applying its queued operations)
+lrdm_status fdm_state(lrdm_fdm_t f, float2** rho, int* n, hipStream_t* s);
+// drop the full-rank handle's queued operations (its state is about to be replaced)
+void fdm_discard_queue(lrdm_fdm_t f);
 
 }  // namespace lrdm

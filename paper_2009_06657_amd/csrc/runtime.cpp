@@ -26,6 +26,7 @@ constexpr size_t kPauliPartDoubles = 4u << 20;
 constexpr int kZBlocks = 256;
 constexpr int kMaxTimed = 8192;
 constexpr int kMaxApplyTerms = 4096;
+constexpr int kMaxSparse = 32768;   // sparse initial state entries (staged in the terms region)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int next_pow2(int x) {
@@ -47,9 +48,12 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
                     std::string& why) {
   if (n < 1 || n > 30) { why = "n must be in [1, 30]"; return false; }
   if (r_max < 1 || r_max > 64) { why = "r_max must be in [1, 64]"; return false; }
-  if (m_max < 1 || m_max > 4) { why = "m_max must be in [1, 4]"; return false; }
-  if (dt != LRDM_C64 && dt != LRDM_C128) { why = "unknown dtype"; return false; }
   const bool plain = flags & LRDM_FLAG_PLAIN;
+  if (m_max < 1 || m_max > (plain ? 16 : 4)) {
+    why = plain ? "m_max must be in [1, 16] (plain form)" : "m_max must be in [1, 4] (fused form)";
+    return false;
+  }
+  if (dt != LRDM_C64 && dt != LRDM_C128) { why = "unknown dtype"; return false; }
   L.r_pad = std::max(8, next_pow2(r_max));
   L.m_pad = next_pow2(m_max);
   if (m_max * L.r_pad > kMaxEig) { why = "m_max * r_pad exceeds 128 (largest Gram order)"; return false; }
@@ -679,6 +683,13 @@ bool same_shape(lrdm_t a, lrdm_t b) {
          a->plain == b->plain && a->lay.ld == b->lay.ld;
 }
 
+// Work already queued on stream `other` finishes before h's stream runs what it queues next.
+lrdm_status order_streams_raw(hipStream_t mine, hipStream_t other) {
+  if (other != mine && hipStreamSynchronize(other) != hipSuccess)
+    return fail(nullptr, LRDM_E_HIP, "synchronising the other handle's stream failed");
+  return LRDM_OK;
+}
+
 // Order work on a's stream before work that b's stream enqueues next.
 lrdm_status order_streams(lrdm_t a, lrdm_t b) {
   if (a->stream != b->stream) HIPCHK(a, hipStreamSynchronize(a->stream));
@@ -783,8 +794,8 @@ lrdm_status lrdm_workspace_size(int n, int r_max, lrdm_dtype dt, int m_max, unsi
   Layout L;
   std::string why;
   if (!compute_layout(n, r_max, dt, m_max, flags, L, why)) {
-    const bool range = (n < 1 || n > 30 || r_max < 1 || r_max > 64 || m_max < 1 || m_max > 4 ||
-                        (dt != LRDM_C64 && dt != LRDM_C128));
+    const bool range = (n < 1 || n > 30 || r_max < 1 || r_max > 64 || m_max < 1 ||
+                        m_max > ((flags & LRDM_FLAG_PLAIN) ? 16 : 4) || (dt != LRDM_C64 && dt != LRDM_C128));
     return fail(nullptr, range ? LRDM_E_ARG : LRDM_E_UNSUPPORTED, why);
   }
   *state_bytes = L.state_bytes;
@@ -928,6 +939,119 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e) {
   h->chan_pending = true;
   h->chan_q = qubit;
   h->chan = ch;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_apply_kraus2(lrdm_t h, int q0, int q1, int m, const double* e) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  if (!h->plain)
+    return fail(h, LRDM_E_UNSUPPORTED, "two-qubit channels run in the plain form (LRDM_FLAG_PLAIN)");
+  if (q0 < 0 || q0 >= h->n || q1 < 0 || q1 >= h->n || q0 == q1)
+    return fail(h, LRDM_E_ARG, "qubits out of range or repeated");
+  if (m < 1 || m > h->m_max) return fail(h, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
+  if (!e) return fail(h, LRDM_E_ARG, "null Kraus matrices");
+  // completeness sum_a E_a^H E_a = I (4 x 4)
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double re = 0, im = 0;
+      for (int a = 0; a < m; ++a)
+        for (int r = 0; r < 4; ++r) {
+          const double ar = e[((a * 4 + r) * 4 + i) * 2], ai = -e[((a * 4 + r) * 4 + i) * 2 + 1];
+          const double br = e[((a * 4 + r) * 4 + j) * 2], bi = e[((a * 4 + r) * 4 + j) * 2 + 1];
+          re += ar * br - ai * bi;
+          im += ar * bi + ai * br;
+        }
+      if (!(std::fabs(re - (i == j)) <= 1e-10 && std::fabs(im) <= 1e-10))
+        return fail(h, LRDM_E_ARG, "Kraus set is not complete within 1e-10");
+    }
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is already pending: compress first");
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  const int c = h->ncols, m_pad = h->lay.m_pad;
+  // launches over operator blocks, the one holding a = 0 (which overwrites the input columns) last
+  std::vector<int> starts;
+  for (int a0 = kKraus2PerLaunch; a0 < m_pad; a0 += kKraus2PerLaunch) starts.push_back(a0);
+  starts.push_back(0);
+  for (int a0 : starts) {
+    Kraus2Chunk ck{};
+    ck.a0 = a0;
+    ck.na = std::min(kKraus2PerLaunch, m_pad - a0);
+    ck.m = m;
+    for (int u = 0; u < ck.na && a0 + u < m; ++u)
+      for (int r = 0; r < 4; ++r)
+        for (int cc = 0; cc < 4; ++cc)
+          for (int z = 0; z < 2; ++z) ck.e[u][r][cc][z] = e[(((a0 + u) * 4 + r) * 4 + cc) * 2 + z];
+    hipError_t he = h->dt == LRDM_C64
+                        ? launch_kraus2_expand<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, c, q0, q1, ck, h->stream)
+                        : launch_kraus2_expand<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, c, q0, q1, ck, h->stream);
+    HIPCHK(h, he);
+  }
+  h->ncols = c * m_pad;
+  h->c_bound = std::min(h->c_bound * m, h->ncols);
+  h->chan_pending = true;   // compress must follow
+  h->chan_q = q0;
+  h->chan = Channel{};
+  h->chan.m = m;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_set_sparse(lrdm_t h, int count, const uint64_t* idx, const double* amp) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  st = not_recording(h);
+  if (st != LRDM_OK) return st;
+  if (count < 1 || count > kMaxSparse) return fail(h, LRDM_E_ARG, "count must be in [1, 32768]");
+  if (!idx || !amp) return fail(h, LRDM_E_ARG, "null indices or amplitudes");
+  if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
+  const uint64_t rows = 1ull << h->n;
+  std::vector<uint64_t> sorted(idx, idx + count);
+  std::sort(sorted.begin(), sorted.end());
+  for (int i = 0; i < count; ++i) {
+    if (sorted[i] >= rows) return fail(h, LRDM_E_ARG, "basis index beyond 2^n");
+    if (i > 0 && sorted[i] == sorted[i - 1]) return fail(h, LRDM_E_ARG, "repeated basis index");
+  }
+  double nrm = 0;
+  for (int i = 0; i < count; ++i) nrm += amp[2 * i] * amp[2 * i] + amp[2 * i + 1] * amp[2 * i + 1];
+  if (!(std::fabs(nrm - 1.0) <= 1e-10)) return fail(h, LRDM_E_ARG, "amplitudes must have unit norm within 1e-10");
+  h->gates.clear();
+  h->proj_pending = false;
+  uint64_t* didx = h->ws<uint64_t>(h->lay.off_terms);
+  double* damp = reinterpret_cast<double*>(didx + kMaxSparse);
+  h->term_stage.assign(3 * (size_t)count, 0);
+  std::memcpy(h->term_stage.data(), idx, (size_t)count * 8);
+  std::memcpy(h->term_stage.data() + count, amp, (size_t)count * 16);
+  HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
+  HIPCHK(h, hipMemcpyAsync(didx, h->term_stage.data(), (size_t)count * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(damp, h->term_stage.data() + count, (size_t)count * 16, hipMemcpyHostToDevice, h->stream));
+  hipError_t he = h->dt == LRDM_C64
+                      ? launch_set_sparse<float>(static_cast<float2*>(h->state), h->lay.ld, didx, damp, count, h->stream)
+                      : launch_set_sparse<double>(static_cast<double2*>(h->state), h->lay.ld, didx, damp, count, h->stream);
+  HIPCHK(h, he);
+  HIPCHK(h, hipStreamSynchronize(h->stream));   // the staging vector is reused by later calls
+  h->ncols = h->lay.r_pad;
+  h->c_bound = 1;
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_to_full(lrdm_t h, lrdm_fdm_t f) {
+  lrdm_status st = ready_for_output(h);
+  if (st != LRDM_OK) return st;
+  float2* rho = nullptr;
+  int nf = 0;
+  hipStream_t fs = nullptr;
+  st = fdm_state(f, &rho, &nf, &fs);
+  if (st != LRDM_OK) return st;
+  if (nf != h->n) return fail(h, LRDM_E_ARG, "the full-rank handle has a different n");
+  fdm_discard_queue(f);
+  st = order_streams_raw(h->stream, fs);
+  if (st != LRDM_OK) return st;
+  hipError_t he = h->dt == LRDM_C64
+                      ? launch_lr_to_full<float>(static_cast<float2*>(h->state), h->n, h->lay.ld, h->ncols, rho, h->stream)
+                      : launch_lr_to_full<double>(static_cast<double2*>(h->state), h->n, h->lay.ld, h->ncols, rho, h->stream);
+  HIPCHK(h, he);
+  if (fs != h->stream) HIPCHK(h, hipStreamSynchronize(h->stream));
   return LRDM_OK;
 }
 

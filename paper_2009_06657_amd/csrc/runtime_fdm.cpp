@@ -521,3 +521,16 @@ lrdm_status lrdm_fdm_synchronize(lrdm_fdm_t h) {
 const char* lrdm_fdm_last_error(lrdm_fdm_t h) { return h ? h->err.c_str() : ""; }
 
 }  // extern "C"
+
+lrdm_status lrdm::fdm_state(lrdm_fdm_t f, float2** rho, int* n, hipStream_t* s) {
+  lrdm_status st = fusable(f);
+  if (st != LRDM_OK) return st;
+  *rho = f->rho;
+  *n = f->n;
+  *s = f->stream;
+  return LRDM_OK;
+}
+
+void lrdm::fdm_discard_queue(lrdm_fdm_t f) {
+  if (f) f->ops.clear();
+}

@@ -53,6 +53,7 @@ bool op_uses_coef(const lrdm_op& o, int n, int64_t& need) {
     case LRDM_OP_ROTATION: need = 8; return true;
     case LRDM_OP_WEIGHT: need = 2ll * (n + 1); return true;
     case LRDM_OP_KRAUS: need = 8ll * o.k; return true;
+    case LRDM_OP_KRAUS2: need = 32ll * o.k; return true;
     default: need = 0; return false;
   }
 }
@@ -66,7 +67,7 @@ lrdm_status validate(const lrdm_program* p, int n, const double* params, int n_p
     const lrdm_op& o = p->ops[i];
     const std::string at = "op " + std::to_string(i) + ": ";
     int64_t need = 0;
-    if (o.kind < LRDM_OP_GATE || o.kind > LRDM_OP_LAYER) return pfail(LRDM_E_ARG, at + "unknown kind");
+    if (o.kind < LRDM_OP_GATE || o.kind > LRDM_OP_KRAUS2) return pfail(LRDM_E_ARG, at + "unknown kind");
     if (op_uses_coef(o, n, need)) {
       if (!p->coef || o.off < 0 || o.off + need > p->n_coef)
         if (!(o.kind == LRDM_OP_ROTATION && params)) return pfail(LRDM_E_ARG, at + "coefficients out of range");
@@ -84,6 +85,13 @@ lrdm_status validate(const lrdm_program* p, int n, const double* params, int n_p
       if (o.k < 1 || o.k > 4) return pfail(LRDM_E_ARG, at + "channel operator count must be in [1, 4]");
       if (i + 1 >= p->n_ops || p->ops[i + 1].kind != LRDM_OP_COMPRESS)
         return pfail(LRDM_E_ARG, at + "a channel must be followed by a compression");
+    } else if (o.kind == LRDM_OP_KRAUS2) {
+      if (o.q0 < 0 || o.q0 >= n || o.q1 < 0 || o.q1 >= n || o.q0 == o.q1)
+        return pfail(LRDM_E_ARG, at + "channel qubits out of range or repeated");
+      if (o.k < 1 || o.k > 16) return pfail(LRDM_E_ARG, at + "two-qubit channel operator count must be in [1, 16]");
+      if (i + 1 >= p->n_ops || p->ops[i + 1].kind != LRDM_OP_COMPRESS)
+        return pfail(LRDM_E_ARG, at + "a channel must be followed by a compression");
+      if (need_channels) return pfail(LRDM_E_UNSUPPORTED, at + "the reverse sweep takes one-qubit channels only");
     } else if (o.kind == LRDM_OP_COMPRESS) {
       if (need_channels && (i == 0 || p->ops[i - 1].kind != LRDM_OP_KRAUS))
         return pfail(LRDM_E_UNSUPPORTED, at + "the reverse sweep needs a channel before every compression");
@@ -112,6 +120,7 @@ lrdm_status issue(lrdm_t h, const lrdm_program* p, const lrdm_op& o, const doubl
     }
     case LRDM_OP_WEIGHT: return lrdm_apply_diagonal_weight(h, p->coef + o.off);
     case LRDM_OP_KRAUS: return lrdm_apply_kraus(h, o.q0, o.k, p->coef + o.off);
+    case LRDM_OP_KRAUS2: return lrdm_apply_kraus2(h, o.q0, o.q1, o.k, p->coef + o.off);
     case LRDM_OP_COMPRESS:
       return rec_dev ? lrdm_compress_record(h, o.r, o.eps, o.tie, o.renorm, rec_dev, nullptr)
                      : lrdm_compress(h, o.r, o.eps, o.tie, o.renorm, nullptr);
@@ -172,15 +181,16 @@ bool values_ok(const lrdm_program* p, int n, const double* params, std::string& 
           why = "op " + std::to_string(i) + ": phase entries must have unit modulus";
           return false;
         }
-    } else if (o.kind == LRDM_OP_KRAUS) {
+    } else if (o.kind == LRDM_OP_KRAUS || o.kind == LRDM_OP_KRAUS2) {
       const double* e = p->coef + o.off;
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
+      const int d = o.kind == LRDM_OP_KRAUS ? 2 : 4;
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
           double re = 0, im = 0;
           for (int m = 0; m < o.k; ++m)
-            for (int r = 0; r < 2; ++r) {
-              const double xr = e[((m * 2 + r) * 2 + a) * 2], xi = -e[((m * 2 + r) * 2 + a) * 2 + 1];
-              const double yr = e[((m * 2 + r) * 2 + b) * 2], yi = e[((m * 2 + r) * 2 + b) * 2 + 1];
+            for (int r = 0; r < d; ++r) {
+              const double xr = e[((m * d + r) * d + a) * 2], xi = -e[((m * d + r) * d + a) * 2 + 1];
+              const double yr = e[((m * d + r) * d + b) * 2], yi = e[((m * d + r) * d + b) * 2 + 1];
               re += xr * yr - xi * yi;
               im += xr * yi + xi * yr;
             }
@@ -365,6 +375,67 @@ lrdm_status lrdm_run(lrdm_t h, const lrdm_program* p, const double* params, int 
     }
   }
   return LRDM_OK;
+}
+
+lrdm_status lrdm_run_switching(lrdm_t h, lrdm_fdm_t f, const lrdm_program* p, const double* params, int n_params,
+                               int* switched_at) {
+  Shape s;
+  lrdm_status st = shape_of(h, s);
+  if (st != LRDM_OK) return st;
+  if (!switched_at) return pfail(LRDM_E_ARG, "null switched_at");
+  st = validate(p, s.n, params, n_params, false);
+  if (st != LRDM_OK) return st;
+  std::string why;
+  if (!values_ok(p, s.n, params, why)) return pfail(LRDM_E_ARG, why);
+  if (s.n <= 16 && !f) return pfail(LRDM_E_ARG, "n <= 16 needs a full-rank handle for the switch");
+  if (s.n <= 16)
+    for (int i = 0; i < p->n_ops; ++i)
+      if (p->ops[i].kind == LRDM_OP_KRAUS2)
+        return pfail(LRDM_E_UNSUPPORTED, "op " + std::to_string(i) +
+                                             ": two-qubit channels cannot follow a switch to full rank");
+  *switched_at = -1;
+  const double two_n = std::ldexp(1.0, s.n);
+  // V: the column count of the factor as Algorithm 1 keeps it, min(r, A V, the kept rank); the
+  // device's reported rank alone can be larger while zero eigenvalues pad its Gram order
+  int V = 1, A_pend = 1;
+  bool full = false;
+  double tmp[8];
+  for (int i = 0; i < p->n_ops; ++i) {
+    const lrdm_op& o = p->ops[i];
+    if (!full && (o.kind == LRDM_OP_KRAUS || o.kind == LRDM_OP_KRAUS2)) {
+      const int M = o.kind == LRDM_OP_KRAUS ? 1 : 2;
+      const double VI = std::cbrt((double)s.n / M) * o.k * V;   // V_I^3 = N (A V)^3 / M
+      if (VI >= two_n) {
+        st = lrdm_to_full(h, f);
+        if (st != LRDM_OK) return st;
+        full = true;
+        *switched_at = i;
+      }
+    }
+    if (full) {
+      if (o.kind == LRDM_OP_GATE || o.kind == LRDM_OP_ROTATION) {
+        const int q[2] = {o.q0, o.q1};
+        st = lrdm_fdm_apply_gate(f, o.kind == LRDM_OP_GATE ? o.k : 1, q, op_matrix(p, o, params, tmp));
+      } else if (o.kind == LRDM_OP_WEIGHT) {
+        st = lrdm_fdm_apply_diagonal_weight(f, p->coef + o.off);
+      } else if (o.kind == LRDM_OP_KRAUS) {
+        st = lrdm_fdm_apply_kraus(f, o.q0, o.k, p->coef + o.off);
+      }
+      if (st != LRDM_OK) return st;
+      continue;
+    }
+    if (o.kind == LRDM_OP_COMPRESS) {
+      lrdm_compress_info info;
+      st = lrdm_compress(h, o.r, o.eps, o.tie, o.renorm, &info);
+      if (st != LRDM_OK) return st;
+      V = std::min(std::min(info.rank, A_pend * V), o.r);
+      continue;
+    }
+    if (o.kind == LRDM_OP_KRAUS || o.kind == LRDM_OP_KRAUS2) A_pend = o.k;
+    st = issue(h, p, o, params, nullptr);
+    if (st != LRDM_OK) return st;
+  }
+  return full ? lrdm_fdm_synchronize(f) : LRDM_OK;
 }
 
 lrdm_status lrdm_energy_grad_bytes(lrdm_t h, const lrdm_program* p, size_t* keep_all_bytes, size_t* min_bytes) {

@@ -31,9 +31,10 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_fdm_synchronize", "lrdm_fdm_last_error", "lrdm_batch_create", "lrdm_batch_begin",
            "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
            "lrdm_batch_times", "lrdm_batch_destroy", "lrdm_layout", "lrdm_run", "lrdm_energy_grad_bytes",
-           "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate", "lrdm_expect_z_noalloc"]
+           "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate", "lrdm_expect_z_noalloc",
+           "lrdm_apply_kraus2", "lrdm_set_sparse", "lrdm_to_full", "lrdm_run_switching"]
 
-OP_GATE, OP_ROTATION, OP_WEIGHT, OP_KRAUS, OP_COMPRESS, OP_LAYER = range(6)
+OP_GATE, OP_ROTATION, OP_WEIGHT, OP_KRAUS, OP_COMPRESS, OP_LAYER, OP_KRAUS2 = range(7)
 _AXIS = {"X": 1, "Y": 2, "Z": 3}
 
 
@@ -99,6 +100,8 @@ class FlatProgram:
             elif isinstance(op, Kraus):
                 ks = np.asarray(op.ops, dtype=np.complex128)
                 o.kind, o.k, o.q0, o.off = OP_KRAUS, ks.shape[0], int(op.qubit), put(ks)
+                if op.qubit2 >= 0:
+                    o.kind, o.q1 = OP_KRAUS2, int(op.qubit2)
             elif isinstance(op, Compress):
                 o.kind, o.r, o.eps, o.tie, o.renorm = OP_COMPRESS, int(op.r), float(op.eps), int(op.tie), int(op.renorm)
             elif isinstance(op, LayerEnd):
@@ -178,6 +181,10 @@ def load_library(path: str = LIB_PATH):
         "lrdm_batch_run": [P, ctypes.POINTER(ctypes.POINTER(CProgram)), P, P, P, SZ, ctypes.POINTER(SZ), dp, dp],
         "lrdm_program_validate": [ctypes.POINTER(CProgram), I, dp, I],
         "lrdm_expect_z_noalloc": [P, I, I, I, I, P, dp, dp, dp],
+        "lrdm_apply_kraus2": [P, I, I, I, dp],
+        "lrdm_set_sparse": [P, I, P, dp],
+        "lrdm_to_full": [P, P],
+        "lrdm_run_switching": [P, P, ctypes.POINTER(CProgram), dp, I, ctypes.POINTER(I)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -275,10 +282,34 @@ class LowRankDM:
         m = _cplx(phase)
         _check(self.lib.lrdm_apply_diagonal_weight(self.h, _dptr(m)), self.h)
 
-    def apply_kraus(self, qubit: int, ops):
+    def apply_kraus(self, qubit: int, ops, qubit2: int = -1):
+        """A one-qubit channel, or with qubit2 >= 0 a two-qubit channel (4 x 4 operators, local
+        index b(qubit) + 2 b(qubit2); plain form)."""
         ops = np.asarray(ops, dtype=np.complex128)
         m = _cplx(ops)
-        _check(self.lib.lrdm_apply_kraus(self.h, int(qubit), ops.shape[0], _dptr(m)), self.h)
+        if qubit2 >= 0:
+            _check(self.lib.lrdm_apply_kraus2(self.h, int(qubit), int(qubit2), ops.shape[0], _dptr(m)), self.h)
+        else:
+            _check(self.lib.lrdm_apply_kraus(self.h, int(qubit), ops.shape[0], _dptr(m)), self.h)
+
+    def set_sparse(self, idx, amp):
+        """L = sum_i amp[i] |idx[i]> (a sparse superposition initial state)."""
+        ix = np.ascontiguousarray(idx, dtype=np.uint64)
+        a = _cplx(np.asarray(amp, dtype=np.complex128))
+        _check(self.lib.lrdm_set_sparse(self.h, ix.shape[0], ix.ctypes.data, _dptr(a)), self.h)
+
+    def to_full(self, fdm: "FullRankDM"):
+        """fdm's rho <- L L^H."""
+        _check(self.lib.lrdm_to_full(self.h, fdm.h), self.h)
+
+    def run_switching(self, program, fdm: "Optional[FullRankDM]") -> int:
+        """lrdm_run_switching: the program with the switch to full density matrix evolution once
+        the intermediate rank reaches 2^n; returns the index of the switching channel or -1."""
+        fp = program if isinstance(program, FlatProgram) else FlatProgram(program)
+        at = ctypes.c_int(-2)
+        _check(self.lib.lrdm_run_switching(self.h, fdm.h if fdm is not None else None, fp.ref, None, 0,
+                                           ctypes.byref(at)), self.h)
+        return at.value
 
     def compress(self, r: int, eps: float = 0.0, tie: int = 0, renorm: int = 1,
                  info: bool = False) -> Optional[dict]:
@@ -588,13 +619,15 @@ def run_program(dm: LowRankDM, program, on_layer=None):
     """Issue every op of a workloads.circuits.Program through the C ABI, in order."""
     from workloads.circuits import Compress, DiagWeight, Gate, Kraus, LayerEnd
 
+    if getattr(program, "init", None) is not None:
+        dm.set_sparse(*program.init)
     for op in program.ops:
         if isinstance(op, Gate):
             dm.apply_gate(op.qubits, op.u)
         elif isinstance(op, DiagWeight):
             dm.apply_diagonal_weight(op.phase)
         elif isinstance(op, Kraus):
-            dm.apply_kraus(op.qubit, op.ops)
+            dm.apply_kraus(op.qubit, op.ops, op.qubit2)
         elif isinstance(op, Compress):
             dm.compress(op.r, op.eps, op.tie, op.renorm)
         elif isinstance(op, LayerEnd):

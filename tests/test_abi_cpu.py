@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     text = open(os.path.join(ROOT, "include", "lrdm.h")).read()
-    return sorted(set(re.findall(r"\b(lrdm_[A-Za-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lrdm_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,138 @@
+"""GPU parity of two-qubit channels and channel groups (Sec. II.C, plain form), sparse initial
+states (Sec. II.D) and the switch to full density matrix evolution (Sec. II.C, last paragraph)
+against the FP64 oracle: probabilities within 1e-5 (complex64) and 1e-10 (complex128)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.lret import run_lret_switching
+from workloads import circuits as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lr():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_06657_amd as lr
+
+    lr.load_library()
+    return lr
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("case", [("dep", 0.004, "", 8), ("ad", 0.02, "", 16), ("deph", 0.01, "zz", 32),
+                                  ("dep", 0.003, "dep2", 8)])
+def test_grouped_channels_plain_form(lr, dtype, case):
+    channel, p, two, r = case
+    if dtype == "c128" and r > 32:
+        pytest.skip("complex128 takes r_pad <= 32")
+    prog = C.grouped_brickwork_program(9, 3, r, channel, p, seed=41, dtype=dtype, two_qubit=two, tie=1)
+    if dtype == "c128" and prog.m_max * max(r, 8) > 64:
+        pytest.skip("the complex128 plain form keeps m_pad * r_pad <= 64 (FP64 GEMM width)")
+    _say(f"[groups] {dtype} {channel} x {channel} / {two or 'product'} r={r} m_max={prog.m_max}")
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64 if dtype == "c64" else lr.C128, prog.m_max, lr.FLAG_PLAIN)
+    lr.run_program(dm, prog)
+    P = dm.probabilities().cpu().numpy()
+    log = []
+    Pref = oracle.probabilities(oracle.run_lret(prog, log=log))
+    err = float(np.max(np.abs(P - Pref)))
+    _say(f"  max|dP| {err:.2e}  (oracle ranks {min(e['k'] for e in log)}..{max(e['k'] for e in log)})")
+    assert err <= (1e-5 if dtype == "c64" else 1e-10)
+    dm.close()
+
+
+def test_two_qubit_channel_needs_plain_form(lr):
+    dm = lr.LowRankDM(6, 8, lr.C64, 4)
+    with pytest.raises(lr.LrdmError) as e:
+        dm.apply_kraus(0, C.correlated_dephasing(0.1), 3)
+    assert e.value.status == 6
+    dm.close()
+    dm = lr.LowRankDM(6, 8, lr.C64, 4, lr.FLAG_PLAIN)
+    with pytest.raises(lr.LrdmError) as e:
+        dm.apply_kraus(0, np.stack([np.eye(4), np.eye(4)]), 3)   # incomplete
+    assert e.value.status == 1
+    with pytest.raises(lr.LrdmError) as e:
+        dm.apply_kraus(2, C.correlated_dephasing(0.1), 2)        # repeated qubit
+    assert e.value.status == 1
+    dm.close()
+
+
+@pytest.mark.parametrize("dtype,plain", [("c64", 0), ("c128", 0), ("c64", 1)])
+def test_sparse_initial_state(lr, dtype, plain):
+    n = 8
+    prog = C.cfg3_program(n=n, r=16, layers=2, dtype=dtype)
+    rng = np.random.default_rng(5)
+    idx = np.array([0, 7, 100, 255], dtype=np.uint64)
+    amp = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    prog.init = (idx, amp / np.linalg.norm(amp))
+    _say(f"[sparse] {dtype} plain={plain}")
+    dm = lr.LowRankDM(n, 16, lr.C64 if dtype == "c64" else lr.C128, prog.m_max, lr.FLAG_PLAIN if plain else 0)
+    lr.run_program(dm, prog)
+    P = dm.probabilities().cpu().numpy()
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    assert float(np.max(np.abs(P - Pref))) <= (1e-5 if dtype == "c64" else 1e-10)
+    # GHZ: <Z_i Z_{i+1}> = 1 before any noise
+    g = lr.LowRankDM(n, 8, lr.C64, 2)
+    g.set_sparse(*C.ghz_init(n))
+    z, zz, tr = g.expect_z()
+    assert np.max(np.abs(zz - 1.0)) < 1e-6 and np.max(np.abs(z)) < 1e-6 and abs(tr - 1) < 1e-6
+    with pytest.raises(lr.LrdmError):
+        g.set_sparse(np.array([1, 1], dtype=np.uint64), np.array([0.6, 0.8]))       # repeated index
+    with pytest.raises(lr.LrdmError):
+        g.set_sparse(np.array([1, 2], dtype=np.uint64), np.array([0.6, 0.7]))       # not unit norm
+    dm.close(); g.close()
+
+
+def test_to_full_equals_outer_product(lr):
+    n = 7
+    prog = C.cfg3_program(n=n, r=16, layers=2)
+    dm = lr.LowRankDM(n, 16, lr.C64, 2)
+    lr.run_program(dm, prog)
+    f = lr.FullRankDM(n)
+    dm.to_full(f)
+    L = dm.get_L()
+    rho = f.rho()
+    assert float(np.max(np.abs(rho - L @ L.conj().T))) < 1e-6
+    dm.close(); f.close()
+
+
+@pytest.mark.parametrize("n,r,layers", [(5, 8, 3), (6, 16, 3), (4, 4, 4)])
+def test_switch_to_full_rank(lr, n, r, layers):
+    """The switch happens at the oracle's channel and the result matches the oracle's run with the
+    switch (complex64 low rank up to the switch, complex64 full rank after it)."""
+    prog = C.cfg1_program(n=n, r=r, layers=layers, p=0.01, dtype="c64")
+    rho_ref, at_ref = run_lret_switching(prog)
+    _say(f"[switch] n={n} r={r}: oracle switches at op {at_ref}")
+    dm = lr.LowRankDM(n, r, lr.C64, prog.m_max)
+    f = lr.FullRankDM(n)
+    at = dm.run_switching(prog, f)
+    assert at == at_ref
+    if at >= 0:
+        P = f.probabilities().cpu().numpy()
+    else:
+        P = dm.probabilities().cpu().numpy()
+    err = float(np.max(np.abs(P - np.real(np.diag(rho_ref)))))
+    _say(f"  switched at {at}, max|dP| {err:.2e}")
+    assert err <= 1e-5
+    dm.close(); f.close()
+
+
+def test_no_switch_above_full_rank_size(lr):
+    """n = 17: V_I = (17)^(1/3) A V stays far below 2^17, so no full-rank handle is needed."""
+    prog = C.cfg3_program(n=17, r=16, layers=1)
+    dm = lr.LowRankDM(17, 16, lr.C64, prog.m_max)
+    assert dm.run_switching(prog, None) == -1
+    z, zz, tr = dm.expect_z()
+    assert abs(tr - 1) < 1e-5
+    dm.close()

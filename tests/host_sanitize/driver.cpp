@@ -227,6 +227,29 @@ static void exercise(int n, int r, lrdm_dtype dt, int m_max, unsigned flags) {
     }
     lrdm_destroy(bar);
   }
+  // sparse initial state, two-qubit channel (plain form), conversion to full rank
+  {
+    const uint64_t sidx[2] = {0, (1ull << n) - 1};
+    const double samp[4] = {std::sqrt(0.5), 0, 0, std::sqrt(0.5)};
+    EXPECT(lrdm_set_sparse(h, n >= 1 && sidx[1] != 0 ? 2 : 1, sidx, samp) == (sidx[1] != 0 ? LRDM_OK : LRDM_E_ARG));
+    if ((flags & LRDM_FLAG_PLAIN) && n >= 2) {
+      std::vector<double> e2(32 * m_max, 0.0);
+      const double w = 1.0 / std::sqrt((double)m_max);
+      for (int a = 0; a < m_max; ++a)
+        for (int i = 0; i < 4; ++i) e2[32 * a + 2 * (4 * i + i)] = w;
+      EXPECT(lrdm_apply_kraus2(h, 0, n - 1, m_max, e2.data()) == LRDM_OK);
+      EXPECT(lrdm_compress(h, rt, 0.0, 0, 1, nullptr) == LRDM_OK);
+    }
+    if (n <= 8) {
+      size_t fb = 0;
+      EXPECT(lrdm_fdm_state_bytes(n, &fb) == LRDM_OK);
+      DevBuf rho(fb);
+      lrdm_fdm_t f = nullptr;
+      EXPECT(lrdm_fdm_init(&f, n, rho.p, fb, nullptr) == LRDM_OK);
+      EXPECT(lrdm_to_full(h, f) == LRDM_OK);
+      lrdm_fdm_destroy(f);
+    }
+  }
   // argument checks
   const int bad[1] = {n};
   EXPECT(lrdm_apply_gate(h, 1, bad, u) == LRDM_E_ARG);

@@ -394,6 +394,31 @@ hipError_t launch_sample(const double* p, int n, double* cdf, double* block_sums
   return hipSuccess;
 }
 template <class T>
+hipError_t launch_kraus2_expand(cx_t<T>* L, int n, int ld, int c, int, int, const Kraus2Chunk& ck, hipStream_t) {
+  ++hs::launches;
+  if (ck.na < 1 || ck.na > kKraus2PerLaunch) {
+    ++hs::violations;
+    std::fprintf(stderr, "two-qubit expansion chunk out of range\n");
+  }
+  touch_L<T>(L, n, ld, (ck.a0 + ck.na) * c, "kraus2 expand L");
+  return hipSuccess;
+}
+template <class T>
+hipError_t launch_set_sparse(cx_t<T>* L, int ld, const uint64_t* idx, const double* amp, int count, hipStream_t) {
+  ++hs::launches;
+  touch(idx, (size_t)count * 8, "sparse idx");
+  touch(amp, (size_t)count * 16, "sparse amp");
+  for (int i = 0; i < count; ++i) touch(L + idx[i] * ld, sizeof(cx_t<T>), "sparse entry");
+  return hipSuccess;
+}
+template <class T>
+hipError_t launch_lr_to_full(const cx_t<T>* L, int n, int ld, int ncols, float2* rho, hipStream_t) {
+  ++hs::launches;
+  touch_L<T>(L, n, ld, ncols, "to_full L");
+  touch(rho, ((size_t)1 << (2 * n)) * 8, "to_full rho");
+  return hipSuccess;
+}
+template <class T>
 hipError_t launch_set_e0(cx_t<T>* L, hipStream_t) {
   touch(L, sizeof(cx_t<T>), "set e0");
   return hipSuccess;
@@ -423,7 +448,10 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t) {
   template hipError_t launch_gram_exact<T>(const cx_t<T>*, int, int, int, int, double*, double*, hipStream_t); \
   template hipError_t launch_compress_adjoint<T>(cx_t<T>*, const cx_t<T>*, int, int, int, int, const Channel&, \
                                                  const double*, const AdjBufs&, hipStream_t);                   \
-  template hipError_t launch_set_e0<T>(cx_t<T>*, hipStream_t);
+  template hipError_t launch_set_e0<T>(cx_t<T>*, hipStream_t);                                                   \
+  template hipError_t launch_kraus2_expand<T>(cx_t<T>*, int, int, int, int, int, const Kraus2Chunk&, hipStream_t);  \
+  template hipError_t launch_set_sparse<T>(cx_t<T>*, int, const uint64_t*, const double*, int, hipStream_t);       \
+  template hipError_t launch_lr_to_full<T>(const cx_t<T>*, int, int, int, float2*, hipStream_t);
 LRDM_STUB_INST(float)
 LRDM_STUB_INST(double)
 

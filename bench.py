@@ -25,7 +25,8 @@ METRIC = "noisy-circuit layers/s at n=20 r=64 vs full-rank DM, same GPU; %HBM pe
 FP32_MFMA_PEAK = 157.3e12
 FP64_PEAK = 78.6e12      # vector (and MFMA): 256 CUs x 2.4 GHz x 128 flop per CU and clock
 HBM_PEAK = 8.0e12
-CLASS_NAMES = {0: "gate_pass", 1: "gram", 2: "gram_reduce", 3: "eigensolve", 4: "projection", 5: "chain_small"}
+CLASS_NAMES = {0: "gate_pass", 1: "gram", 2: "gram_reduce", 3: "eigensolve", 4: "projection", 5: "small_fp64",
+               6: "gram_pair"}
 
 
 # Blocks of the projection matrix W (2 x 2 blocks of r x r, input value -> output value of the
@@ -46,6 +47,9 @@ def algorithmic_flops(n: int, r_pad: int, cls: int, m: int = 2, k: int = 64, blo
     rows, w = 2 ** (n - 1), 2 * r_pad
     if cls == 1:
         return 8.0 * rows * w * w / 2
+    if cls == 6:   # 4-way Gram of a bit pair: the two halves (split Grams over half the rows each,
+        # Hermitian) and the full cross block C = X_0^H X_1 over 2^(n-2) rows
+        return 2 * 8.0 * (rows / 2) * w * w / 2 + 8.0 * (rows / 2) * w * w
     if cls == 4:
         return 8.0 * rows * w * w * blocks / 4
     if cls == 3:
@@ -109,24 +113,15 @@ def measured_mfma(cls: int):
     return {"busy_frac": float(busy.group(1)), "mfma_flops_per_launch": float(flops.group(1))}
 
 
-def error_vs_oracle(dm, prog, zz, samples) -> dict:
-    """The step's outputs against the FP64 oracle's for the same circuit (tests/golden, written by
-    tests/golden/make_cfg3_golden.py from the oracle alone): <Z_i Z_{i+1}> and <Z_i>, Prob(x) at
-    8192 fixed indices (absolute and relative to the oracle's value), and the samples (those that
-    differ, and the largest distance of their uniform to a CDF step of the oracle's distribution)."""
-    path = os.path.join(ROOT, "tests", "golden", f"cfg3_n20_r64_l{prog.layers}.json")
-    if prog.n != 20 or prog.r != 64 or not os.path.exists(path):
-        return {"available": False, "reason": f"no oracle run stored for n={prog.n} r={prog.r} layers={prog.layers}"}
-    with open(path) as f:
-        g = json.load(f)
-    z, zz_now, _ = dm.expect_z()
+def _against_golden(g, path, dm, zz, samples) -> dict:
+    z, _, _ = dm.expect_z()
     P = dm.probabilities().cpu().numpy()
     idx = np.concatenate([np.array(g["prob_largest_idx"]), np.array(g["prob_random_idx"])])
     ref = np.concatenate([np.array(g["prob_largest"]), np.array(g["prob_random"])])
     dP = np.abs(P[idx] - ref)
     diff = np.nonzero(np.asarray(samples, dtype=np.uint64) != np.array(g["samples"], dtype=np.uint64))[0]
     margin = np.array(g["sample_margin"])
-    return {"available": True, "golden": os.path.relpath(path, ROOT),
+    return {"available": True, "golden": os.path.relpath(path, ROOT), "layers_compared": g.get("layers"),
             "zz": float(np.max(np.abs(np.asarray(zz) - np.array(g["zz"])))),
             "z": float(np.max(np.abs(z - np.array(g["z"])))),
             "prob_8192_fixed_idx": float(dP.max()),
@@ -134,6 +129,58 @@ def error_vs_oracle(dm, prog, zz, samples) -> dict:
             "trace": abs(float(np.sum(P)) - g["trace"]),
             "samples_differing": int(diff.size), "samples": int(len(samples)),
             "samples_differing_max_margin": float(margin[diff].max()) if diff.size else 0.0}
+
+
+def error_vs_oracle(dm, prog, zz, samples, flags, uniforms) -> dict:
+    """The step's outputs against the FP64 oracle's for the same circuit (tests/golden, written by
+    tests/golden/make_cfg3_golden.py from the oracle alone): <Z_i Z_{i+1}> and <Z_i>, Prob(x) at
+    8192 fixed indices (absolute and relative to the oracle's value), and the samples (those that
+    differ, and the largest distance of their uniform to a CDF step of the oracle's distribution).
+    Where no oracle run of the whole circuit is stored, the first four layers are run again with
+    the same flags and compared with the stored oracle run of those layers."""
+    import paper_2009_06657_amd as lr
+    from workloads import circuits as C
+
+    path = os.path.join(ROOT, "tests", "golden", f"cfg3_n20_r64_l{prog.layers}.json")
+    if prog.n != 20 or prog.r != 64:
+        return {"available": False, "reason": f"no oracle run stored for n={prog.n} r={prog.r}"}
+    if os.path.exists(path):
+        with open(path) as f:
+            g = json.load(f)
+        g.setdefault("layers", prog.layers)
+        return _against_golden(g, path, dm, zz, samples)
+    path4 = os.path.join(ROOT, "tests", "golden", "cfg3_n20_r64_l4.json")
+    if not os.path.exists(path4):
+        return {"available": False, "reason": f"no oracle run stored for n=20 r=64 layers={prog.layers} or 4"}
+    with open(path4) as f:
+        g = json.load(f)
+    g.setdefault("layers", 4)
+    prog4 = C.cfg3_program(layers=4)
+    dm4 = lr.LowRankDM(prog4.n, prog4.r, lr.C64, prog4.m_max, flags)
+    zz4, samples4, _ = run_step(dm4, prog4, uniforms)
+    out = _against_golden(g, path4, dm4, zz4, samples4)
+    out["note"] = f"no oracle run of all {prog.layers} layers stored: the first 4 layers, same flags"
+    dm4.close()
+    return out
+
+
+def unflagged_comparator(prog, uniforms, ms_overlap: float, steps: int = 2) -> dict:
+    """The same workload on one stream (no LRDM_FLAG_OVERLAP): every eigensolve waits for the
+    Gram pass before it and the projection waits for it."""
+    import torch
+
+    import paper_2009_06657_amd as lr
+
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max)
+    run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        zz, _, _ = run_step(dm, prog, uniforms)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    dm.close()
+    return {"layers_per_s": prog.layers * 1e3 / ms, "ms_per_step": ms, "overlap_speedup": ms / ms_overlap}
 
 
 def plain_comparator(prog, uniforms, ms_fused: float, steps: int = 2) -> dict:
@@ -559,6 +606,8 @@ def main():
                     help="skip the distortion of the fixed-rank workloads against the full-rank DM")
     ap.add_argument("--accuracy-only", action="store_true",
                     help="only run the distortion sweeps (random circuits, low rank vs full rank) and print them")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="time the single-stream path (no LRDM_FLAG_OVERLAP) as the headline")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -588,7 +637,9 @@ def main():
 
     prog = C.cfg3_program(layers=args.layers)
     uniforms = C.sample_uniforms(prog.meta["samples"], prog.meta["sample_seed"])
-    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, device="cuda:0")
+    # overlapped compressions: eigensolves on one XCD beside the passes over L on the others
+    flags = 0 if args.no_overlap else lr.FLAG_OVERLAP
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, flags, device="cuda:0")
 
     for _ in range(args.warmup):
         run_step(dm, prog, uniforms)
@@ -603,9 +654,9 @@ def main():
     elapsed = time.perf_counter() - t0
 
     # per-class kernel times: one further step per class, every launch of that class bracketed
-    # by HIP events on the handle's stream
+    # by HIP events on the stream it runs on
     br = {}
-    for cls in (() if args.no_breakdown else (0, 1, 2, 3, 4, 5)):
+    for cls in (() if args.no_breakdown else (0, 1, 2, 3, 4, 5, 6)):
         dm.timing_begin(cls)
         run_step(dm, prog, uniforms)
         n_, m_, t_ = dm.timing_end()
@@ -615,7 +666,7 @@ def main():
                           "ms_per_step": 1e3 * elapsed / args.steps, "profiling_run": True}), flush=True)
         return
     # the dominant kernel class: the most time per step
-    dominant = max((0, 1, 3, 4), key=lambda c: br[c][2])
+    dominant = max((0, 1, 3, 4, 6), key=lambda c: br[c][2])
 
     layers = args.layers * args.steps
     ms_per_step = 1e3 * elapsed / args.steps
@@ -657,16 +708,22 @@ def main():
         "config": {"workload": "random brickwork, amplitude damping + dephasing per qubit per layer, "
                                "compress after every channel, <ZZ> + 1e4 samples",
                    "n": prog.n, "r": prog.r, "layers": args.layers, "compressions_per_step": prog.n_compress(),
-                   "eigensolve": "f64", "trace_after": tr},
+                   "eigensolve": "f64", "trace_after": tr,
+                   "overlap": "eigensolves on one XCD's CUs beside the Gram and projection passes on the other "
+                              "seven; split Gram of the next qubit from the 4-way Gram of the bit pair"
+                              if flags else "off"},
         "roofline": roof_of(dominant),
         "roofline_projection": roof_of(4),
         "roofline_gram": roof_of(1),
+        "roofline_gram_pair": roof_of(6) if br.get(6, (0,))[0] else None,
         "roofline_gate_pass": roof_of(0),
         "roofline_eigensolve": roof_of(3),
         "breakdown_one_step": {CLASS_NAMES[c]: {"launches": br[c][0], "mean_ms": br[c][1], "total_ms": br[c][2]}
                                for c in br},
     }
-    out["max_abs_err_vs_oracle"] = error_vs_oracle(dm, prog, zz, samples)
+    out["max_abs_err_vs_oracle"] = error_vs_oracle(dm, prog, zz, samples, flags, uniforms)
+    if flags:
+        out["without_overlap"] = unflagged_comparator(prog, uniforms, ms_per_step)
     if not args.no_plain:
         out["vs_plain_low_rank"] = plain_comparator(prog, uniforms, ms_per_step)
     if not args.no_grad:

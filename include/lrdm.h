@@ -54,6 +54,16 @@ typedef enum { LRDM_C64 = 0, LRDM_C128 = 1 } lrdm_dtype;
 #define LRDM_FLAG_PLAIN 0x1u   /* plain low-rank form: apply_kraus materialises [E_1 L | ... | E_m L]
                                   (Eq. "low rank evolution K") and compress diagonalises its full
                                   (m r) x (m r) Gram matrix; the default fuses both (see lrdm_compress) */
+#define LRDM_FLAG_OVERLAP 0x2u /* fused form only: eigensolves run on a second stream that the handle
+                                  creates (default priority), beside the projections and Gram passes on
+                                  the caller's stream.  A channel on qubit q that follows a compression
+                                  on qubit p != q takes its split Gram matrix from the 4-way Gram of the
+                                  bit pair (p, q), formed before the projection on p, transformed by that
+                                  projection's W in FP64 (S_bb' = sum_c W_c^H G4_bb' W_c; Sec. II.B, the
+                                  Gram of the projected factor), so the eigensolve of q needs no pass
+                                  over the projected factor and overlaps the projection on p.  Same
+                                  method, different rounding order; every call keeps its contract
+                                  (outputs wait for both streams). */
 
 /* Per-compression record (Sec. II.B). */
 typedef struct {
@@ -170,9 +180,11 @@ lrdm_status lrdm_synchronize(lrdm_t h);
 
 /* Kernel timing for performance reports.  kernel_class: 0 = gate sweep, 1 = Gram pass over L,
  * 2 = Gram reduction, 3 = eigensolver (all stages), 4 = projection, 5 = the small FP64 products
- * of chained compressions (the second Gram matrix W^H S W and the composed W).  Between lrdm_timing_begin and
- * lrdm_timing_end every launch of that class is bracketed by HIP events on the handle's
- * stream; lrdm_timing_end synchronises and returns the number of launches and their mean
+ * of chained compressions (the second Gram matrix W^H S W and the composed W) and, with
+ * LRDM_FLAG_OVERLAP, of the pair transform, 6 = the 4-way Gram of a bit pair (LRDM_FLAG_OVERLAP:
+ * its two passes over L and their reduction).  Between lrdm_timing_begin and
+ * lrdm_timing_end every launch of that class is bracketed by HIP events on the stream it runs
+ * on; lrdm_timing_end synchronises and returns the number of launches and their mean
  * duration in milliseconds.  At most 65536 launches are recorded. */
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class);
 lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* total_ms);

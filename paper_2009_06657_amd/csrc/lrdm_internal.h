@@ -225,6 +225,21 @@ hipError_t launch_chain_gram(double* S, const double* W, double* tmp, int n, hip
 template <class T>
 hipError_t launch_chain_compose(double* Wp, const double* Wn, double* tmp, cx_t<T>* Wt, int n, hipStream_t s);
 
+// ---------------------------------------------------------------- overlapped compressions
+// 4-way Gram G4 (4c x 4c complex FP64, row-major, index (bit q, bit p, column)) of the factor on
+// the bit pair (p, q): the halves with bit q = 0 and 1 (split Gram on p; partials part_h, 2
+// gram4_blocks_halves(n) blocks of the upper tiles of width 4c) and the cross block (partials
+// part_c, gram4_blocks_cross(n) blocks of every tile), reduced in a fixed order in FP64.
+// max_blocks: the CUs the stream may use (at most that many work-groups per pass).
+template <class T>
+hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T* part_h, T* part_c, double* S4,
+                        int max_blocks, hipStream_t s);
+int gram4_blocks_halves(int n);
+int gram4_blocks_cross(int n);
+// Split Gram on q (2c x 2c, written to S) of the factor after the projection W (2c x 2c, FP64)
+// on p, from G4 taken before that projection; T: 3 (2c)^2 complex FP64 scratch.
+hipError_t launch_pair_transform(const double* G4, const double* W, double* T, double* S, int c, hipStream_t s);
+
 // ---------------------------------------------------------------- full-rank comparator (k_fdm.hip)
 constexpr int kFdmLowBits = 5;     // index bits 0..4 are local in every pass (256-byte runs)
 constexpr int kFdmMaxLocal = 13;   // 2^13 complex64 = 64 KB tile

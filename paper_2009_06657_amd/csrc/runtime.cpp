@@ -42,6 +42,11 @@ struct Layout {
   bool adjoint;        // reverse sweep available (fused form, m_max * r_pad <= 64)
   size_t off_adj, rec_bytes;
   size_t off_chain;    // fused form: W of the pending projection, the next W (FP64) and scratch
+  // overlapped compressions (LRDM_FLAG_OVERLAP): a second W slot in the bulk precision (the
+  // chain region then holds a fourth block, FP64 W of slot 1), two G4 slots, the FP64 scratch
+  // of the pair transform and the partials of the 4-way Gram
+  bool overlap;
+  size_t off_W2, off_S4, off_T4, off_part4;
 };
 
 bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
@@ -58,6 +63,9 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   L.m_pad = next_pow2(m_max);
   if (m_max * L.r_pad > kMaxEig) { why = "m_max * r_pad exceeds 128 (largest Gram order)"; return false; }
   if (dt == LRDM_C128 && L.r_pad > 32) { why = "complex128 supports r_pad <= 32"; return false; }
+  L.overlap = flags & LRDM_FLAG_OVERLAP;
+  if (L.overlap && plain) { why = "LRDM_FLAG_OVERLAP applies to the fused form"; return false; }
+  if (L.overlap && n < 2) { why = "LRDM_FLAG_OVERLAP needs n >= 2"; return false; }
   L.ld = plain ? L.m_pad * L.r_pad : L.r_pad;
   if (plain && 2 * L.ld > (dt == LRDM_C64 ? 256 : 128)) { why = "plain form exceeds the GEMM width"; return false; }
   L.F_max = std::max(4 * L.r_pad, 2 * L.ld);
@@ -91,7 +99,17 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   const int N_rec = m_max * L.r_pad;
   L.adjoint = !plain && N_rec <= kRecMaxN;
   L.off_adj = L.adjoint ? take(adj_doubles(L.r_pad, N_rec) * 8) : 0;
-  L.off_chain = plain ? 0 : take((size_t)3 * (2 * L.r_pad) * (2 * L.r_pad) * 16);
+  L.off_chain = plain ? 0 : take((size_t)(L.overlap ? 4 : 3) * (2 * L.r_pad) * (2 * L.r_pad) * 16);
+  L.off_W2 = L.off_S4 = L.off_T4 = L.off_part4 = 0;
+  if (L.overlap) {
+    const size_t c4 = 4 * (size_t)L.r_pad, c2 = 2 * (size_t)L.r_pad;
+    const size_t nt = c4 / 16;   // 16-wide real tiles across one half (4c reals)
+    const size_t nup = nt * (nt + 1) / 2;
+    L.off_W2 = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
+    L.off_S4 = take(2 * c4 * c4 * 16);
+    L.off_T4 = take(3 * c2 * c2 * 16);
+    L.off_part4 = take(((size_t)2 * gram4_blocks_halves(n) * nup + (size_t)gram4_blocks_cross(n) * nt * nt) * 256 * rs);
+  }
   L.rec_bytes = L.adjoint ? align_up(record_doubles(N_rec) * 8) : 0;
   L.total = o;
   return true;
@@ -160,8 +178,29 @@ struct lrdm_ctx {
   int pend_q = -1;
   bool last_w_next = false;   // the last compression's own W is in the "next" buffer (chained)
   int pend_skip = 0;          // zero blocks of the pending projection's W (see reach_skip)
+  // overlapped compressions: the passes over L of a compression (Gram, 4-way Gram, projection)
+  // run on gemm, the eigensolves and their small FP64 products on aux, two streams of the handle
+  // on disjoint sets of CUs (an eigensolve work-group then never waits for, nor shares a CU
+  // with, the GEMMs).  ev_a2g orders gemm after the caller's stream, ev_g2b aux after gemm (S or
+  // G4 ready), ev_b2g gemm (or the caller's stream) after aux (W ready, aux done with the
+  // eigensolver buffers), ev_g2a the caller's stream after gemm.  wslot is the W slot of the
+  // pending projection, s4slot the next G4 slot.
+  bool overlap = false;
+  hipStream_t aux = nullptr, gemm = nullptr;
+  hipEvent_t ev_a2g = nullptr, ev_g2b = nullptr, ev_b2g = nullptr, ev_g2a = nullptr;
+  int wslot = 0;
+  int s4slot = 0;
+  int gemm_cus = 256;   // CUs the gemm stream may use
+  // the caller's stream may hold work that gemm has not been ordered after (set wherever the
+  // caller's stream is joined to the handle's streams, which precedes all work queued there)
+  bool main_dirty = true;
 
   template <class P> P* ws(size_t off) { return reinterpret_cast<P*>(work + off); }
+  // W of slot s in the bulk precision and in FP64 (the chain region: slot 0, the next W, scratch,
+  // slot 1)
+  template <class T> cx_t<T>* w_bulk(int s) { return ws<cx_t<T>>(s ? lay.off_W2 : lay.off_W); }
+  double* chain_block(int i) { return ws<double>(lay.off_chain) + (size_t)i * 2 * (2 * lay.r_pad) * (2 * lay.r_pad); }
+  double* wp64(int s) { return chain_block(s ? 3 : 0); }
 };
 
 namespace {
@@ -193,6 +232,10 @@ lrdm_status check_usable(lrdm_t h) {
 // Sync the stream and check the device-side eigensolver status.
 lrdm_status sync_and_check(lrdm_t h) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->overlap) {
+    HIPCHK(h, hipStreamSynchronize(h->gemm));
+    HIPCHK(h, hipStreamSynchronize(h->aux));
+  }
   DevInfo info;
   HIPCHK(h, hipMemcpy(&info, h->ws<DevInfo>(h->lay.off_info), sizeof(info), hipMemcpyDeviceToHost));
   if (info.status != 0) {
@@ -202,14 +245,84 @@ lrdm_status sync_and_check(lrdm_t h) {
   return LRDM_OK;
 }
 
-void timed_begin(lrdm_t h, int cls) {
+void timed_begin(lrdm_t h, int cls, hipStream_t s = nullptr) {
   if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
-  hipEventRecord(h->ev[h->ev_used], h->stream);
+  hipEventRecord(h->ev[h->ev_used], s ? s : h->stream);
 }
-void timed_end(lrdm_t h, int cls) {
+void timed_end(lrdm_t h, int cls, hipStream_t s = nullptr) {
   if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
-  hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+  hipEventRecord(h->ev[h->ev_used + 1], s ? s : h->stream);
   h->ev_used += 2;
+}
+
+// Overlap mode: work the caller's stream queues next runs after everything queued on the
+// handle's two streams so far.
+lrdm_status join_aux(lrdm_t h) {
+  if (!h->overlap) return LRDM_OK;
+  h->main_dirty = true;
+  HIPCHK(h, hipEventRecord(h->ev_g2a, h->gemm));
+  HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_g2a, 0));
+  HIPCHK(h, hipStreamWaitEvent(h->stream, h->ev_b2g, 0));
+  return LRDM_OK;
+}
+// The overlap mode's two streams (default priority): aux on the CUs of one XCD (the last 32 bits
+// of the CU mask on this part: 8 XCDs of 32 CUs), gemm on the others.  Measured on the brickwork
+// n = 20, r = 64 run: the eigensolver's kernels hand their data from one to the next through
+// that XCD's L2, and no CU pair is shared between the two streams (a CU pair shares its
+// instruction and scalar caches: aux CUs spread over the XCDs ran both the eigensolve and the
+// GEMMs twice as slowly); the GEMM work-groups spread over the 7 remaining XCDs, whereas 16 aux
+// CUs taken out of one XCD left that XCD a second round of every GEMM grid.  Where the runtime
+// refuses a CU mask, both become ordinary streams (the results are the same; only the CU
+// sharing differs).
+#ifndef LRDM_AUX_CUS
+#define LRDM_AUX_CUS 32
+#endif
+constexpr int kAuxCUs = LRDM_AUX_CUS;
+bool aux_cu(int i, int ncu) { return i >= ncu - kAuxCUs; }
+hipError_t create_overlap_streams(lrdm_t h) {
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (ncu > 2 * kAuxCUs && ncu <= 1024) {
+    const int words = (ncu + 31) / 32;
+    std::vector<uint32_t> mg(words, 0), mb(words, 0);
+    for (int i = 0; i < ncu; ++i) (aux_cu(i, ncu) ? mb : mg)[i / 32] |= 1u << (i % 32);
+    if (hipExtStreamCreateWithCUMask(&h->gemm, (uint32_t)words, mg.data()) == hipSuccess &&
+        hipExtStreamCreateWithCUMask(&h->aux, (uint32_t)words, mb.data()) == hipSuccess) {
+      h->gemm_cus = ncu - kAuxCUs;
+      return hipSuccess;
+    }
+    if (h->gemm) hipStreamDestroy(h->gemm);
+    h->gemm = nullptr;
+    (void)hipGetLastError();
+  }
+  h->gemm_cus = std::max(2, std::min(ncu, 256));
+  e = hipStreamCreateWithFlags(&h->gemm, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+  return e;
+}
+// work already queued on the handle's streams finishes before they and the events go
+void release_overlap(lrdm_t h) {
+  if (h->gemm) hipStreamSynchronize(h->gemm);
+  if (h->aux) hipStreamSynchronize(h->aux);
+  for (hipEvent_t* e : {&h->ev_a2g, &h->ev_g2b, &h->ev_b2g, &h->ev_g2a})
+    if (*e) hipEventDestroy(*e);
+  if (h->gemm) hipStreamDestroy(h->gemm);
+  if (h->aux) hipStreamDestroy(h->aux);
+  h->gemm = h->aux = nullptr;
+}
+
+// Overlap mode: work the gemm stream queues next runs after everything on the caller's stream.
+// Only when the caller's stream has new work: the handle's CU-masked streams are blocking
+// streams, so a marker on the legacy default stream would also wait for all their work and
+// stall the pipeline between consecutive compressions.
+lrdm_status enter_gemm(lrdm_t h) {
+  if (!h->main_dirty) return LRDM_OK;
+  HIPCHK(h, hipEventRecord(h->ev_a2g, h->stream));
+  HIPCHK(h, hipStreamWaitEvent(h->gemm, h->ev_a2g, 0));
+  h->main_dirty = false;
+  return LRDM_OK;
 }
 
 bool is_unitary(const double* u, int d) {
@@ -457,18 +570,24 @@ Reach skip_reach(int skip) {
 // compression.
 template <class T>
 lrdm_status settle_t(lrdm_t h) {
-  if (!h->proj_pending) return LRDM_OK;
-  h->proj_pending = false;
-  const int c = h->lay.r_pad;
-  timed_begin(h, 4);
-  HIPCHK(h, launch_project<T>(static_cast<cx_t<T>*>(h->state), h->n, h->lay.ld, c, 2, h->pend_q, c,
-                              h->ws<cx_t<T>>(h->lay.off_W), h->pend_skip, h->stream));
-  timed_end(h, 4);
-  return LRDM_OK;
+  if (h->proj_pending) {
+    h->proj_pending = false;
+    const int c = h->lay.r_pad;
+    hipStream_t gs = h->stream;
+    if (h->overlap) {   // on gemm, once W is ready (the caller's stream has nothing newer for it)
+      gs = h->gemm;
+      HIPCHK(h, hipStreamWaitEvent(gs, h->ev_b2g, 0));
+    }
+    timed_begin(h, 4, gs);
+    HIPCHK(h, launch_project<T>(static_cast<cx_t<T>*>(h->state), h->n, h->lay.ld, c, 2, h->pend_q, c,
+                                h->w_bulk<T>(h->wslot), h->pend_skip, gs));
+    timed_end(h, 4, gs);
+  }
+  return join_aux(h);   // overlap mode: the caller's stream after both of the handle's streams
 }
 
 lrdm_status settle(lrdm_t h) {
-  if (!h->proj_pending) return LRDM_OK;
+  if (!h->proj_pending && !h->overlap) return LRDM_OK;
   return h->dt == LRDM_C64 ? settle_t<float>(h) : settle_t<double>(h);
 }
 
@@ -566,47 +685,89 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   // chained compression: the previous one (same qubit) left its projection pending, so S of
   // the factor it would produce is W^H S W and the two projections compose
   const bool chain = !rec && nsplit == 2 && h->proj_pending && h->pend_q == q;
-  if (!chain) {
+  // overlap mode: a channel on another qubit takes its S from the 4-way Gram of the bit pair,
+  // and every fused eigensolve runs on aux
+  const bool pipe = h->overlap && !rec && nsplit == 2 && h->proj_pending && h->pend_q != q;
+  const bool on_aux = h->overlap && !rec && nsplit == 2;
+  hipStream_t es = on_aux ? h->aux : h->stream;    // eigensolve
+  hipStream_t gs = on_aux ? h->gemm : h->stream;   // passes over L
+  if (!chain && !pipe) {
     lrdm_status st = settle_t<T>(h);
     if (st != LRDM_OK) return st;
   }
-  double* Wp64 = h->ws<double>(h->lay.off_chain);          // W of the pending projection
-  double* Wn64 = Wp64 + 2 * (size_t)Fc * Fc;                // W of this compression
-  double* tmp64 = Wn64 + 2 * (size_t)Fc * Fc;
+  if (on_aux && !chain) {
+    lrdm_status st = enter_gemm(h);   // gates and other work on the caller's stream come first
+    if (st != LRDM_OK) return st;
+  }
+  double* Wn64 = h->chain_block(1);   // W of this compression when chained
+  double* tmp64 = h->chain_block(2);
+  int slot = h->wslot;                // W slot this compression's (pending) projection uses
   if (rec) {
     // recorded compressions (reverse sweep) form S exactly from the bulk-precision factor
     HIPCHK(h, launch_gram_exact<T>(L, h->n, h->lay.ld, c, q, adj_bufs(h).part, b.S, h->stream));
   } else if (chain) {
     // S holds the Gram matrix of the split view before the previous compression; transform it
     // by that compression's own W (not the composed product)
-    timed_begin(h, 5);
-    HIPCHK(h, launch_chain_gram(b.S, h->last_w_next ? Wn64 : Wp64, tmp64, Fc, h->stream));
-    timed_end(h, 5);
+    timed_begin(h, 5, es);
+    HIPCHK(h, launch_chain_gram(b.S, h->last_w_next ? Wn64 : h->wp64(slot), tmp64, Fc, es));
+    timed_end(h, 5, es);
+  } else if (pipe) {
+    const int p = h->pend_q;
+    double* S4 = h->ws<double>(h->lay.off_S4) + (size_t)h->s4slot * 2 * (4 * c) * (4 * c);
+    T* part_h = h->ws<T>(h->lay.off_part4);
+    T* part_c = part_h + (size_t)2 * gram4_blocks_halves(h->n) * ((c / 4) * (c / 4 + 1) / 2) * 256;
+    // the 4-way Gram of (p, q) on the factor before the projection on p ...
+    timed_begin(h, 6, gs);
+    HIPCHK(h, launch_gram4<T>(L, h->n, h->lay.ld, c, p, q, part_h, part_c, S4, h->gemm_cus, gs));
+    timed_end(h, 6, gs);
+    HIPCHK(h, hipEventRecord(h->ev_g2b, gs));
+    // ... then that projection, once its W is ready
+    HIPCHK(h, hipStreamWaitEvent(gs, h->ev_b2g, 0));
+    timed_begin(h, 4, gs);
+    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, 2, p, c, h->w_bulk<T>(h->wslot), h->pend_skip, gs));
+    timed_end(h, 4, gs);
+    h->proj_pending = false;
+    // aux: the split Gram on q of the projected factor, from G4 and the projection's FP64 W
+    HIPCHK(h, hipStreamWaitEvent(h->aux, h->ev_g2b, 0));
+    timed_begin(h, 5, h->aux);
+    HIPCHK(h, launch_pair_transform(S4, h->wp64(h->wslot), h->ws<double>(h->lay.off_T4), b.S, c, h->aux));
+    timed_end(h, 5, h->aux);
+    h->s4slot ^= 1;
+    slot = h->wslot ^ 1;
   } else {
-    timed_begin(h, 1);
-    HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nb, h->stream));
-    timed_end(h, 1);
-    timed_begin(h, 2);
-    HIPCHK(h, launch_gram_reduce<T>(part, nb, F, b.S, h->stream));
-    timed_end(h, 2);
+    const int nbg = on_aux ? std::min(nb, h->gemm_cus) : nb;   // one round on the gemm stream's CUs
+    timed_begin(h, 1, gs);
+    HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nbg, gs));
+    timed_end(h, 1, gs);
+    timed_begin(h, 2, gs);
+    HIPCHK(h, launch_gram_reduce<T>(part, nbg, F, b.S, gs));
+    timed_end(h, 2, gs);
+    if (on_aux) {
+      HIPCHK(h, hipEventRecord(h->ev_g2b, gs));
+      HIPCHK(h, hipStreamWaitEvent(h->aux, h->ev_g2b, 0));
+      slot = h->wslot ^ 1;   // nothing is pending: either slot is free
+    }
   }
   const bool defer = !rec && nsplit == 2;   // fused compressions defer their projection
-  if (defer) b.W64 = chain ? Wn64 : Wp64;
-  timed_begin(h, 3);
+  if (defer) b.W64 = chain ? Wn64 : h->wp64(slot);
+  W = h->w_bulk<T>(slot);
+  timed_begin(h, 3, es);
   HIPCHK(h, launch_eig<T>(b.S, Fc, ch, nsplit, c, N, kmax, r_target, eps, tie, renorm, c_out, b,
-                          W, h->stream));
-  timed_end(h, 3);
+                          W, es));
+  timed_end(h, 3, es);
   if (chain) {
-    timed_begin(h, 5);
-    HIPCHK(h, launch_chain_compose<T>(Wp64, Wn64, tmp64, W, Fc, h->stream));
-    timed_end(h, 5);
+    timed_begin(h, 5, es);
+    HIPCHK(h, launch_chain_compose<T>(h->wp64(slot), Wn64, tmp64, W, Fc, es));
+    timed_end(h, 5, es);
   }
+  if (on_aux) HIPCHK(h, hipEventRecord(h->ev_b2g, h->aux));
   if (defer) {
     const Reach here = channel_reach(ch);
     h->pend_skip = reach_skip(chain ? compose_reach(skip_reach(h->pend_skip), here) : here);
     h->proj_pending = true;
     h->pend_q = q;
     h->last_w_next = chain;
+    h->wslot = slot;
   } else {
     timed_begin(h, 4);
     HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W,
@@ -640,6 +801,8 @@ lrdm_status reset_t(lrdm_t h) {
     h->chan_pending = false;
     return LRDM_OK;
   }
+  lrdm_status st = join_aux(h);   // a dropped pending compression may still run on aux
+  if (st != LRDM_OK) return st;
   HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
   HIPCHK(h, hipMemsetAsync(h->ws<DevInfo>(h->lay.off_info), 0, sizeof(DevInfo), h->stream));
   HIPCHK(h, launch_set_e0<T>(static_cast<cx_t<T>*>(h->state), h->stream));
@@ -827,10 +990,25 @@ lrdm_status lrdm_init(lrdm_t* out, int n, int r_max, lrdm_dtype dt, int m_max, u
   h->state = state_dev;
   h->work = static_cast<char*>(work_dev);
   h->stream = static_cast<hipStream_t>(hip_stream);
+  h->overlap = L.overlap;
+  if (h->overlap) {
+    hipError_t e = create_overlap_streams(h);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_a2g, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_g2b, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_b2g, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_g2a, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_b2g, h->aux);
+    if (e != hipSuccess) {
+      const std::string msg = std::string("creating the handle's streams: ") + hipGetErrorString(e);
+      release_overlap(h);
+      delete h;
+      return fail(nullptr, LRDM_E_HIP, msg);
+    }
+  }
   lrdm_status st = dt == LRDM_C64 ? reset_t<float>(h) : reset_t<double>(h);
   if (st != LRDM_OK) {
     g_last_error = h->err;
-    delete h;
+    lrdm_destroy(h);
     return st;
   }
   *out = h;
@@ -855,6 +1033,7 @@ lrdm_status lrdm_reset(lrdm_t h) {
 lrdm_status lrdm_destroy(lrdm_t h) {
   if (!h) return fail(nullptr, LRDM_E_ARG, "null handle");
   for (hipEvent_t e : h->ev) hipEventDestroy(e);
+  if (h->overlap) release_overlap(h);
   delete h;
   return LRDM_OK;
 }
@@ -1016,6 +1195,8 @@ lrdm_status lrdm_set_sparse(lrdm_t h, int count, const uint64_t* idx, const doub
   if (!(std::fabs(nrm - 1.0) <= 1e-10)) return fail(h, LRDM_E_ARG, "amplitudes must have unit norm within 1e-10");
   h->gates.clear();
   h->proj_pending = false;
+  st = join_aux(h);
+  if (st != LRDM_OK) return st;
   uint64_t* didx = h->ws<uint64_t>(h->lay.off_terms);
   double* damp = reinterpret_cast<double*>(didx + kMaxSparse);
   h->term_stage.assign(3 * (size_t)count, 0);
@@ -1184,6 +1365,8 @@ lrdm_status lrdm_set_L(lrdm_t h, const void* src, int from_host, int rank) {
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
   h->gates.clear();
   h->proj_pending = false;
+  st = join_aux(h);
+  if (st != LRDM_OK) return st;
   const size_t cs = (h->dt == LRDM_C64) ? 8 : 16;
   const size_t rows = 1ull << h->n;
   HIPCHK(h, hipMemsetAsync(h->state, 0, h->lay.state_bytes, h->stream));
@@ -1213,7 +1396,7 @@ lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {
   if (st != LRDM_OK) return st;
   st = not_recording(h);
   if (st != LRDM_OK) return st;
-  if (kernel_class < 0 || kernel_class > 5) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 5]");
+  if (kernel_class < 0 || kernel_class > 6) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 6]");
   if (h->ev.empty()) {
     h->ev.resize(2 * kMaxTimed);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
@@ -1227,6 +1410,10 @@ lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* to
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (h->overlap) {
+    HIPCHK(h, hipStreamSynchronize(h->gemm));
+    HIPCHK(h, hipStreamSynchronize(h->aux));
+  }
   double tot = 0;
   const int nl = h->ev_used / 2;
   for (int i = 0; i < nl; ++i) {
@@ -1272,6 +1459,8 @@ lrdm_status lrdm_restore(lrdm_t h, const void* src_dev, int rank) {
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is pending: call lrdm_compress first");
   h->gates.clear();
   h->proj_pending = false;
+  st = join_aux(h);
+  if (st != LRDM_OK) return st;
   HIPCHK(h, hipMemcpyAsync(h->state, src_dev, h->lay.state_bytes, hipMemcpyDeviceToDevice, h->stream));
   h->ncols = h->lay.r_pad;
   h->c_bound = rank;
@@ -1295,6 +1484,8 @@ lrdm_status lrdm_apply_pauli_sum(lrdm_t dst, lrdm_t src, int n_terms, const uint
   if (dst->chan_pending) return fail(dst, LRDM_E_STATE, "a Kraus channel is pending on the destination");
   dst->gates.clear();
   dst->proj_pending = false;
+  st = join_aux(dst);   // the destination's own streams are done with its state
+  if (st != LRDM_OK) return st;
   st = order_streams(src, dst);
   if (st != LRDM_OK) return st;
   std::vector<uint64_t> stage(3 * (size_t)n_terms);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblrdm.so")
 
 C64, C128 = 0, 1
 FLAG_PLAIN = 0x1
+FLAG_OVERLAP = 0x2
 STATUS = {0: "LRDM_OK", 1: "LRDM_E_ARG", 2: "LRDM_E_NOMEM", 3: "LRDM_E_HIP", 4: "LRDM_E_EIG",
           5: "LRDM_E_STATE", 6: "LRDM_E_UNSUPPORTED"}
 SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lrdm_apply_gate",

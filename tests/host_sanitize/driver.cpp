@@ -257,7 +257,7 @@ static void exercise(int n, int r, lrdm_dtype dt, int m_max, unsigned flags) {
   EXPECT(lrdm_compress(h, 1, 1.0, 0, 1, nullptr) == LRDM_E_ARG);
   EXPECT(lrdm_sample(h, 0, un.data(), smp.data()) == LRDM_E_ARG);
   EXPECT(lrdm_set_L(h, host.data(), 1, rp + 1) == LRDM_E_ARG);
-  EXPECT(lrdm_timing_begin(h, 6) == LRDM_E_ARG);
+  EXPECT(lrdm_timing_begin(h, 7) == LRDM_E_ARG);
   lrdm_destroy(h);
 }
 
@@ -346,7 +346,7 @@ int main() {
     for (int r : {1, 3, 8, 13, 16, 24, 32, 40, 64})
       for (int m : {1, 2, 4})
         for (lrdm_dtype dt : {LRDM_C64, LRDM_C128})
-          for (unsigned fl : {0u, LRDM_FLAG_PLAIN}) exercise(n, r, dt, m, fl);
+          for (unsigned fl : {0u, LRDM_FLAG_PLAIN, LRDM_FLAG_OVERLAP}) exercise(n, r, dt, m, fl);
   for (int n : {1, 2, 3, 5, 7}) exercise_fdm(n);
   exercise_batch();
   // entry points with no handle

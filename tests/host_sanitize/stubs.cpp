@@ -74,6 +74,12 @@ hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
   *s = reinterpret_cast<hipStream_t>(new char[8]);
   return hipSuccess;
 }
+hipError_t hipExtStreamCreateWithCUMask(hipStream_t* s, uint32_t words, const uint32_t* mask) {
+  if (words == 0 || !mask) return hipErrorInvalidValue;
+  volatile uint32_t last = mask[words - 1];   // the mask array is read whole
+  (void)last;
+  return hipStreamCreateWithFlags(s, 0);
+}
 hipError_t hipStreamDestroy(hipStream_t s) {
   delete[] reinterpret_cast<char*>(s);
   return hipSuccess;
@@ -94,6 +100,7 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) {
   return hipSuccess;
 }
 const char* hipGetErrorString(hipError_t) { return "host stub"; }
+hipError_t hipGetLastError(void) { return hipSuccess; }
 hipError_t hipGetDevice(int* d) {
   *d = 0;
   return hipSuccess;
@@ -305,6 +312,37 @@ hipError_t launch_pauli(const cx_t<T>* bra, const cx_t<T>* ket, int n, int ld, i
   touch(out, (size_t)n_terms * (complex_out ? 2 : 1) * 8, "pauli out");
   return hipSuccess;
 }
+int gram4_blocks_halves(int n) {
+  const uint64_t chunks = ((1ull << (n - 2)) + 63) / 64;
+  return (int)(chunks < 128 ? chunks : 128);
+}
+int gram4_blocks_cross(int n) {
+  const uint64_t chunks = ((1ull << (n - 2)) + 31) / 32;
+  return (int)(chunks < 256 ? chunks : 256);
+}
+template <class T>
+hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T* part_h, T* part_c, double* S4,
+                        int, hipStream_t) {
+  ++hs::launches;
+  if (p == q || p < 0 || q < 0 || p >= n || q >= n) {
+    ++hs::violations;
+    std::fprintf(stderr, "4-way Gram on bits %d, %d of %d qubits\n", p, q, n);
+  }
+  touch_L<T>(L, n, ld, c, "gram4 L");
+  const size_t nt = (size_t)(4 * c) / 16;
+  touch(part_h, (size_t)2 * gram4_blocks_halves(n) * (nt * (nt + 1) / 2) * 256 * sizeof(T), "gram4 halves partials");
+  touch(part_c, (size_t)gram4_blocks_cross(n) * nt * nt * 256 * sizeof(T), "gram4 cross partials");
+  touch(S4, (size_t)(4 * c) * (4 * c) * 16, "gram4 S4");
+  return hipSuccess;
+}
+hipError_t launch_pair_transform(const double* G4, const double* W, double* T, double* S, int c, hipStream_t) {
+  ++hs::launches;
+  touch(G4, (size_t)(4 * c) * (4 * c) * 16, "pair G4");
+  touch(W, (size_t)(2 * c) * (2 * c) * 16, "pair W");
+  touch(T, (size_t)3 * (2 * c) * (2 * c) * 16, "pair T");
+  touch(S, (size_t)(2 * c) * (2 * c) * 16, "pair S");
+  return hipSuccess;
+}
 hipError_t launch_chain_gram(double* S, const double* W, double* tmp, int n, hipStream_t) {
   ++hs::launches;
   touch(S, (size_t)n * n * 16, "chain S");
@@ -451,7 +489,8 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t) {
   template hipError_t launch_set_e0<T>(cx_t<T>*, hipStream_t);                                                   \
   template hipError_t launch_kraus2_expand<T>(cx_t<T>*, int, int, int, int, int, const Kraus2Chunk&, hipStream_t);  \
   template hipError_t launch_set_sparse<T>(cx_t<T>*, int, const uint64_t*, const double*, int, hipStream_t);       \
-  template hipError_t launch_lr_to_full<T>(const cx_t<T>*, int, int, int, float2*, hipStream_t);
+  template hipError_t launch_lr_to_full<T>(const cx_t<T>*, int, int, int, float2*, hipStream_t);                 \
+  template hipError_t launch_gram4<T>(const cx_t<T>*, int, int, int, int, int, T*, T*, double*, int, hipStream_t);
 LRDM_STUB_INST(float)
 LRDM_STUB_INST(double)
 

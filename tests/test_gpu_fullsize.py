@@ -77,12 +77,16 @@ def _golden(name):
         return json.load(f)
 
 
+@pytest.mark.parametrize("overlap", [0, 1])
 @pytest.mark.parametrize("layers", [1, 4])
-def test_brickwork_n20_r64_against_oracle(lr, layers):
+def test_brickwork_n20_r64_against_oracle(lr, layers, overlap):
+    """Also with LRDM_FLAG_OVERLAP (the split Gram of the next qubit from the 4-way Gram of the
+    bit pair, eigensolves on a second stream), the configuration the benchmark times."""
     g = _golden(f"cfg3_n20_r64_l{layers}.json")
     prog = C.cfg3_program(layers=layers)
-    _say(f"[n20] brickwork n=20 r=64 layers={layers} ({prog.n_compress()} compressions)")
-    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max)
+    flags = lr.FLAG_OVERLAP if overlap else 0
+    _say(f"[n20] brickwork n=20 r=64 layers={layers} ({prog.n_compress()} compressions) overlap={overlap}")
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, flags)
     comps, per_layer = run_with_log(lr, dm, prog)
     # ranks and discarded mass of every compression
     k_gpu = np.array([c["rank"] for c in comps])
@@ -121,7 +125,7 @@ def test_brickwork_n20_r64_against_oracle(lr, layers):
     assert np.all(dl <= 1e-3 * pl + 1e-10) and np.all(dr <= 1e-3 * pr + 1e-10)
     assert np.all(margin[mism] < 1e-7)
     # the benchmark issues the same ops without per-compression info: identical results
-    dm2 = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max)
+    dm2 = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, flags)
     lr.run_program(dm2, prog)
     z2, zz2, _ = dm2.expect_z()
     assert np.array_equal(zz2, per_layer[-1][1]) and np.array_equal(z2, per_layer[-1][0])

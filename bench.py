@@ -59,7 +59,7 @@ def algorithmic_flops(n: int, r_pad: int, cls: int, m: int = 2, k: int = 64, blo
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "all_kernels_brickwork_n20_r64_hbm_counters.md")
-CLASS_SOURCE = {0: "k_gate.hip", 1: "k_gram.hip", 3: "k_eig.hip", 4: "k_proj.hip"}
+CLASS_SOURCE = {0: "k_gate.hip", 1: "k_gram.hip", 3: "k_eig.hip", 4: "k_proj.hip", 6: "k_gram.hip"}
 
 
 def measured_traffic(cls: int):

@@ -130,6 +130,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2009_06657_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded (loaded before
+    # torch, it would start a second runtime in the process, which finds no device for the
+    # handle's own streams)
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     P, I, D, U, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)

@@ -568,8 +568,11 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
     // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1).  (A chunked LDS staging of S was slower.)
     z64 A[BR][BC];
     {
+      // split view: S has halves of c columns; G's copies take the first cw = N / m of them, a
+      // power of two (the factor's later columns are zero while its rank is still growing)
       const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
-      const int cs = __ffs(c) - 1;
+      const int cw = (nsplit == 2) ? N / m : c;
+      const int cs = __ffs(cw) - 1;
   #pragma unroll
       for (int a = 0; a < BR; ++a) {
         const int i = R + NH * a;
@@ -581,8 +584,8 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   #pragma unroll
           for (int uv = 0; uv < 4; ++uv) {
             size_t off;
-            if (nsplit == 2) {   // c is a power of two in the split view
-              off = (size_t)((uv >> 1) * c + (i & (c - 1))) * Fc + ((uv & 1) * c + (j & (c - 1)));
+            if (nsplit == 2) {   // c and cw are powers of two in the split view
+              off = (size_t)((uv >> 1) * c + (i & (cw - 1))) * Fc + ((uv & 1) * c + (j & (cw - 1)));
             } else {
               off = (size_t)i * Fc + j;
             }
@@ -1120,14 +1123,15 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
   if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
     const int cs = __ffs(c) - 1;   // c is a power of two in the split view
+    const int cw = N / ch.m;       // columns of each copy in G (rows v >= cw of W are zero)
     for (int rw = lane; rw < rows; rw += 64) {
       const int b = rw >> cs, v = rw & (c - 1);
 #pragma unroll
       for (int bp = 0; bp < 2; ++bp) {
         z64 acc = zmk(0, 0);
-        if (col < k) {
+        if (col < k && v < cw) {
           for (int a = 0; a < ch.m; ++a)
-            acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), Vs[wave][a * c + v]));
+            acc = zadd(acc, zmul(zmk(ch.e[a][bp][b][0], ch.e[a][bp][b][1]), Vs[wave][a * cw + v]));
         }
         const int e = rw * cols + bp * c_out + col;
         C o;

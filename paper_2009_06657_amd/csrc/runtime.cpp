@@ -600,7 +600,11 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   if (nsplit == 2) {
     ch = h->chan;
     c = h->lay.r_pad;
-    N = ch.m * c;
+    // while the rank grows the factor's columns from c_bound on are zero: G is formed over the
+    // first cw columns of each copy (a power of two >= 8), the zero eigenvalues of the rest left
+    // out (the rank rule does not depend on them); the reverse sweep's records keep the full order
+    const int cw = rec ? c : std::min(c, std::max(8, next_pow2(h->c_bound)));
+    N = ch.m * cw;
     F = 4 * c;
   } else {
     ch.m = 1;

@@ -77,6 +77,34 @@ def _golden(name):
         return json.load(f)
 
 
+def test_gate_layer_n20_elementwise(lr):
+    """One brickwork gate layer at the benchmark's size (n = 20, r = 64: 20 Haar SU(2) gates and
+    10 CZ, the fused register-phase passes the benchmark times) against the oracle's column-wise
+    gate contraction, element by element, from a seeded complex64 factor: relative 1e-6 of the
+    largest entry (FP32 rounding over 30 gates is ~3e-7)."""
+    from oracle.linalg import apply_gate
+
+    prog = C.cfg3_program(layers=1)
+    gates = [op for op in prog.ops if isinstance(op, C.Gate)]
+    rng = np.random.default_rng(2020)
+    L0 = (rng.standard_normal((2 ** 20, 64)) + 1j * rng.standard_normal((2 ** 20, 64))).astype(np.complex64)
+    L0 /= np.linalg.norm(L0)
+    _say(f"[n20 gates] {len(gates)} gates on 2^20 x 64")
+    dm = lr.LowRankDM(20, 64, lr.C64, prog.m_max)
+    dm.set_L(L0)
+    for g in gates:
+        dm.apply_gate(g.qubits, g.u)
+    got = dm.get_L()[:, :64]
+    dm.close()
+    ref = L0.astype(np.complex128)
+    for g in gates:
+        ref = apply_gate(ref, 20, g.qubits, g.u)
+    err = float(np.max(np.abs(got - ref)))
+    scale = float(np.max(np.abs(ref)))
+    _say(f"  max|dL| {err:.2e} (largest entry {scale:.2e})")
+    assert err <= 1e-6 * scale
+
+
 @pytest.mark.parametrize("overlap", [0, 1])
 @pytest.mark.parametrize("layers", [1, 4])
 def test_brickwork_n20_r64_against_oracle(lr, layers, overlap):

@@ -606,6 +606,8 @@ def main():
                     help="skip the distortion of the fixed-rank workloads against the full-rank DM")
     ap.add_argument("--accuracy-only", action="store_true",
                     help="only run the distortion sweeps (random circuits, low rank vs full rank) and print them")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="the library's default launch shapes instead of the autotuner's table")
     ap.add_argument("--no-overlap", action="store_true",
                     help="time the single-stream path (no LRDM_FLAG_OVERLAP) as the headline")
     ap.add_argument("--copy-calib", action="store_true",
@@ -639,7 +641,8 @@ def main():
     uniforms = C.sample_uniforms(prog.meta["samples"], prog.meta["sample_seed"])
     # overlapped compressions: eigensolves on one XCD beside the passes over L on the others
     flags = 0 if args.no_overlap else lr.FLAG_OVERLAP
-    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, flags, device="cuda:0")
+    dm = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, flags, device="cuda:0",
+                      tuning=None if args.no_tuning else "table")
 
     for _ in range(args.warmup):
         run_step(dm, prog, uniforms)
@@ -711,7 +714,10 @@ def main():
                    "eigensolve": "f64", "trace_after": tr,
                    "overlap": "eigensolves on one XCD's CUs beside the Gram and projection passes on the other "
                               "seven; split Gram of the next qubit from the 4-way Gram of the bit pair"
-                              if flags else "off"},
+                              if flags else "off",
+                   "tuning": {"applied": dm.tuning, "in_use": dm.get_tuning(),
+                              "source": "paper_2009_06657_amd/tuning_table.json (autotune.py)" if dm.tuning
+                              else "library defaults"}},
         "roofline": roof_of(dominant),
         "roofline_projection": roof_of(4),
         "roofline_gram": roof_of(1),

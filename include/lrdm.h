@@ -187,6 +187,28 @@ lrdm_status lrdm_synchronize(lrdm_t h);
  * on; lrdm_timing_end synchronises and returns the number of launches and their mean
  * duration in milliseconds.  At most 65536 launches are recorded. */
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class);
+
+/* Launch shapes the autotuner (paper_2009_06657_amd/autotune.py) chooses per workload; they
+ * change where work-groups split the rows, never the operations, so results move only by
+ * rounding order.  0 in a field keeps the default.
+ *   gram_blocks:    split-K work-groups of a Gram pass over L, 1..256 (default: one per CU of
+ *                   the stream, at most 256, fewer when L has fewer 64-row chunks)
+ *   gram4_blocks:   work-groups of each pass of the 4-way Gram (LRDM_FLAG_OVERLAP), 2..256
+ *                   (default: one per CU of its stream)
+ *   gate_local_max: local qubits of a fused gate pass, 1..8 (default: as many as a 64 KB tile
+ *                   holds)
+ *   aux_cus:        LRDM_FLAG_OVERLAP: CUs of the eigensolver stream, a multiple of 32 (whole XCDs)
+ *                   below the device's CU count (default 32)
+ * lrdm_set_tuning orders the change after the work already queued; LRDM_E_ARG on a value out of
+ * range (nothing changes then). */
+typedef struct {
+  int gram_blocks;
+  int gram4_blocks;
+  int gate_local_max;
+  int aux_cus;
+} lrdm_tuning;
+lrdm_status lrdm_set_tuning(lrdm_t h, const lrdm_tuning* t);
+lrdm_status lrdm_get_tuning(lrdm_t h, lrdm_tuning* t);   /* the values in use (defaults resolved) */
 lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* total_ms);
 
 /* ---------------------------------------------------------------- reverse sweep (gradients)

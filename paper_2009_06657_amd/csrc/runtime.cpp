@@ -191,6 +191,9 @@ struct lrdm_ctx {
   int wslot = 0;
   int s4slot = 0;
   int gemm_cus = 256;   // CUs the gemm stream may use
+  int ncu = 256;        // CUs of the device
+  lrdm_tuning tune{};   // autotuned launch shapes (0 = default)
+  int aux_cus = 0;      // CUs of the aux stream (overlap mode)
   // the caller's stream may hold work that gemm has not been ordered after (set wherever the
   // caller's stream is joined to the handle's streams, which precedes all work queued there)
   bool main_dirty = true;
@@ -274,23 +277,22 @@ lrdm_status join_aux(lrdm_t h) {
 // CUs taken out of one XCD left that XCD a second round of every GEMM grid.  Where the runtime
 // refuses a CU mask, both become ordinary streams (the results are the same; only the CU
 // sharing differs).
-#ifndef LRDM_AUX_CUS
-#define LRDM_AUX_CUS 32
-#endif
-constexpr int kAuxCUs = LRDM_AUX_CUS;
-bool aux_cu(int i, int ncu) { return i >= ncu - kAuxCUs; }
+constexpr int kAuxCUs = 32;
 hipError_t create_overlap_streams(lrdm_t h) {
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  if (ncu > 2 * kAuxCUs && ncu <= 1024) {
+  h->ncu = ncu;
+  const int aux = h->tune.aux_cus ? h->tune.aux_cus : kAuxCUs;
+  if (ncu > aux && ncu - aux >= 32 && ncu <= 1024) {
     const int words = (ncu + 31) / 32;
     std::vector<uint32_t> mg(words, 0), mb(words, 0);
-    for (int i = 0; i < ncu; ++i) (aux_cu(i, ncu) ? mb : mg)[i / 32] |= 1u << (i % 32);
+    for (int i = 0; i < ncu; ++i) (i >= ncu - aux ? mb : mg)[i / 32] |= 1u << (i % 32);
     if (hipExtStreamCreateWithCUMask(&h->gemm, (uint32_t)words, mg.data()) == hipSuccess &&
         hipExtStreamCreateWithCUMask(&h->aux, (uint32_t)words, mb.data()) == hipSuccess) {
-      h->gemm_cus = ncu - kAuxCUs;
+      h->gemm_cus = ncu - aux;
+      h->aux_cus = aux;
       return hipSuccess;
     }
     if (h->gemm) hipStreamDestroy(h->gemm);
@@ -298,6 +300,7 @@ hipError_t create_overlap_streams(lrdm_t h) {
     (void)hipGetLastError();
   }
   h->gemm_cus = std::max(2, std::min(ncu, 256));
+  h->aux_cus = 0;
   e = hipStreamCreateWithFlags(&h->gemm, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
   return e;
@@ -411,7 +414,8 @@ void build_phases(GatePass<T>& p) {
 
 template <class T>
 lrdm_status flush_gates_t(lrdm_t h) {
-  const int kloc_max = local_budget(h->n, h->ncols, sizeof(cx_t<T>));
+  int kloc_max = local_budget(h->n, h->ncols, sizeof(cx_t<T>));
+  if (h->tune.gate_local_max) kloc_max = std::min(kloc_max, h->tune.gate_local_max);
   std::vector<char> placed(h->gates.size(), 0);
   size_t remaining = h->gates.size();
   while (remaining > 0) {
@@ -722,7 +726,8 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     T* part_c = part_h + (size_t)2 * gram4_blocks_halves(h->n) * ((c / 4) * (c / 4 + 1) / 2) * 256;
     // the 4-way Gram of (p, q) on the factor before the projection on p ...
     timed_begin(h, 6, gs);
-    HIPCHK(h, launch_gram4<T>(L, h->n, h->lay.ld, c, p, q, part_h, part_c, S4, h->gemm_cus, gs));
+    HIPCHK(h, launch_gram4<T>(L, h->n, h->lay.ld, c, p, q, part_h, part_c, S4,
+                              h->tune.gram4_blocks ? h->tune.gram4_blocks : h->gemm_cus, gs));
     timed_end(h, 6, gs);
     HIPCHK(h, hipEventRecord(h->ev_g2b, gs));
     // ... then that projection, once its W is ready
@@ -739,7 +744,8 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     h->s4slot ^= 1;
     slot = h->wslot ^ 1;
   } else {
-    const int nbg = on_aux ? std::min(nb, h->gemm_cus) : nb;   // one round on the gemm stream's CUs
+    int nbg = on_aux ? std::min(nb, h->gemm_cus) : nb;   // one round on the gemm stream's CUs
+    if (h->tune.gram_blocks) nbg = std::min(nb, h->tune.gram_blocks);
     timed_begin(h, 1, gs);
     HIPCHK(h, launch_gram<T>(L, h->n, h->lay.ld, c, nsplit, q, part, nbg, gs));
     timed_end(h, 1, gs);
@@ -1393,6 +1399,53 @@ lrdm_status lrdm_synchronize(lrdm_t h) {
   st = flush_gates(h);
   if (st != LRDM_OK) return st;
   return sync_and_check(h);
+}
+
+lrdm_status lrdm_set_tuning(lrdm_t h, const lrdm_tuning* t) {
+  lrdm_status st = check_usable(h);
+  if (st != LRDM_OK) return st;
+  st = not_recording(h);
+  if (st != LRDM_OK) return st;
+  if (!t) return fail(h, LRDM_E_ARG, "null tuning");
+  if (t->gram_blocks < 0 || t->gram_blocks > 256) return fail(h, LRDM_E_ARG, "gram_blocks must be in [0, 256]");
+  if (t->gram4_blocks < 0 || t->gram4_blocks == 1 || t->gram4_blocks > 256)
+    return fail(h, LRDM_E_ARG, "gram4_blocks must be 0 or in [2, 256]");
+  if (t->gate_local_max < 0 || t->gate_local_max > 8) return fail(h, LRDM_E_ARG, "gate_local_max must be in [0, 8]");
+  if (t->aux_cus < 0 || t->aux_cus % 32 != 0) return fail(h, LRDM_E_ARG, "aux_cus must be 0 or a multiple of 32");
+  if (t->aux_cus && (!h->overlap || t->aux_cus > h->ncu - 32))
+    return fail(h, LRDM_E_ARG, "aux_cus needs LRDM_FLAG_OVERLAP and leaves at least 32 CUs to the GEMMs");
+  // the launch shapes take effect from the next launch; queued gates keep their passes
+  st = flush_gates(h);
+  if (st != LRDM_OK) return st;
+  const int aux_old = h->tune.aux_cus;
+  h->tune = *t;
+  if (h->overlap && t->aux_cus != aux_old) {
+    // new CU split: pending work settles, then the two streams are made again
+    st = settle(h);
+    if (st != LRDM_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->gemm));
+    HIPCHK(h, hipStreamSynchronize(h->aux));
+    HIPCHK(h, hipStreamDestroy(h->gemm));
+    HIPCHK(h, hipStreamDestroy(h->aux));
+    h->gemm = h->aux = nullptr;
+    HIPCHK(h, create_overlap_streams(h));
+    HIPCHK(h, hipEventRecord(h->ev_b2g, h->aux));
+    h->main_dirty = true;
+  }
+  return LRDM_OK;
+}
+
+lrdm_status lrdm_get_tuning(lrdm_t h, lrdm_tuning* t) {
+  if (!h || !t) return fail(h, LRDM_E_ARG, "null argument");
+  const int nb = gram_blocks(h->n, h->plain ? 1 : 2);
+  t->gram_blocks = h->tune.gram_blocks ? std::min(nb, h->tune.gram_blocks)
+                                       : (h->overlap ? std::min(nb, h->gemm_cus) : nb);
+  t->gram4_blocks = h->overlap ? (h->tune.gram4_blocks ? h->tune.gram4_blocks : h->gemm_cus) : 0;
+  const int kl = local_budget(h->n, h->lay.r_pad, h->dt == LRDM_C64 ? 8 : 16);
+  t->gate_local_max = h->tune.gate_local_max ? std::min(kl, h->tune.gate_local_max) : kl;
+  t->aux_cus = h->overlap ? h->aux_cus : 0;
+  return LRDM_OK;
 }
 
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {

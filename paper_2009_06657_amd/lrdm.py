@@ -33,6 +33,7 @@ SYMBOLS = ["lrdm_workspace_size", "lrdm_init", "lrdm_reset", "lrdm_destroy", "lr
            "lrdm_batch_end", "lrdm_batch_instantiate", "lrdm_batch_launch", "lrdm_batch_info",
            "lrdm_batch_times", "lrdm_batch_destroy", "lrdm_layout", "lrdm_run", "lrdm_energy_grad_bytes",
            "lrdm_energy_grad", "lrdm_batch_run", "lrdm_program_validate", "lrdm_expect_z_noalloc",
+           "lrdm_set_tuning", "lrdm_get_tuning",
            "lrdm_apply_kraus2", "lrdm_set_sparse", "lrdm_to_full", "lrdm_run_switching"]
 
 OP_GATE, OP_ROTATION, OP_WEIGHT, OP_KRAUS, OP_COMPRESS, OP_LAYER, OP_KRAUS2 = range(7)
@@ -49,6 +50,15 @@ class CompressInfo(ctypes.Structure):
     _fields_ = [("rank", ctypes.c_int), ("n_eig", ctypes.c_int), ("discarded", ctypes.c_double),
                 ("discarded_total", ctypes.c_double), ("trace_before", ctypes.c_double),
                 ("boundary_gap", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    """lrdm_tuning of include/lrdm.h (0 = default)."""
+    _fields_ = [("gram_blocks", ctypes.c_int), ("gram4_blocks", ctypes.c_int), ("gate_local_max", ctypes.c_int),
+                ("aux_cus", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -156,6 +166,8 @@ def load_library(path: str = LIB_PATH):
         "lrdm_synchronize": [P],
         "lrdm_timing_begin": [P, I],
         "lrdm_timing_end": [P, ctypes.POINTER(I), dp, dp],
+        "lrdm_set_tuning": [P, P],
+        "lrdm_get_tuning": [P, P],
         "lrdm_record_bytes": [P, ctypes.POINTER(SZ)],
         "lrdm_compress_record": [P, I, D, I, I, P, ctypes.POINTER(CompressInfo)],
         "lrdm_checkpoint": [P, P, ctypes.POINTER(I)],
@@ -241,7 +253,9 @@ class LowRankDM:
     """A handle over caller-owned device memory; method names follow the C ABI."""
 
     def __init__(self, n: int, r_max: int, dtype: int = C64, m_max: int = 4, flags: int = 0,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, tuning=None):
+        """tuning: None (the library's launch shapes), "table" (the autotuner's entry for this
+        shape, if any: paper_2009_06657_amd/tuning_table.json) or a dict of lrdm_tuning fields."""
         import torch
 
         self.lib = load_library()
@@ -259,6 +273,14 @@ class LowRankDM:
         _check(self.lib.lrdm_layout(self.h, None, ctypes.byref(ld), ctypes.byref(r_pad), None), self.h)
         self.r_pad = r_pad.value
         self.ld = ld.value
+        self.tuning = None
+        if tuning == "table":
+            from . import autotune
+
+            self.tuning = autotune.apply(self)
+        elif tuning:
+            self.set_tuning(**tuning)
+            self.tuning = dict(tuning)
 
     # -------------------------------------------------------------- lifetime
     def close(self):
@@ -432,6 +454,16 @@ class LowRankDM:
     # -------------------------------------------------------------- timing
     def timing_begin(self, kernel_class: int):
         _check(self.lib.lrdm_timing_begin(self.h, int(kernel_class)), self.h)
+
+    def set_tuning(self, **kw):
+        """lrdm_set_tuning: fields of lrdm_tuning by name (unnamed fields keep 0 = default)."""
+        t = Tuning(**{k: int(v) for k, v in kw.items()})
+        _check(self.lib.lrdm_set_tuning(self.h, ctypes.byref(t)), self.h)
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(self.lib.lrdm_get_tuning(self.h, ctypes.byref(t)), self.h)
+        return t.as_dict()
 
     def timing_end(self):
         n = ctypes.c_int()

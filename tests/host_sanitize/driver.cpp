@@ -98,6 +98,23 @@ static void exercise(int n, int r, lrdm_dtype dt, int m_max, unsigned flags) {
   int nn = 0, ld = 0, rp = 0;
   size_t sbb = 0;
   EXPECT(lrdm_layout(h, &nn, &ld, &rp, &sbb) == LRDM_OK && sbb == sb && nn == n);
+  // launch shapes: defaults resolved, a value out of range refused, odd shapes taken
+  lrdm_tuning tu{};
+  EXPECT(lrdm_get_tuning(h, &tu) == LRDM_OK && tu.gram_blocks >= 1 && tu.gate_local_max >= 1);
+  lrdm_tuning bad_t{};
+  bad_t.gram_blocks = 300;
+  EXPECT(lrdm_set_tuning(h, &bad_t) == LRDM_E_ARG);
+  bad_t = lrdm_tuning{};
+  bad_t.aux_cus = 48;
+  EXPECT(lrdm_set_tuning(h, &bad_t) == LRDM_E_ARG);
+  lrdm_tuning odd{};
+  odd.gram_blocks = 7;
+  odd.gate_local_max = 3;
+  if (flags & LRDM_FLAG_OVERLAP) {
+    odd.gram4_blocks = 5;
+    odd.aux_cus = 64;
+  }
+  EXPECT(lrdm_set_tuning(h, &odd) == LRDM_OK);
   double u[32], e[32], ph[2 * 31];
   mat_h(u);
   for (int q = 0; q < n; ++q) {

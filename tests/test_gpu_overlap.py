@@ -171,3 +171,35 @@ def test_overlap_reset_and_outputs_mid_program(lr):
     assert np.array_equal(P3, P1)
     assert all(np.array_equal(a[1], b[1]) for a, b in zip(zs1, zs3))
     dm.close(); ref.close()
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_tuned_launch_shapes_against_oracle(lr, flags):
+    """Launch shapes away from the defaults (fewer split-K Gram blocks, a smaller gate tile, fewer
+    4-way Gram blocks and a second XCD for the eigensolves): the same oracle parity, and the
+    library refuses shapes outside lrdm_tuning's ranges."""
+    prog = C.cfg3_program(n=10, r=64, layers=2)
+    dm = lr.LowRankDM(10, 64, lr.C64, prog.m_max, flags)
+    tun = {"gram_blocks": 5, "gate_local_max": 4}
+    if flags:
+        tun.update(gram4_blocks=3, aux_cus=64)
+    dm.set_tuning(**tun)
+    got = dm.get_tuning()
+    _say(f"[tuning] flags={flags} in use {got}")
+    assert got["gate_local_max"] == 4 and got["gram_blocks"] == 5
+    if flags:
+        assert got["gram4_blocks"] == 3 and got["aux_cus"] in (0, 64)   # 0: the runtime refused CU masks
+    lr.run_program(dm, prog)
+    P = dm.probabilities().cpu().numpy()
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    err = float(np.max(np.abs(P - Pref)))
+    _say(f"  max|dP| {err:.2e}")
+    assert err <= 1e-5
+    for bad in ({"gram_blocks": 300}, {"gate_local_max": 9}, {"gram4_blocks": 1}, {"aux_cus": 48}):
+        with pytest.raises(lr.LrdmError) as e:
+            dm.set_tuning(**bad)
+        assert e.value.status == 1
+    if not flags:
+        with pytest.raises(lr.LrdmError):
+            dm.set_tuning(aux_cus=64)
+    dm.close()

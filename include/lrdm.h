@@ -133,9 +133,11 @@ lrdm_status lrdm_compress(lrdm_t h, int r_target, double eps, int tie_policy, in
 /* Two-qubit Kraus channel (Sec. II.C: noise as one- and two-qubit Kraus operators; a group of
  * M = 2 qubits' channels as their product set {E_a (x) F_b}) on (q0, q1): e holds m 4 x 4
  * matrices (row-major, interleaved, local index b(q0) + 2 b(q1)), m in [1, m_max], completeness
- * within 1e-10.  Plain form only (handles made with LRDM_FLAG_PLAIN, where m_max may be up to 16
- * with m_pad * r_pad <= 128; fused handles: LRDM_E_UNSUPPORTED): [E_1 L | ... | E_m L] is
- * materialised here and the next call must be lrdm_compress. */
+ * within 1e-10; the next call must be lrdm_compress.  Plain form (LRDM_FLAG_PLAIN, m_max up to 16
+ * with m_pad * r_pad <= 128): [E_1 L | ... | E_m L] is materialised here.  Fused form (m_max <= 4,
+ * r_pad <= 32, else LRDM_E_UNSUPPORTED; not while recording a batch): nothing is materialised;
+ * the compression forms the 4-way Gram of the pair, G = sum_{u u'} (E_a^H E_b)_{u u'} S4_{u u'}
+ * and projects the 4-way view in place, W_{(u,v),(u',j)} = c sum_a (E_a)_{u'u} V[(a,v), j]. */
 lrdm_status lrdm_apply_kraus2(lrdm_t h, int q0, int q1, int m, const double* e);
 
 /* Sparse superposition initial state (Sec. II.D: Algorithm 1 also starts from any sparse linear
@@ -284,8 +286,7 @@ typedef enum {
   LRDM_OP_COMPRESS = 4,  /* lrdm_compress(r, eps, tie, renorm) */
   LRDM_OP_LAYER = 5,     /* end of a layer (checkpoint boundary); no arithmetic */
   LRDM_OP_KRAUS2 = 6     /* two-qubit channel on (q0, q1) with m = k operators (4 x 4) at coef + off
-                            (as lrdm_apply_kraus2, plain form); the next operation must be
-                            LRDM_OP_COMPRESS */
+                            (as lrdm_apply_kraus2); the next operation must be LRDM_OP_COMPRESS */
 } lrdm_op_kind;
 
 typedef struct {

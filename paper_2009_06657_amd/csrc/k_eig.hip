@@ -540,7 +540,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   constexpr int NP = 32 * BC;            // padded order; the thread grid is (NP / BR) x 32
   constexpr int NTH = 32 * (NP / BR);    // threads
   extern __shared__ __attribute__((aligned(16))) double dyn[];   // phase-dependent scratch
-  __shared__ z64 Mab[64];
+  __shared__ z64 Mab[256];   // (E_a^H E_b) blocks: 2 x 2 (one qubit) or 4 x 4 (a qubit pair)
   __shared__ z64 col_buf[NP], vbuf[2 * NP], pbuf[2 * NP], cola[2 * NP];
   __shared__ double d_s[NP], e_s[NP], e2_s[NP], lam_s[NP + 1], tau_s[2 * NP], trp[32];
   __shared__ int cl_start[NP], cl_len[NP];
@@ -550,7 +550,7 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int R = tid >> 5, Cc = tid & 31;   // half-wave / lane in it
   constexpr int NH = NP / BR;              // half-waves; thread rows R + NH a, columns BC Cc + b
-  const int m = (nsplit == 2) ? ch.m : 1;
+  const int m = (nsplit >= 2) ? ch.m : 1;
 
   if constexpr (PART != 2) {   // phases 1 and 2 (and the scaling of T below) run in part 1
     // ---------------------------------------------------------------- 1. assemble G
@@ -561,13 +561,39 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
         acc = zadd(acc, zcmul(zmk(ch.e[a][r][u][0], ch.e[a][r][u][1]), zmk(ch.e[b][r][v][0], ch.e[b][r][v][1])));
       Mab[tid] = acc;   // (E_a^H E_b)_{uv} at ((a m + b) 2 + u) 2 + v
     }
+    if (nsplit == 4 && tid < m * m * 16)   // (E_a^H E_b)_{u u'} at ((a m + b) 4 + u) 4 + u', formed on the host
+      Mab[tid] = zmk(B.M4[2 * tid], B.M4[2 * tid + 1]);
     __syncthreads();
     // Each thread reads the S entries of its own G entries straight from memory (S is at most
     // 256 KiB): one row of the thread's layout per round, the 4 BC loads of a round in flight
     // before the first product; the terms of each G entry are added in the order
     // (u, v) = (0, 0), (0, 1), (1, 0), (1, 1).  (A chunked LDS staging of S was slower.)
     z64 A[BR][BC];
-    {
+    if (nsplit == 4) {
+      // a qubit pair: S is the 4-way Gram (blocks of c columns, index u = b(q0) + 2 b(q1)), G's
+      // copies take its first cw = N / m columns of each block
+      const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
+      const int cw = N / m;
+      const int cs = __ffs(cw) - 1;
+  #pragma unroll
+      for (int a = 0; a < BR; ++a) {
+        const int i = R + NH * a;
+  #pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int j = BC * Cc + b;
+          z64 acc = zmk(0, 0);
+          if (i < N && j < N) {
+            const int ai = i >> cs, bj = j >> cs, v = i & (cw - 1), w = j & (cw - 1);
+            for (int u = 0; u < 4; ++u)
+              for (int u2 = 0; u2 < 4; ++u2) {
+                const double2 sv = S2[(size_t)(u * c + v) * Fc + (u2 * c + w)];
+                acc = zadd(acc, zmul(Mab[((ai * m + bj) * 4 + u) * 4 + u2], zmk(sv.x, sv.y)));
+              }
+          }
+          A[a][b] = acc;
+        }
+      }
+    } else {
       // split view: S has halves of c columns; G's copies take the first cw = N / m of them, a
       // power of two (the factor's later columns are zero while its rank is still growing)
       const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
@@ -1120,7 +1146,28 @@ __device__ __forceinline__ void backtransform_body(const Channel& ch, int nsplit
   }
   if (col >= c_out) return;
   using C = cx_t<T>;
-  if (nsplit == 2) {
+  if (nsplit == 4) {
+    // a qubit pair: W_{(u,v),(u',j)} = c sum_a (E_a)_{u'u} V[(a,v), j], u = b(q0) + 2 b(q1)
+    const int rows = 4 * c, cols = 4 * c_out;
+    const int cs = __ffs(c) - 1;
+    const int cw = N / ch.m;
+    for (int rw = lane; rw < rows; rw += 64) {
+      const int u = rw >> cs, v = rw & (c - 1);
+      for (int up = 0; up < 4; ++up) {
+        z64 acc = zmk(0, 0);
+        if (col < k && v < cw) {
+          for (int a = 0; a < ch.m; ++a) {
+            const int e = (a * 4 + up) * 4 + u;
+            acc = zadd(acc, zmul(zmk(B.E4[2 * e], B.E4[2 * e + 1]), Vs[wave][a * cw + v]));
+          }
+        }
+        C o;
+        o.x = (T)(acc.x * scl);
+        o.y = (T)(acc.y * scl);
+        W[rw * cols + up * c_out + col] = o;
+      }
+    }
+  } else if (nsplit == 2) {
     const int rows = 2 * c, cols = 2 * c_out;
     const int cs = __ffs(c) - 1;   // c is a power of two in the split view
     const int cw = N / ch.m;       // columns of each copy in G (rows v >= cw of W are zero)
@@ -1320,7 +1367,8 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
                       int kmax, int r_target, double eps, int tie, int renorm, int c_out,
                       const EigBufs& b, cx_t<T>* W, hipStream_t s) {
   if (N < 1 || N > kMaxEig || kmax < 1 || kmax > N || r_target > 64 || c_out > 64) return hipErrorInvalidValue;
-  if (nsplit == 2 && (c < 1 || (c & (c - 1)))) return hipErrorInvalidValue;   // split view: c a power of two
+  if (nsplit >= 2 && (c < 1 || (c & (c - 1)))) return hipErrorInvalidValue;   // split view: c a power of two
+  if (nsplit == 4 && (!b.M4 || !b.E4 || b.rec || N % ch.m)) return hipErrorInvalidValue;
   if (b.rec && (N > kRecMaxN || kmax != N)) return hipErrorInvalidValue;
   hipError_t e;
   // layouts: order <= 32 on 256 threads (<4, 1>), <= 64 on 512 threads (<4, 2>), <= 128 on 512

@@ -48,7 +48,7 @@ template <class T, int FO>
 __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, int F, int seg_in_shift,
                                              int nsplit, int q, int seg_out_shift,
                                              const cx_t<T>* __restrict__ W, int skip, uint32_t rows,
-                                             uint32_t bid) {
+                                             uint32_t bid, int q1 = -1) {
   using A4 = typename PAcc4<T>::type;
   using P2 = typename PPair<T>::type;
   constexpr int NTO = FO / 16;
@@ -72,6 +72,12 @@ __device__ __forceinline__ void project_body(cx_t<T>* __restrict__ L, int ld, in
 
   auto row_index = [&](uint32_t y, int h) -> uint32_t {
     if (nsplit == 1) return y;
+    if (nsplit == 4) {   // qubit pair (q, q1): segment h = b(q) + 2 b(q1)
+      const int lo = q < q1 ? q : q1, hi = q < q1 ? q1 : q;
+      uint32_t t = ((y >> lo) << (lo + 1)) | (y & ((1u << lo) - 1u));
+      t = ((t >> hi) << (hi + 1)) | (t & ((1u << hi) - 1u));
+      return t | ((uint32_t)(h & 1) << q) | ((uint32_t)(h >> 1) << q1);
+    }
     return ((((y >> q) << (q + 1)) | (y & ((1u << q) - 1u))) | ((uint32_t)h << q));
   };
 
@@ -211,6 +217,14 @@ __global__ __launch_bounds__(256, 2) void project_kernel(cx_t<T>* __restrict__ L
   project_body<T, FO>(L, ld, F, seg_in_shift, nsplit, q, seg_out_shift, W, skip, rows, blockIdx.x);
 }
 
+// the qubit-pair view (nsplit = 4)
+template <class T, int FO>
+__global__ __launch_bounds__(256, 2) void project4_kernel(cx_t<T>* __restrict__ L, int ld, int F, int seg_in_shift,
+                                                          int q0, int q1, int seg_out_shift,
+                                                          const cx_t<T>* __restrict__ W, uint32_t rows) {
+  project_body<T, FO>(L, ld, F, seg_in_shift, 4, q0, seg_out_shift, W, 0, rows, blockIdx.x, q1);
+}
+
 template <class T, int FO>
 __global__ __launch_bounds__(256, 2) void project_batched(const ProjJob<T>* __restrict__ jobs, int njobs) {
   const int j = find_job(jobs, njobs, blockIdx.x);
@@ -268,6 +282,37 @@ hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q
   }
 }
 
+template <class T, int FO>
+static hipError_t launch_proj4_f(cx_t<T>* L, int n, int ld, int c_in, int q0, int q1, int c_out, const cx_t<T>* W,
+                                 hipStream_t s) {
+  const uint32_t rows = 1u << (n - 2);
+  const uint32_t blocks = (rows + kProjBM - 1) / kProjBM;
+  int si = 0, so = 0;
+  while ((1 << si) < 2 * c_in) ++si;
+  while ((1 << so) < 2 * c_out) ++so;
+  if ((1 << si) != 2 * c_in || (1 << so) != 2 * c_out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((project4_kernel<T, FO>), dim3(blocks), dim3(256), 0, s, L, ld, 8 * c_in, si, q0, q1, so, W,
+                     rows);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project4(cx_t<T>* L, int n, int ld, int c_in, int q0, int q1, int c_out, const cx_t<T>* W,
+                           hipStream_t s) {
+  if (n < 2 || q0 == q1 || q0 < 0 || q1 < 0 || q0 >= n || q1 >= n || c_in > 32 || c_in < 1 || c_out > 32)
+    return hipErrorInvalidValue;
+  switch (8 * c_out) {
+    case 64: return launch_proj4_f<T, 64>(L, n, ld, c_in, q0, q1, c_out, W, s);
+    case 128: return launch_proj4_f<T, 128>(L, n, ld, c_in, q0, q1, c_out, W, s);
+    case 256:
+      if constexpr (sizeof(T) == 4) return launch_proj4_f<T, 256>(L, n, ld, c_in, q0, q1, c_out, W, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_project4<float>(float2*, int, int, int, int, int, int, const float2*, hipStream_t);
+template hipError_t launch_project4<double>(double2*, int, int, int, int, int, int, const double2*, hipStream_t);
 template hipError_t launch_project_batched<float>(int, const ProjJob<float>*, int, uint32_t, hipStream_t);
 template hipError_t launch_project_batched<double>(int, const ProjJob<double>*, int, uint32_t, hipStream_t);
 template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, int, hipStream_t);

@@ -72,6 +72,10 @@ struct EigBufs {
   double* W64;      // nullable: W in FP64 as well (split view), for chained compressions
   double* Y;        // reflector scalars tau_j (2 (N - 1) doubles), then at kEigYOff the kept
                     // eigenvectors of T, column t at t * kMaxEig (eigensolver -> back-transform)
+  // a channel on a qubit pair (nsplit = 4): (E_a^H E_b)_{u u'} at ((a m + b) 4 + u) 4 + u' and
+  // (E_a)_{u' u} at (a 4 + u') 4 + u, complex FP64 (null otherwise)
+  const double* M4 = nullptr;
+  const double* E4 = nullptr;
 };
 constexpr int kEigYOff = 2 * kMaxEig;
 // after the eigenvectors: the scaled T (d, e, e^2), tau, the trace and the Gershgorin norm,
@@ -200,6 +204,12 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
                           const cx_t<T>* W, int skip, hipStream_t s);
+
+// Projection of a channel on the qubit pair (q0, q1): the 4-way view X4 = [L_0 | L_1 | L_2 | L_3]
+// (u = b(q0) + 2 b(q1), 2^(n-2) rows) times W (4c x 4c_out), in place.
+template <class T>
+hipError_t launch_project4(cx_t<T>* L, int n, int ld, int c_in, int q0, int q1, int c_out, const cx_t<T>* W,
+                           hipStream_t s);
 
 template <class T>
 hipError_t launch_probabilities(const cx_t<T>* L, int n, int ld, int ncols, double* p,

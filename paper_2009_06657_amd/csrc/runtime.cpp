@@ -47,6 +47,9 @@ struct Layout {
   // of the pair transform and the partials of the 4-way Gram
   bool overlap;
   size_t off_W2, off_S4, off_T4, off_part4;
+  // fused form, channels on a qubit pair: W of the 4-way view (4 r_pad x 4 r_pad) and the FP64
+  // operator blocks the eigensolver reads (E_a^H E_b and E_a); the 4-way Gram uses S4 and part4
+  size_t off_W4, off_M4;
 };
 
 bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, Layout& L,
@@ -100,15 +103,20 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
   L.adjoint = !plain && N_rec <= kRecMaxN;
   L.off_adj = L.adjoint ? take(adj_doubles(L.r_pad, N_rec) * 8) : 0;
   L.off_chain = plain ? 0 : take((size_t)(L.overlap ? 4 : 3) * (2 * L.r_pad) * (2 * L.r_pad) * 16);
-  L.off_W2 = L.off_S4 = L.off_T4 = L.off_part4 = 0;
-  if (L.overlap) {
-    const size_t c4 = 4 * (size_t)L.r_pad, c2 = 2 * (size_t)L.r_pad;
+  L.off_W2 = L.off_S4 = L.off_T4 = L.off_part4 = L.off_W4 = L.off_M4 = 0;
+  if (!plain && n >= 2) {
+    const size_t c4 = 4 * (size_t)L.r_pad;
     const size_t nt = c4 / 16;   // 16-wide real tiles across one half (4c reals)
     const size_t nup = nt * (nt + 1) / 2;
-    L.off_W2 = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
     L.off_S4 = take(2 * c4 * c4 * 16);
-    L.off_T4 = take(3 * c2 * c2 * 16);
     L.off_part4 = take(((size_t)2 * gram4_blocks_halves(n) * nup + (size_t)gram4_blocks_cross(n) * nt * nt) * 256 * rs);
+    L.off_W4 = take(c4 * c4 * cs);
+    L.off_M4 = take((size_t)(16 * 16 + 4 * 16) * 16);
+  }
+  if (L.overlap) {
+    const size_t c2 = 2 * (size_t)L.r_pad;
+    L.off_W2 = take((size_t)(L.F_max / 2) * (L.FO_max / 2) * cs);
+    L.off_T4 = take(3 * c2 * c2 * 16);
   }
   L.rec_bytes = L.adjoint ? align_up(record_doubles(N_rec) * 8) : 0;
   L.total = o;
@@ -164,6 +172,11 @@ struct lrdm_ctx {
   bool chan_pending = false;
   int chan_q = 0;
   Channel chan{};
+  // fused form: the pending channel acts on the pair (chan_q, chan_q1) with the 4 x 4 operators
+  // in pair_e; pair_stage holds E_a^H E_b and E_a for the upload
+  bool chan_pair = false;
+  int chan_q1 = -1;
+  std::vector<double> pair_e, pair_stage;
   // timing
   int timing_class = -1;
   std::vector<hipEvent_t> ev;
@@ -596,7 +609,14 @@ lrdm_status settle(lrdm_t h) {
 }
 
 template <class T>
+lrdm_status compress_pair_t(lrdm_t h, int r_target, double eps, int tie, int renorm);
+
+template <class T>
 lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, double* rec) {
+  if (h->chan_pending && h->chan_pair) {
+    if (rec) return fail(h, LRDM_E_UNSUPPORTED, "compression records take one-qubit channels");
+    return compress_pair_t<T>(h, r_target, eps, tie, renorm);
+  }
   const int nsplit = (h->chan_pending && !h->plain) ? 2 : 1;
   const int q = nsplit == 2 ? h->chan_q : 0;
   Channel ch{};
@@ -791,6 +811,70 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   return LRDM_OK;
 }
 
+// A channel on the qubit pair (q0, q1), fused form: G = sum_{u u'} (E_a^H E_b)_{u u'} S4_{u u'}
+// from the 4-way Gram S4 of the pair (Sec. II.C: a channel group of two qubits, one truncation),
+// then L_new = X4 W with W_{(u,v),(u',j)} = c sum_a (E_a)_{u'u} V[(a,v), j].  No chaining: the
+// projection is issued at once, on the caller's stream.
+template <class T>
+lrdm_status compress_pair_t(lrdm_t h, int r_target, double eps, int tie, int renorm) {
+  lrdm_status st = settle_t<T>(h);
+  if (st != LRDM_OK) return st;
+  const int c = h->lay.r_pad, m = h->chan.m;
+  const int cw = std::min(c, std::max(8, next_pow2(h->c_bound)));
+  const int N = m * cw, Fc = 4 * c;
+  const int kmax = std::min(r_target + 1, N);
+  const int q0 = h->chan_q, q1 = h->chan_q1;
+  auto* L = static_cast<cx_t<T>*>(h->state);
+  // the operator blocks (host FP64, staged once per channel)
+  double* M4 = h->ws<double>(h->lay.off_M4);
+  double* E4 = M4 + 2 * 16 * 16;
+  h->pair_stage.assign(2 * (16 * 16 + 4 * 16), 0.0);
+  const double* e = h->pair_e.data();
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      for (int u = 0; u < 4; ++u)
+        for (int u2 = 0; u2 < 4; ++u2) {
+          double re = 0, im = 0;
+          for (int r = 0; r < 4; ++r) {
+            const double ar = e[((a * 4 + r) * 4 + u) * 2], ai = -e[((a * 4 + r) * 4 + u) * 2 + 1];
+            const double br = e[((b * 4 + r) * 4 + u2) * 2], bi = e[((b * 4 + r) * 4 + u2) * 2 + 1];
+            re += ar * br - ai * bi;
+            im += ar * bi + ai * br;
+          }
+          const int t = ((a * m + b) * 4 + u) * 4 + u2;
+          h->pair_stage[2 * t] = re;
+          h->pair_stage[2 * t + 1] = im;
+        }
+  std::copy(e, e + 32 * m, h->pair_stage.begin() + 2 * 16 * 16);
+  HIPCHK(h, hipMemcpyAsync(M4, h->pair_stage.data(), h->pair_stage.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));   // the staging vector is reused by the next channel
+  // 4-way Gram of the pair on the caller's stream (the overlap mode's pipeline is settled)
+  double* S4 = h->ws<double>(h->lay.off_S4);
+  T* part_h = h->ws<T>(h->lay.off_part4);
+  T* part_c = part_h + (size_t)2 * gram4_blocks_halves(h->n) * ((c / 4) * (c / 4 + 1) / 2) * 256;
+  timed_begin(h, 6);
+  HIPCHK(h, launch_gram4<T>(L, h->n, h->lay.ld, c, q0, q1, part_h, part_c, S4,
+                            h->tune.gram4_blocks ? h->tune.gram4_blocks : 256, h->stream));
+  timed_end(h, 6);
+  EigBufs b = eig_bufs(h);
+  b.M4 = M4;
+  b.E4 = E4;
+  Channel ch{};
+  ch.m = m;
+  cx_t<T>* W4 = h->ws<cx_t<T>>(h->lay.off_W4);
+  timed_begin(h, 3);
+  HIPCHK(h, launch_eig<T>(S4, Fc, ch, 4, c, N, kmax, r_target, eps, tie, renorm, c, b, W4, h->stream));
+  timed_end(h, 3);
+  timed_begin(h, 4);
+  HIPCHK(h, launch_project4<T>(L, h->n, h->lay.ld, c, q0, q1, c, W4, h->stream));
+  timed_end(h, 4);
+  h->ncols = c;
+  h->c_bound = std::min(std::min(h->c_bound * m, r_target), N);
+  h->chan_pending = false;
+  h->chan_pair = false;
+  return LRDM_OK;
+}
+
 template <class T>
 lrdm_status reset_t(lrdm_t h) {
   if (h->rec) {
@@ -809,6 +893,7 @@ lrdm_status reset_t(lrdm_t h) {
     h->c_bound = 1;
     h->gates.clear();
     h->chan_pending = false;
+    h->chan_pair = false;
     return LRDM_OK;
   }
   lrdm_status st = join_aux(h);   // a dropped pending compression may still run on aux
@@ -821,6 +906,7 @@ lrdm_status reset_t(lrdm_t h) {
   h->c_bound = 1;
   h->gates.clear();
   h->chan_pending = false;
+  h->chan_pair = false;
   return LRDM_OK;
 }
 
@@ -1134,11 +1220,14 @@ lrdm_status lrdm_apply_kraus(lrdm_t h, int qubit, int m, const double* e) {
 lrdm_status lrdm_apply_kraus2(lrdm_t h, int q0, int q1, int m, const double* e) {
   lrdm_status st = check_usable(h);
   if (st != LRDM_OK) return st;
-  if (!h->plain)
-    return fail(h, LRDM_E_UNSUPPORTED, "two-qubit channels run in the plain form (LRDM_FLAG_PLAIN)");
   if (q0 < 0 || q0 >= h->n || q1 < 0 || q1 >= h->n || q0 == q1)
     return fail(h, LRDM_E_ARG, "qubits out of range or repeated");
   if (m < 1 || m > h->m_max) return fail(h, LRDM_E_ARG, "Kraus count must be in [1, m_max]");
+  if (!h->plain) {
+    if (h->rec) return fail(h, LRDM_E_UNSUPPORTED, "channels on a qubit pair are not recorded into a batch");
+    if (h->lay.r_pad > 32)
+      return fail(h, LRDM_E_UNSUPPORTED, "fused channels on a qubit pair take r_pad <= 32 (else LRDM_FLAG_PLAIN)");
+  }
   if (!e) return fail(h, LRDM_E_ARG, "null Kraus matrices");
   // completeness sum_a E_a^H E_a = I (4 x 4)
   for (int i = 0; i < 4; ++i)
@@ -1157,6 +1246,16 @@ lrdm_status lrdm_apply_kraus2(lrdm_t h, int q0, int q1, int m, const double* e) 
   if (h->chan_pending) return fail(h, LRDM_E_STATE, "a Kraus channel is already pending: compress first");
   st = flush_gates(h);
   if (st != LRDM_OK) return st;
+  if (!h->plain) {   // fused: kept for the compression, nothing materialised
+    h->pair_e.assign(e, e + 32 * m);
+    h->chan_pending = true;
+    h->chan_pair = true;
+    h->chan_q = q0;
+    h->chan_q1 = q1;
+    h->chan = Channel{};
+    h->chan.m = m;
+    return LRDM_OK;
+  }
   const int c = h->ncols, m_pad = h->lay.m_pad;
   // launches over operator blocks, the one holding a = 0 (which overwrites the input columns) last
   std::vector<int> starts;

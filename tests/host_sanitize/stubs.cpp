@@ -166,6 +166,8 @@ static void touch_eig(const double* S, int Fc, int N, int nsplit, int c, int c_o
   touch(b.info, sizeof(DevInfo), "eig info");
   if (b.rec) touch(b.rec, record_doubles(N) * 8, "eig record");
   if (b.W64) touch(b.W64, (size_t)(nsplit * c) * (nsplit * c_out) * 16, "eig W64");
+  if (b.M4) touch(b.M4, (size_t)16 * 16 * 16, "eig operator products");
+  if (b.E4) touch(b.E4, (size_t)4 * 16 * 16, "eig operators");
   touch(W, (size_t)(nsplit * c) * (nsplit * c_out) * wsz, "eig W");
 }
 
@@ -335,6 +337,18 @@ hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T*
   touch(S4, (size_t)(4 * c) * (4 * c) * 16, "gram4 S4");
   return hipSuccess;
 }
+template <class T>
+hipError_t launch_project4(cx_t<T>* L, int n, int ld, int c_in, int q0, int q1, int c_out, const cx_t<T>* W,
+                           hipStream_t) {
+  ++hs::launches;
+  if (q0 == q1 || q0 < 0 || q1 < 0 || q0 >= n || q1 >= n) {
+    ++hs::violations;
+    std::fprintf(stderr, "pair projection on bits %d, %d of %d qubits\n", q0, q1, n);
+  }
+  touch_L<T>(L, n, ld, c_in > c_out ? c_in : c_out, "proj4 L");
+  touch(W, (size_t)(4 * c_in) * (4 * c_out) * sizeof(cx_t<T>), "proj4 W");
+  return hipSuccess;
+}
 hipError_t launch_pair_transform(const double* G4, const double* W, double* T, double* S, int c, hipStream_t) {
   ++hs::launches;
   touch(G4, (size_t)(4 * c) * (4 * c) * 16, "pair G4");
@@ -490,7 +504,8 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t) {
   template hipError_t launch_kraus2_expand<T>(cx_t<T>*, int, int, int, int, int, const Kraus2Chunk&, hipStream_t);  \
   template hipError_t launch_set_sparse<T>(cx_t<T>*, int, const uint64_t*, const double*, int, hipStream_t);       \
   template hipError_t launch_lr_to_full<T>(const cx_t<T>*, int, int, int, float2*, hipStream_t);                 \
-  template hipError_t launch_gram4<T>(const cx_t<T>*, int, int, int, int, int, T*, T*, double*, int, hipStream_t);
+  template hipError_t launch_gram4<T>(const cx_t<T>*, int, int, int, int, int, T*, T*, double*, int, hipStream_t); \
+  template hipError_t launch_project4<T>(cx_t<T>*, int, int, int, int, int, int, const cx_t<T>*, hipStream_t);
 LRDM_STUB_INST(float)
 LRDM_STUB_INST(double)
 

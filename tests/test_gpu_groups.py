@@ -52,11 +52,64 @@ def test_grouped_channels_plain_form(lr, dtype, case):
     dm.close()
 
 
-def test_two_qubit_channel_needs_plain_form(lr):
-    dm = lr.LowRankDM(6, 8, lr.C64, 4)
+def _swap_pair(prog):
+    """The same program with every pair channel given as (q1, q0): its matrices with the two local
+    index bits exchanged (u = b(q0) + 2 b(q1) -> b(q1) + 2 b(q0))."""
+    P = np.eye(4)[[0, 2, 1, 3]]
+    ops = []
+    for op in prog.ops:
+        if isinstance(op, C.Kraus) and op.qubit2 >= 0:
+            ops.append(C.Kraus(op.qubit2, np.stack([P @ E @ P for E in op.ops]), op.name, op.qubit))
+        else:
+            ops.append(op)
+    return C.Program(prog.n, ops, prog.r, prog.dtype, prog.m_max, prog.name, prog.layers, dict(prog.meta))
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("case", [("c64", 8, "ad", "", 16, False), ("c64", 9, "deph", "", 32, True),
+                                  ("c64", 8, "", "zz", 32, False), ("c128", 8, "ad", "", 16, True),
+                                  ("c128", 7, "", "zz", 8, False)])
+def test_fused_pair_channels_against_oracle(lr, flags, case):
+    """Channels on a qubit pair in the fused form (the 4-way Gram of the pair, G from
+    (E_a^H E_b) blocks, the 4-way projection in place): the oracle's probabilities within 1e-5
+    (complex64) and 1e-10 (complex128), the plain form's within the same bar; pairs given in both
+    qubit orders; with the overlap flag, one-qubit channels (odd n) between pair channels."""
+    dtype, n, channel, two, r, swap = case
+    if dtype == "c128" and flags:
+        pytest.skip("the overlap flag is exercised in complex64 here")
+    prog = C.grouped_brickwork_program(n, 3, r, channel, 0.02, seed=51, dtype=dtype, two_qubit=two, tie=1)
+    if swap:
+        prog = _swap_pair(prog)
+    dt = lr.C64 if dtype == "c64" else lr.C128
+    _say(f"[fused pair] {dtype} n={n} {channel or two} r={r} m_max={prog.m_max} swap={swap} flags={flags}")
+    dm = lr.LowRankDM(n, r, dt, prog.m_max, flags)
+    lr.run_program(dm, prog)
+    P = dm.probabilities().cpu().numpy()
+    pl = lr.LowRankDM(n, r, dt, prog.m_max, lr.FLAG_PLAIN)
+    lr.run_program(pl, prog)
+    Pp = pl.probabilities().cpu().numpy()
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    bar = 1e-5 if dtype == "c64" else 1e-10
+    err, errp = float(np.max(np.abs(P - Pref))), float(np.max(np.abs(Pp - Pref)))
+    _say(f"  max|dP| fused {err:.2e}, plain {errp:.2e}")
+    assert err <= bar and errp <= bar
+    dm.close(); pl.close()
+
+
+def test_two_qubit_channel_limits(lr):
+    # fused form: up to r_pad = 32 (the 4-way projection's width)
+    dm = lr.LowRankDM(6, 64, lr.C64, 2)
     with pytest.raises(lr.LrdmError) as e:
         dm.apply_kraus(0, C.correlated_dephasing(0.1), 3)
     assert e.value.status == 6
+    dm.close()
+    dm = lr.LowRankDM(6, 8, lr.C64, 2)
+    with pytest.raises(lr.LrdmError) as e:
+        dm.apply_kraus(0, C.grouped_channel(C.amplitude_damping(0.1), C.amplitude_damping(0.1)), 3)
+    assert e.value.status == 1   # 4 operators on a handle made for 2
+    dm.apply_kraus(0, C.correlated_dephasing(0.1), 3)
+    dm.compress(8)
+    assert abs(dm.expect_z()[2] - 1) < 1e-5
     dm.close()
     dm = lr.LowRankDM(6, 8, lr.C64, 4, lr.FLAG_PLAIN)
     with pytest.raises(lr.LrdmError) as e:

@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from oracle import grad as OG
 from workloads import circuits as C
 
@@ -70,6 +71,26 @@ def test_run_equals_operation_calls_and_checkpoints_resume(lr):
     assert np.array_equal(c.get_L(), La)
     for h in (a, b, c):
         h.close()
+
+
+def test_run_with_overlap_equals_operation_calls(lr):
+    """lrdm_run on an LRDM_FLAG_OVERLAP handle issues the same launches as the operation calls on
+    one (the same bits), with per-layer checkpoints taken between the streams' work."""
+    import torch
+
+    prog = C.cfg3_program(n=10, r=32, layers=3)
+    a = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, lr.FLAG_OVERLAP)
+    lr.run_program(a, prog)
+    La = a.get_L()
+    b = lr.LowRankDM(prog.n, prog.r, lr.C64, prog.m_max, lr.FLAG_OVERLAP)
+    fp = lr.lrdm.FlatProgram(prog)
+    S = (b.state.numel() + 255) // 256 * 256
+    ckpt = torch.empty(fp.n_layers * S, dtype=torch.uint8, device=b.device)
+    b.run(fp, ckpt)
+    assert np.array_equal(b.get_L(), La)
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    assert float(np.max(np.abs(b.probabilities().cpu().numpy() - Pref))) <= 1e-5
+    a.close(); b.close()
 
 
 def test_energy_grad_direct_call_matches_finite_differences(lr):

@@ -99,147 +99,215 @@ __device__ __forceinline__ uint32_t pick_or(int i, const uint32_t (&v)[R]) {
   return r;
 }
 
-// Register layout of phase ph: the thread's 2^R elements differ in the phase's register slots
-// (sh_pos: their tile offsets, sh_row: their row bits); the other tile-index bits come from the
-// thread id (pos: its tile offset, sub: the local-qubit part of its row index).
+// Register layout of phase ph (GatePass::ph_word): the thread's 2^R elements differ in the
+// phase's register slots (sh_pos: their tile offsets, sh_row: their row bits); the column and
+// the other slots come from the thread index te (pos: its tile offset, sub: the local-qubit part
+// of its row index).
 template <class T, int R>
-__device__ __forceinline__ void phase_layout(const GatePass<T>& P, int ph, int E, int cshift,
-                                             const uint32_t* slot_off, uint32_t& pos, uint32_t& sub,
-                                             uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
-  const uint32_t tid = threadIdx.x;
-  uint32_t rmask = 0;
+__device__ __forceinline__ void phase_layout(const GatePass<T>& P, int ph, int cshift, uint32_t te, uint32_t& pos,
+                                             uint32_t& sub, uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
+  const uint32_t w = P.ph_word[ph];
 #pragma unroll
   for (int b = 0; b < R; ++b) {
-    const int slot = P.ph_slots[ph][b];
+    const uint32_t slot = (w >> (4 * b)) & 15u;
     sh_pos[b] = 1u << (cshift + slot);
     sh_row[b] = 1u << P.local_q[slot];
-    rmask |= sh_pos[b];
   }
-  const uint32_t tmask = ((1u << E) - 1u) & ~rmask;
-  uint32_t p = 0;
-  int src = 0;
-  for (int q = 0; q < E; ++q)
-    if ((tmask >> q) & 1u) {
-      p |= ((tid >> src) & 1u) << q;
-      ++src;
-    }
-  pos = p;
-  sub = slot_off[(p >> cshift) & 255u];
+  pos = te & ((1u << cshift) - 1u);
+  sub = 0;
+  for (int t = 0; t < P.k - R; ++t) {
+    const uint32_t slot = (w >> (16 + 4 * t)) & 15u;
+    const uint32_t bit = (te >> (cshift + t)) & 1u;
+    pos |= bit << (cshift + slot);
+    sub |= bit << P.local_q[slot];
+  }
 }
 
-// Operations of phase ph on the registers (row_g: the row index of register 0).  In phase mode
-// op_a of a 1q operation is a register bit index (0 .. R-1); only 1q and 1- or 2-qubit diagonal
-// operations occur (passes with general 2q gates or Hamming-weight phases use the
-// per-operation sweeps instead).
-template <class T, int R>
-__device__ __forceinline__ void phase_apply(const GatePass<T>& P, int ph, RC<T> (&x)[1 << R], uint32_t row_g,
-                                            const uint32_t (&sh_row)[R]) {
-  using C = RC<T>;
+// Diagonal operation on the registers of one thread.  Its phase index is sel = b_a + 2 b_b
+// (b_a, b_b: the row bits of its two qubits).  RA / RB is the register bit holding qubit a / b
+// in this phase, or -1 where that bit comes from the thread's row index (ta / tb, shared by all
+// its registers).  The registers fall into at most four patterns s = (bit RA of i, bit RB of i)
+// with one phase each (the same on every lane when both qubits are register bits).  Every
+// register is multiplied in place, without branches, so the registers keep their places.
+template <int RA, int RB, bool REAL, class T, int R>
+__device__ __forceinline__ void reg_diag(RC<T> (&x)[1 << R], RC<T> d0, RC<T> d1, RC<T> d2, RC<T> d3, uint32_t ta,
+                                         uint32_t tb) {
   constexpr int NR = 1 << R;
-  const int o0 = P.ph_first[ph], o1 = o0 + P.ph_count[ph];
-  for (int o = o0; o < o1; ++o) {
-    const T* u = P.coef + P.op_coef[o];
-    const int ty = P.op_type[o];
-    if (ty == OP_1Q) {
-      switch (P.op_a[o]) {
-        case 0: reg_1q<0, R, T>(x, u); break;
-        case 1: reg_1q<1, R, T>(x, u); break;
-        case 2: reg_1q<2, R, T>(x, u); break;
-        default: reg_1q<3, R, T>(x, u); break;
-      }
+  T px[4], py[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if ((RA < 0 && (s & 1)) || (RB < 0 && (s & 2))) continue;
+    if (RA >= 0 && RB >= 0) {
+      px[s] = (s == 3) ? d3.x : (s == 2) ? d2.x : (s == 1) ? d1.x : d0.x;
+      py[s] = (s == 3) ? d3.y : (s == 2) ? d2.y : (s == 1) ? d1.y : d0.y;
     } else {
-      // OP_DIAG1 / OP_DIAG2: the (at most four) phases are uniform; each element selects one
-      const int qa = P.op_a[o], qb = (ty == OP_DIAG2) ? P.op_b[o] : P.op_a[o];
-      const C d0{u[0], u[1]}, d1{u[2], u[3]};
-      const C d2{(ty == OP_DIAG2) ? u[4] : u[0], (ty == OP_DIAG2) ? u[5] : u[1]};
-      const C d3{(ty == OP_DIAG2) ? u[6] : u[2], (ty == OP_DIAG2) ? u[7] : u[3]};
-      if (d0.y == 0 && d1.y == 0 && d2.y == 0 && d3.y == 0) {
-        // real phases (CZ, sign flips): a real scale per element
+      // a per-lane choice: the phases go through registers first, so that it stays a chain of
+      // lane selects (not a table in scratch memory indexed per lane)
+      const uint32_t sa = (uint32_t)(s & 1) | ta, sb = (uint32_t)((s >> 1) & 1) | tb;
+      T a0 = d0.x, a1 = d1.x, a2 = d2.x, a3 = d3.x, b0 = d0.y, b1 = d1.y, b2 = d2.y, b3 = d3.y;
+      asm volatile("" : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3));
+      px[s] = sb ? (sa ? a3 : a2) : (sa ? a1 : a0);
+      py[s] = sb ? (sa ? b3 : b2) : (sa ? b1 : b0);
+    }
+  }
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          const uint32_t row = row_g | pick_or<R>(i, sh_row);
-          const bool ba = (row >> qa) & 1u, bb = (row >> qb) & 1u;
-          const T pr = bb ? (ba ? d3.x : d2.x) : (ba ? d1.x : d0.x);
-          x[i].x *= pr;
-          x[i].y *= pr;
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) {
-          const uint32_t row = row_g | pick_or<R>(i, sh_row);
-          const bool ba = (row >> qa) & 1u, bb = (row >> qb) & 1u;
-          const T pr = bb ? (ba ? d3.x : d2.x) : (ba ? d1.x : d0.x);
-          const T pi = bb ? (ba ? d3.y : d2.y) : (ba ? d1.y : d0.y);
-          const T xr = x[i].x, xi = x[i].y;
-          x[i].x = pr * xr - pi * xi;
-          x[i].y = pr * xi + pi * xr;
-        }
-      }
+  for (int i = 0; i < NR; ++i) {
+    const int s = (RA >= 0 ? (i >> (RA >= 0 ? RA : 0)) & 1 : 0) + 2 * (RB >= 0 ? (i >> (RB >= 0 ? RB : 0)) & 1 : 0);
+    if constexpr (REAL) {
+      x[i].x *= px[s];
+      x[i].y *= px[s];
+    } else {
+      const T xr = x[i].x, xi = x[i].y;
+      x[i].x = px[s] * xr - py[s] * xi;
+      x[i].y = px[s] * xi + py[s] * xr;
     }
   }
 }
 
-// Phases 1 .. n_phases - 1 of one tile: each exchanges the registers through LDS into the next
-// phase's layout and applies its operations; on return the layout is the last phase's.
+// The diagonal operations ph_diag[j0 .. j1) of a phase, all with real phases (REAL) or all with
+// complex ones.
+template <bool REAL, class T, int R>
+__device__ __forceinline__ void phase_diagonals(const GatePass<T>& P, RC<T> (&x)[1 << R], uint32_t row_g, int j0,
+                                                int j1) {
+  using C = RC<T>;
+  for (int j = j0; j < j1; ++j) {
+    const int o = P.ph_diag[j];
+    const T* u = P.coef + P.op_coef[o];
+    // OP_DIAG1 / OP_DIAG2: the phases d[b_a + 2 b_b] (a one-qubit diagonal takes b_b = 0 and
+    // lists its two phases twice)
+    const bool two = (P.op_type[o] == OP_DIAG2);
+    const C d0{u[0], u[1]}, d1{u[2], u[3]};
+    const C d2 = two ? C{u[4], u[5]} : d0, d3 = two ? C{u[6], u[7]} : d1;
+    const int code = P.op_code[o];
+    const int ra = code / 5 - 1, rb = code % 5 - 1;
+    const uint32_t ta = ra < 0 ? (row_g >> P.op_a[o]) & 1u : 0u;
+    const uint32_t tb = (two && rb < 0) ? (row_g >> P.op_b[o]) & 1u : 0u;
+    switch (code) {
+      case 0: reg_diag<-1, -1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 5: reg_diag<0, -1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 10: reg_diag<1, -1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 15: reg_diag<2, -1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 20: reg_diag<3, -1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 7: reg_diag<0, 1, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 8: reg_diag<0, 2, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 9: reg_diag<0, 3, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 13: reg_diag<1, 2, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      case 14: reg_diag<1, 3, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+      default: reg_diag<2, 3, REAL, T, R>(x, d0, d1, d2, d3, ta, tb); break;
+    }
+  }
+}
+
+// Operations of phase ph on the registers (row_g: the row index of register 0, whose register
+// bits are clear): a 2x2 gate on each register bit, then the phase's diagonal operations (see
+// GatePass).
 template <class T, int R>
-__device__ __forceinline__ void phase_rest(const GatePass<T>& P, RC<T> (&x)[1 << R], cx_t<T>* tile, int E, int cshift,
-                                           const uint32_t* slot_off, uint32_t base, bool live, uint32_t& pos,
-                                           uint32_t& sub, uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
+__device__ __forceinline__ void phase_apply(const GatePass<T>& P, int ph, RC<T> (&x)[1 << R], uint32_t row_g) {
+  static_assert(R == 4, "four register bits per phase");
+  const uint32_t g01 = P.ph_gc[ph][0], g23 = P.ph_gc[ph][1];
+  reg_1q<0, R, T>(x, P.coef + (g01 & 0xffffu));
+  reg_1q<1, R, T>(x, P.coef + (g01 >> 16));
+  reg_1q<2, R, T>(x, P.coef + (g23 & 0xffffu));
+  reg_1q<3, R, T>(x, P.coef + (g23 >> 16));
+  const uint32_t ut = P.ph_u[ph];
+  if (ut & (1u << 16)) {
+    // the product of the real diagonal operations on register bits only: one uniform real
+    // phase per register, in place
+    const T* uu = P.coef + (ut & 0xffffu);
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+      x[i].x *= uu[i];
+      x[i].y *= uu[i];
+    }
+  }
+  const uint32_t ops = P.ph_ops[ph];
+  const int j0 = (int)(ops & 255u), j1 = j0 + (int)((ops >> 8) & 255u), j2 = j1 + (int)((ops >> 16) & 255u);
+  if (j1 > j0) phase_diagonals<true, T, R>(P, x, row_g, j0, j1);
+  if (j2 > j1) phase_diagonals<false, T, R>(P, x, row_g, j1, j2);
+}
+
+// One phase's register <-> LDS exchange: the registers go to the tile in the current layout and
+// come back in phase ph's.
+template <class T, int R>
+__device__ __forceinline__ void phase_exchange(const GatePass<T>& P, int ph, RC<T> (&x)[1 << R], cx_t<T>* tile,
+                                               int cshift, uint32_t te, bool first, uint32_t& pos, uint32_t& sub,
+                                               uint32_t (&sh_pos)[R], uint32_t (&sh_row)[R]) {
   constexpr int NR = 1 << R;
-  for (int ph = 1; ph < P.n_phases; ++ph) {
-    if (live) {
+  if (!first) __syncthreads();   // the previous exchange's reads are done
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        cx_t<T> v;
-        v.x = x[i].x;
-        v.y = x[i].y;
-        tile[pos | pick_or<R>(i, sh_pos)] = v;
-      }
-    }
-    __syncthreads();
-    phase_layout<T, R>(P, ph, E, cshift, slot_off, pos, sub, sh_pos, sh_row);
-    if (live) {
+  for (int i = 0; i < NR; ++i) {
+    cx_t<T> v;
+    v.x = x[i].x;
+    v.y = x[i].y;
+    tile[pos | pick_or<R>(i, sh_pos)] = v;
+  }
+  __syncthreads();
+  phase_layout<T, R>(P, ph, cshift, te, pos, sub, sh_pos, sh_row);
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const cx_t<T> v = tile[pos | pick_or<R>(i, sh_pos)];
-        x[i] = RC<T>{v.x, v.y};
-      }
-      phase_apply<T, R>(P, ph, x, base | sub, sh_row);
-    }
-    if (ph + 1 < P.n_phases) __syncthreads();
+  for (int i = 0; i < NR; ++i) {
+    const cx_t<T> v = tile[pos | pick_or<R>(i, sh_pos)];
+    x[i] = RC<T>{v.x, v.y};
   }
 }
 
 // Apply the pass's operations phase by phase in registers, one tile: phase 0 reads from HBM and
-// the last phase writes to HBM (lanes run along the columns of a row); consecutive phases
-// exchange data through LDS.
-template <class T, int R>
+// the last phase writes to HBM (lanes run along the columns of a row); before every later phase
+// the registers go through LDS into that phase's layout.  NPH > 0: the pass has exactly NPH
+// phases (unrolled); 0: any number.  Threads beyond the 2^(E - R) distinct register groups
+// repeat a group (their LDS writes are the same values) and do not store, so that every thread
+// runs the same code and reaches every barrier.
+template <class T, int R, int NPH>
 __device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __restrict__ L, size_t ld,
-                                            cx_t<T>* tile, int cshift, uint32_t base,
-                                            const uint32_t* slot_off) {
+                                            cx_t<T>* tile, int cshift, uint32_t base) {
   constexpr int NR = 1 << R;
   const int E = P.k + cshift;
-  const bool live = threadIdx.x < (1u << (E - R));
+  const uint32_t groups = 1u << (E - R);
+  const uint32_t te = threadIdx.x & (groups - 1u);
   RC<T> x[NR];
   uint32_t pos = 0, sub = 0, sh_pos[R], sh_row[R];
-  phase_layout<T, R>(P, 0, E, cshift, slot_off, pos, sub, sh_pos, sh_row);
-  if (live) {
+  phase_layout<T, R>(P, 0, cshift, te, pos, sub, sh_pos, sh_row);
+  {
     const uint32_t col = pos & ((1u << cshift) - 1u);
+    const cx_t<T>* tp = L + (size_t)(base | sub) * ld + col;   // row offsets below are uniform
 #pragma unroll
-    for (int i = 0; i < NR; ++i) x[i] = ld_nt<T>(L + (size_t)(base | sub | pick_or<R>(i, sh_row)) * ld + col);
-    phase_apply<T, R>(P, 0, x, base | sub, sh_row);
+    for (int i = 0; i < NR; ++i) x[i] = ld_nt<T>(tp + (size_t)pick_or<R>(i, sh_row) * ld);
   }
-  phase_rest<T, R>(P, x, tile, E, cshift, slot_off, base, live, pos, sub, sh_pos, sh_row);
-  if (live) {
-    const uint32_t col = pos & ((1u << cshift) - 1u);
+  if constexpr (NPH > 0) {
 #pragma unroll
-    for (int i = 0; i < NR; ++i) st_nt<T>(L + (size_t)(base | sub | pick_or<R>(i, sh_row)) * ld + col, x[i]);
+    for (int ph = 0; ph < NPH; ++ph) {
+      if (ph > 0) phase_exchange<T, R>(P, ph, x, tile, cshift, te, ph == 1, pos, sub, sh_pos, sh_row);
+      phase_apply<T, R>(P, ph, x, base | sub);
+    }
+  } else {
+    for (int ph = 0; ph < P.n_phases; ++ph) {
+      if (ph > 0) phase_exchange<T, R>(P, ph, x, tile, cshift, te, ph == 1, pos, sub, sh_pos, sh_row);
+      phase_apply<T, R>(P, ph, x, base | sub);
+    }
+  }
+  if (threadIdx.x < groups) {
+    const uint32_t col = pos & ((1u << cshift) - 1u);
+    cx_t<T>* tp = L + (size_t)(base | sub) * ld + col;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) st_nt<T>(tp + (size_t)pick_or<R>(i, sh_row) * ld, x[i]);
   }
 }
 
+// Row index of the tile's first row: the tile index deposited into the non-local bit positions
+// (ascending local qubits).
 template <class T>
-__device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __restrict__ L, int cshift,
-                                               uint32_t tile_index) {
+__device__ __forceinline__ uint32_t tile_base(const GatePass<T>& P, uint32_t tile_index) {
+  uint32_t base = tile_index;
+  for (int j = 0; j < P.k; ++j) {
+    const int p = P.sorted_q[j];
+    base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
+  }
+  return base;
+}
+
+// One LDS sweep per operation over the tile (passes without register phases).
+template <class T>
+__device__ __forceinline__ void gate_sweep_body(const GatePass<T>& P, cx_t<T>* __restrict__ L, int cshift,
+                                                uint32_t base) {
   using C = cx_t<T>;
   extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
   C* tile = reinterpret_cast<C*>(gate_smem);   // [2^k][ncols]
@@ -252,19 +320,6 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
     slot_off[tid] = off;
   }
   __syncthreads();
-
-  // deposit the tile index into the non-local bit positions (ascending local qubits)
-  uint32_t base = tile_index;
-  for (int j = 0; j < k; ++j) {
-    const int p = P.sorted_q[j];
-    base = ((base >> p) << (p + 1)) | (base & ((1u << p) - 1u));
-  }
-  constexpr int RPH = 4;   // register slots per phase (kPhaseRegs on the host)
-  if (P.n_phases > 0) {
-    // register phases: the first reads from HBM, the last writes to HBM, LDS only in between
-    gate_phases<T, RPH>(P, L, ld, tile, cshift, base, slot_off);
-    return;
-  }
   const int elems = nc << k;
   // HBM -> LDS with 16-byte accesses, kUnroll loads in flight per thread before the LDS writes
   constexpr int CPU = 16 / (int)sizeof(C);   // complex values per 16-byte unit
@@ -364,27 +419,53 @@ __device__ __forceinline__ void gate_pass_body(const GatePass<T>& P, cx_t<T>* __
 }
 
 template <class T>
-__global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
-                                                        int cshift) {
-  gate_pass_body<T>(P, L, cshift, blockIdx.x);
+__device__ __forceinline__ void gate_phase_body(const GatePass<T>& P, cx_t<T>* __restrict__ L, int cshift,
+                                                uint32_t base, int nph) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
+  cx_t<T>* tile = reinterpret_cast<cx_t<T>*>(gate_smem);
+  const size_t ld = (size_t)P.ld;
+  switch (nph) {
+    case 1: gate_phases<T, 4, 1>(P, L, ld, tile, cshift, base); break;
+    case 2: gate_phases<T, 4, 2>(P, L, ld, tile, cshift, base); break;
+    case 3: gate_phases<T, 4, 3>(P, L, ld, tile, cshift, base); break;
+    default: gate_phases<T, 4, 0>(P, L, ld, tile, cshift, base); break;
+  }
 }
 
-
-// Register-phase passes over wide factors split the columns in two: a work-group owns one half
-// of a tile's columns (the gates act on rows only), 256 threads and half the LDS, so four
-// work-groups share a CU and their loads, phases and stores overlap more evenly.
+// Passes without register phases: one LDS sweep per operation.
 template <class T>
-__global__ __launch_bounds__(kGateThreads / 2, 4) void gate_pass_split_kernel(const GatePass<T> P,
-                                                                              cx_t<T>* __restrict__ L,
-                                                                              int cshift) {
-  const uint32_t half = blockIdx.x & 1u;
-  gate_pass_body<T>(P, L + (size_t)half * (1u << cshift), cshift, blockIdx.x >> 1);
+__global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<T> P, cx_t<T>* __restrict__ L,
+                                                        int cshift) {
+  gate_sweep_body<T>(P, L, cshift, tile_base(P, blockIdx.x));
+}
+
+// Register-phase passes, one kernel per phase count NPH (1 .. 3; 0: any), so that each unrolls
+// its phases.  SPLIT: the columns of a wide factor are split in two, a work-group owns one half
+// of a tile's columns (the gates act on rows only) with 256 threads and half the LDS, so four
+// work-groups share a CU and their loads, phases and stores overlap more evenly.
+template <class T, int NPH, bool SPLIT>
+__global__ __launch_bounds__(SPLIT ? kGateThreads / 2 : kGateThreads, SPLIT ? 4 : 1) void gate_phase_kernel(
+    const GatePass<T> pass, cx_t<T>* __restrict__ L, int cshift) {
+  // read the pass where the launch put it (the first kernel argument): uniform scalar loads,
+  // never a private copy of the whole structure
+  (void)pass;
+  const GatePass<T>& P = *(const GatePass<T>*)__builtin_amdgcn_kernarg_segment_ptr();
+  extern __shared__ __attribute__((aligned(16))) unsigned char gate_smem[];
+  cx_t<T>* tile = reinterpret_cast<cx_t<T>*>(gate_smem);
+  const uint32_t half = SPLIT ? (blockIdx.x & 1u) : 0u;
+  const uint32_t t = SPLIT ? (blockIdx.x >> 1) : blockIdx.x;
+  gate_phases<T, 4, NPH>(P, L + (size_t)half * (1u << cshift), (size_t)P.ld, tile, cshift, tile_base(P, t));
 }
 
 template <class T>
 __global__ __launch_bounds__(kGateThreads) void gate_pass_batched(const GateJob<T>* __restrict__ jobs, int njobs) {
   const int j = find_job(jobs, njobs, blockIdx.x);
-  gate_pass_body<T>(jobs[j].p, jobs[j].L, jobs[j].cshift, blockIdx.x - jobs[j].block0);
+  const GatePass<T>& P = jobs[j].p;
+  const uint32_t base = tile_base(P, blockIdx.x - jobs[j].block0);
+  if (P.n_phases > 0)
+    gate_phase_body<T>(P, jobs[j].L, jobs[j].cshift, base, P.n_phases);
+  else
+    gate_sweep_body<T>(P, jobs[j].L, jobs[j].cshift, base);
 }
 
 size_t gate_pass_shm(int ncols, int k, size_t csize, int n_phases) {
@@ -408,14 +489,34 @@ hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
   const size_t shm = gate_pass_shm(p.ncols, p.k, sizeof(cx_t<T>), p.n_phases);
   if (shm > 65536) return hipErrorInvalidValue;
   const uint32_t tiles = 1u << (p.n - p.k);
-  if constexpr (sizeof(T) == 4) {   // complex64 (the complex128 phases need more than 128 registers)
-    // passes with several operations (a lone gate streams slightly faster unsplit)
-    if (p.n_phases > 0 && p.n_ops > 2 && p.ncols >= 64 && p.k + cshift - 1 >= 8) {
-      // every live thread of the 256 holds 16 elements: 2^(k + cshift - 1) = 16 * 256 at most
-      hipLaunchKernelGGL(gate_pass_split_kernel<T>, dim3(2 * tiles), dim3(kGateThreads / 2), shm / 2, s, p, L,
-                         cshift - 1);
-      return hipGetLastError();
+  if (p.n_phases > 0) {
+    // passes with several operations split wide factors (a lone gate streams slightly faster
+    // unsplit); the complex128 phases need more than 128 registers, so they stay unsplit
+    const bool split = sizeof(T) == 4 && p.n_ops > 2 && p.ncols >= 64 && p.k + cshift - 1 >= 8;
+    const int cs = split ? cshift - 1 : cshift;
+    // each thread holds 16 elements: 2^(k + cs) = 16 * threads at most
+    if (p.k + cs - 4 > (split ? 8 : 9)) return hipErrorInvalidValue;
+    const dim3 grid(split ? 2 * tiles : tiles), block(split ? kGateThreads / 2 : kGateThreads);
+    const size_t sh = split ? shm / 2 : shm;
+    auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, grid, block, sh, s, p, L, cs); };
+    if constexpr (sizeof(T) == 4) {
+      if (split) {
+        switch (p.n_phases) {
+          case 1: go(gate_phase_kernel<T, 1, true>); break;
+          case 2: go(gate_phase_kernel<T, 2, true>); break;
+          case 3: go(gate_phase_kernel<T, 3, true>); break;
+          default: go(gate_phase_kernel<T, 0, true>); break;
+        }
+        return hipGetLastError();
+      }
     }
+    switch (p.n_phases) {
+      case 1: go(gate_phase_kernel<T, 1, false>); break;
+      case 2: go(gate_phase_kernel<T, 2, false>); break;
+      case 3: go(gate_phase_kernel<T, 3, false>); break;
+      default: go(gate_phase_kernel<T, 0, false>); break;
+    }
+    return hipGetLastError();
   }
   hipLaunchKernelGGL(gate_pass_kernel<T>, dim3(tiles), dim3(kGateThreads), shm, s, p, L, cshift);
   return hipGetLastError();

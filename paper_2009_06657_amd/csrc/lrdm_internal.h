@@ -24,9 +24,21 @@ enum GateOpType : int { OP_1Q = 0, OP_2Q = 1, OP_DIAG1 = 2, OP_DIAG2 = 3, OP_WEI
 // qubits; general 1q/2q gates act on local qubits, diagonal gates on any qubit (the full row
 // index is known).  Operations are applied in list order.
 // With n_phases > 0 the operations are applied in register phases: phase p holds the tile rows
-// that differ in the local slots ph_slots[p][0 .. 4) in
-// registers and applies operations [ph_first[p], ph_first[p] + ph_count[p]) there; every
-// non-diagonal operation of a phase acts on its slots (op_a is then the register bit).
+// that differ in 4 local slots in registers (ph_word[p] bits 4b .. 4b + 3: the slot of register
+// bit b; bits 16 + 4t ..: the other k - 4 local slots, ascending, which come from the thread
+// index).  It first applies one 2x2 gate on each register bit b, coefficients at offset
+// (ph_gc[p][b / 2] >> (16 * (b & 1))) & 0xffff (identity coefficients where the phase has fewer
+// gates; the gates act on distinct qubits, so their order is free), then its diagonal
+// operations, which commute with each other: those with real phases whose qubits are both
+// register bits as one product, the 16 real phases of the register patterns at coefficient
+// offset ph_u[p] & 0xffff (bit 16: present), then ph_diag[first .. first + nreal) with real phases
+// and ph_diag[first + nreal .. first + nreal + ncplx) with complex ones (ph_ops[p]: first in
+// bits 0 .. 7, nreal in bits 8 .. 15, ncplx in bits 16 .. 23).  A diagonal operation may act in
+// any phase between the gates on its qubits that precede it in list order and those that
+// follow it, so the list order's result is kept.  A listed diagonal operation carries its
+// register bits in op_code ((ra + 1) * 5 + rb + 1, -1: not a register bit of the phase), with a
+// register qubit first and two register qubits ascending (op_a / op_b and the middle two phases
+// swapped to match).
 // n_phases = 0: one LDS sweep per operation.
 template <class T> struct GatePass {
   int n, k, ld, ncols, n_ops, n_phases;
@@ -36,9 +48,12 @@ template <class T> struct GatePass {
   int op_a[kGateMaxOps];
   int op_b[kGateMaxOps];
   int op_coef[kGateMaxOps];
-  unsigned char ph_first[kGateMaxPhases];
-  unsigned char ph_count[kGateMaxPhases];
-  unsigned char ph_slots[kGateMaxPhases][5];
+  int op_code[kGateMaxOps];
+  int ph_diag[kGateMaxOps];
+  uint32_t ph_word[kGateMaxPhases];
+  uint32_t ph_ops[kGateMaxPhases];
+  uint32_t ph_gc[kGateMaxPhases][2];
+  uint32_t ph_u[kGateMaxPhases];
   T coef[kGateMaxCoef];
 };
 

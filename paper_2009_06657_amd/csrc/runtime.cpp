@@ -368,60 +368,156 @@ int local_budget(int n, int ncols, size_t csize) {
   return k;
 }
 
-// Register phases of a fused pass (see GatePass): consecutive operations share a phase while
-// the 1q operations among them act on at most kPhaseRegs distinct local slots; diagonal
-// operations join any phase.  Passes with other operation types keep the per-operation sweeps.
+// Register phases of a fused pass (see GatePass).  One-qubit gates join the current phase in
+// list order; a gate opens a new phase when the phase already has 4 gates, a gate on the same
+// qubit, or a diagonal operation on that qubit (which must act before it).  A diagonal
+// operation then moves, within the phases its qubits' gates allow, to one where the most of its
+// qubits are gate slots.  The register slots of a phase are its gates' slots, then local slots
+// of qubits its diagonal operations act on, then any others; register bits without a gate get
+// the identity.  The diagonal operations with real phases whose qubits are both register bits
+// multiply into one table of 16 phases per phase (a CZ layer costs one multiply per element),
+// the others stay listed.  Coefficients appended here (identity, tables) need room in coef; without it, or with
+// other operation types, the pass keeps the per-operation sweeps.
 constexpr int kPhaseRegs = 4;
 
 template <class T>
-void build_phases(GatePass<T>& p) {
+void build_phases(GatePass<T>& p, int& nc) {
   p.n_phases = 0;
-  if (p.k < kPhaseRegs) return;
+  if (p.k < kPhaseRegs || p.k > 8) return;
   for (int o = 0; o < p.n_ops; ++o)
     if (p.op_type[o] != OP_1Q && p.op_type[o] != OP_DIAG1 && p.op_type[o] != OP_DIAG2) return;
-  int nph = 0;
-  int first[kGateMaxOps], count[kGateMaxOps], slots[kGateMaxOps][kPhaseRegs], nsl[kGateMaxOps];
-  int regbit[kGateMaxOps];
-  auto open_phase = [&](int o) {
-    first[nph] = o;
-    count[nph] = 0;
-    nsl[nph] = 0;
-    ++nph;
+  struct Phase {
+    int ng = 0, gslot[kPhaseRegs] = {}, gcoef[kPhaseRegs] = {};
+    uint32_t gq = 0, dq = 0;   // qubits with a gate / touched by a diagonal operation
+    std::vector<int> diag;
   };
-  open_phase(0);
+  auto qmask = [&](int o) {
+    return (1u << p.op_a[o]) | (p.op_type[o] == OP_DIAG2 ? (1u << p.op_b[o]) : 0u);
+  };
+  std::vector<Phase> ph(1);
   for (int o = 0; o < p.n_ops; ++o) {
-    int ph = nph - 1;
     if (p.op_type[o] == OP_1Q) {
       const int slot = p.op_a[o];
-      int b = -1;
-      for (int i = 0; i < nsl[ph]; ++i)
-        if (slots[ph][i] == slot) b = i;
-      if (b < 0 && nsl[ph] == kPhaseRegs) {
-        open_phase(o);
-        ph = nph - 1;
+      const uint32_t qb = 1u << p.local_q[slot];
+      Phase* c = &ph.back();
+      if (c->ng == kPhaseRegs || (c->gq & qb) || (c->dq & qb)) {
+        ph.emplace_back();
+        c = &ph.back();
       }
-      if (b < 0) {
-        b = nsl[ph];
-        slots[ph][nsl[ph]++] = slot;
-      }
-      regbit[o] = b;
+      c->gslot[c->ng] = slot;
+      c->gcoef[c->ng] = p.op_coef[o];
+      ++c->ng;
+      c->gq |= qb;
+    } else {
+      ph.back().diag.push_back(o);
+      ph.back().dq |= qmask(o);
     }
-    ++count[ph];
   }
+  const int nph = (int)ph.size();
   if (nph > kGateMaxPhases) return;
-  for (int ph = 0; ph < nph; ++ph) {
-    // fill the register slots with unused local slots
-    for (int j = 0; j < p.k && nsl[ph] < kPhaseRegs; ++j) {
-      bool used = false;
-      for (int i = 0; i < nsl[ph]; ++i) used |= (slots[ph][i] == j);
-      if (!used) slots[ph][nsl[ph]++] = j;
+  // move each diagonal operation to the phase in its window with the most of its qubits gated
+  std::vector<std::vector<int>> diag(nph);
+  for (int c = 0; c < nph; ++c)
+    for (int o : ph[c].diag) {
+      const uint32_t qm = qmask(o);
+      int lo = c, hi = c;
+      while (lo > 0 && !(ph[lo].gq & qm)) --lo;
+      while (hi + 1 < nph && !(ph[hi + 1].gq & qm)) ++hi;
+      int best = c, best_n = __builtin_popcount(ph[c].gq & qm);
+      for (int t = lo; t <= hi; ++t) {
+        const int n = __builtin_popcount(ph[t].gq & qm);
+        if (n > best_n) best = t, best_n = n;
+      }
+      diag[best].push_back(o);
     }
-    p.ph_first[ph] = (unsigned char)first[ph];
-    p.ph_count[ph] = (unsigned char)count[ph];
-    for (int i = 0; i < kPhaseRegs; ++i) p.ph_slots[ph][i] = (unsigned char)slots[ph][i];
+  bool pad = false;
+  for (const Phase& c : ph) pad |= c.ng < kPhaseRegs;
+  int need = pad ? 8 : 0;
+  const int ident = nc;
+  if (nc + need > kGateMaxCoef) return;
+  if (pad) {
+    const T id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+    for (int i = 0; i < 8; ++i) p.coef[nc++] = id[i];
   }
-  for (int o = 0; o < p.n_ops; ++o)
-    if (p.op_type[o] == OP_1Q) p.op_a[o] = regbit[o];
+  int nd_total = 0;
+  for (int i = 0; i < nph; ++i) {
+    const Phase& c = ph[i];
+    uint32_t dq = 0;
+    for (int o : diag[i]) dq |= qmask(o);
+    int slots[8], ns = 0;
+    for (int g = 0; g < c.ng; ++g) slots[ns++] = c.gslot[g];
+    auto taken = [&](int j) {
+      for (int t = 0; t < ns; ++t)
+        if (slots[t] == j) return true;
+      return false;
+    };
+    for (int j = 0; j < p.k && ns < kPhaseRegs; ++j)
+      if ((dq >> p.local_q[j]) & 1u && !taken(j)) slots[ns++] = j;
+    for (int j = 0; j < p.k && ns < kPhaseRegs; ++j)
+      if (!taken(j)) slots[ns++] = j;
+    for (int j = 0; j < p.k; ++j)   // the thread-index slots, ascending
+      if (!taken(j)) slots[ns++] = j;
+    uint32_t w = 0;
+    for (int t = 0; t < p.k; ++t) w |= (uint32_t)slots[t] << (t < kPhaseRegs ? 4 * t : 16 + 4 * (t - kPhaseRegs));
+    p.ph_word[i] = w;
+    int gc[kPhaseRegs];
+    for (int g = 0; g < kPhaseRegs; ++g) gc[g] = g < c.ng ? c.gcoef[g] : ident;
+    p.ph_gc[i][0] = (uint32_t)gc[0] | ((uint32_t)gc[1] << 16);
+    p.ph_gc[i][1] = (uint32_t)gc[2] | ((uint32_t)gc[3] << 16);
+    auto reg = [&](int q) {
+      for (int t = 0; t < kPhaseRegs; ++t)
+        if (p.local_q[slots[t]] == q) return t;
+      return -1;
+    };
+    // listed: real phases first, then complex ones
+    auto is_real = [&](int o) {
+      const T* u = p.coef + p.op_coef[o];
+      const int nphase = p.op_type[o] == OP_DIAG2 ? 4 : 2;
+      for (int t = 0; t < nphase; ++t)
+        if (u[2 * t + 1] != 0) return false;
+      return true;
+    };
+    std::vector<int> regd, rest;
+    for (int o : diag[i]) {
+      const bool two = p.op_type[o] == OP_DIAG2;
+      const bool inreg = reg(p.op_a[o]) >= 0 && (!two || reg(p.op_b[o]) >= 0);
+      (inreg && is_real(o) ? regd : rest).push_back(o);
+    }
+    p.ph_u[i] = 0;
+    if (!regd.empty() && nc + 16 <= kGateMaxCoef) {
+      for (int e = 0; e < 16; ++e) {
+        double v = 1;
+        for (int o : regd) {
+          const T* u = p.coef + p.op_coef[o];
+          const bool two = p.op_type[o] == OP_DIAG2;
+          const int ba = (e >> reg(p.op_a[o])) & 1, bb = two ? (e >> reg(p.op_b[o])) & 1 : 0;
+          v *= (double)u[2 * (ba + 2 * bb)];
+        }
+        p.coef[nc + e] = (T)v;
+      }
+      p.ph_u[i] = (uint32_t)nc | (1u << 16);
+      nc += 16;
+    } else {
+      rest.insert(rest.end(), regd.begin(), regd.end());
+    }
+    std::stable_partition(rest.begin(), rest.end(), is_real);
+    int nreal = 0;
+    for (int o : rest) nreal += is_real(o);
+    p.ph_ops[i] = (uint32_t)nd_total | ((uint32_t)nreal << 8) | ((uint32_t)(rest.size() - nreal) << 16);
+    for (int o : rest) {
+      p.ph_diag[nd_total++] = o;
+      const bool two = p.op_type[o] == OP_DIAG2;
+      int ra = reg(p.op_a[o]), rb = two ? reg(p.op_b[o]) : -1;
+      if (rb >= 0 && (ra < 0 || rb < ra)) {
+        std::swap(p.op_a[o], p.op_b[o]);
+        std::swap(ra, rb);
+        T* u = p.coef + p.op_coef[o];   // phases of b_a + 2 b_b = 1 and 2 trade places
+        std::swap(u[2], u[4]);
+        std::swap(u[3], u[5]);
+      }
+      p.op_code[o] = (ra + 1) * 5 + (rb + 1);
+    }
+  }
   p.n_phases = nph;
 }
 
@@ -473,7 +569,7 @@ lrdm_status flush_gates_t(lrdm_t h) {
     for (int j = 0; j < nloc; ++j) sorted[j] = p.local_q[j];
     std::sort(sorted, sorted + nloc);
     for (int j = 0; j < nloc; ++j) p.sorted_q[j] = sorted[j];
-    build_phases(p);
+    build_phases(p, nc);
     if (h->rec) {
       if constexpr (sizeof(T) == 4) {
         GateJob<float> j;

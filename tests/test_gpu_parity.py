@@ -96,6 +96,51 @@ def test_gate_sweeps_elementwise(lr, dtype, n, r):
     dm.close()
 
 
+def phase_gate_program(n, r, seed, count=80, dtype="c64"):
+    """One-qubit gates and diagonal gates only, so that every gate pass runs in register phases:
+    CZ, Z(x)Z-type sign patterns, diagonals with some phases exactly 1, controlled phases, Z, S,
+    T and Rz, on random qubits (register bits, thread bits and tile bits of a pass)."""
+    rng = np.random.default_rng(seed)
+    ops = []
+    for _ in range(count):
+        kind = int(rng.integers(0, 8))
+        q0, q1 = (int(x) for x in rng.choice(n, 2, replace=False))
+        if kind <= 1:
+            ops.append(C.Gate((q0,), C.haar_su2(np.random.Generator(np.random.PCG64(int(rng.integers(1 << 30)))))))
+        elif kind == 2:
+            ops.append(C.Gate((q0, q1), C.CZ, diagonal=True))
+        elif kind == 3:
+            ops.append(C.Gate((q0, q1), np.diag(rng.choice([-1.0, 1.0], 4)).astype(np.complex128), diagonal=True))
+        elif kind == 4:
+            ops.append(C.Gate((q0, q1), np.diag([1, 1, 1, np.exp(1j * rng.uniform(-3, 3))]), diagonal=True))
+        elif kind == 5:
+            ops.append(C.Gate((q0,), [C.Z, C.S, C.T, C.rz(rng.uniform(-3, 3))][int(rng.integers(0, 4))]))
+        elif kind == 6:
+            ops.append(C.Gate((q0, q1), np.diag([1.0, -1.0, 1.0, 1.0]).astype(np.complex128), diagonal=True))
+        else:
+            ops.append(C.Gate((q0,), [C.H, C.X][int(rng.integers(0, 2))]))
+    return C.Program(n, ops, r, dtype, 2, "phases")
+
+
+@pytest.mark.parametrize("dtype,n,r", [("c64", 7, 8), ("c64", 8, 64), ("c64", 11, 64), ("c128", 8, 32),
+                                       ("c128", 10, 32)])
+def test_register_phase_passes_elementwise(lr, dtype, n, r):
+    """Passes of one-qubit and diagonal gates (the register-phase form of a gate pass), with the
+    diagonal qubits in every combination of register, thread and tile bits, element by element
+    against the oracle's gate contractions (Eq. "low rank evolution G")."""
+    _say(f"[phase gates] dtype={dtype} n={n} r={r}")
+    prog = phase_gate_program(n, r, seed=n * 31 + r, dtype=dtype)
+    L0 = cast_input(C.random_orthogonal_factor(n, r, seed=11 + n), dtype)
+    dm = run_gpu(lr, prog, L0)
+    got = dm.get_L()[:, :r]
+    ref = oracle.run_lret(prog, L0)
+    tol = 2e-6 if dtype == "c64" else 1e-13
+    err = float(np.max(np.abs(got - ref)))
+    _say(f"  max|dL| {err:.2e}")
+    assert err < tol
+    dm.close()
+
+
 # ------------------------------------------------------------------------------- one compression
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("chan", ["ad", "dep", "deph", "none"])

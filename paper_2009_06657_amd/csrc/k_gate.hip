@@ -199,16 +199,17 @@ __device__ __forceinline__ void phase_diagonals(const GatePass<T>& P, RC<T> (&x)
 }
 
 // Operations of phase ph on the registers (row_g: the row index of register 0, whose register
-// bits are clear): a 2x2 gate on each register bit, then the phase's diagonal operations (see
-// GatePass).
-template <class T, int R>
+// bits are clear): a 2x2 gate on each register bit b < NG (the host puts the identity on the
+// bits without a gate; NG < 4 leaves them out, for a last phase of NG gates), then the phase's
+// diagonal operations (see GatePass).
+template <class T, int R, int NG = 4>
 __device__ __forceinline__ void phase_apply(const GatePass<T>& P, int ph, RC<T> (&x)[1 << R], uint32_t row_g) {
   static_assert(R == 4, "four register bits per phase");
   const uint32_t g01 = P.ph_gc[ph][0], g23 = P.ph_gc[ph][1];
-  reg_1q<0, R, T>(x, P.coef + (g01 & 0xffffu));
-  reg_1q<1, R, T>(x, P.coef + (g01 >> 16));
-  reg_1q<2, R, T>(x, P.coef + (g23 & 0xffffu));
-  reg_1q<3, R, T>(x, P.coef + (g23 >> 16));
+  if constexpr (NG > 0) reg_1q<0, R, T>(x, P.coef + (g01 & 0xffffu));
+  if constexpr (NG > 1) reg_1q<1, R, T>(x, P.coef + (g01 >> 16));
+  if constexpr (NG > 2) reg_1q<2, R, T>(x, P.coef + (g23 & 0xffffu));
+  if constexpr (NG > 3) reg_1q<3, R, T>(x, P.coef + (g23 >> 16));
   const uint32_t ut = P.ph_u[ph];
   if (ut & (1u << 16)) {
     // the product of the real diagonal operations on register bits only: one uniform real
@@ -253,10 +254,10 @@ __device__ __forceinline__ void phase_exchange(const GatePass<T>& P, int ph, RC<
 // Apply the pass's operations phase by phase in registers, one tile: phase 0 reads from HBM and
 // the last phase writes to HBM (lanes run along the columns of a row); before every later phase
 // the registers go through LDS into that phase's layout.  NPH > 0: the pass has exactly NPH
-// phases (unrolled); 0: any number.  Threads beyond the 2^(E - R) distinct register groups
-// repeat a group (their LDS writes are the same values) and do not store, so that every thread
-// runs the same code and reaches every barrier.
-template <class T, int R, int NPH>
+// phases (unrolled), the last of them applying GL gates; 0: any number.  Threads beyond the
+// 2^(E - R) distinct register groups repeat a group (their LDS writes are the same values) and
+// do not store, so that every thread runs the same code and reaches every barrier.
+template <class T, int R, int NPH, int GL = 4>
 __device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __restrict__ L, size_t ld,
                                             cx_t<T>* tile, int cshift, uint32_t base) {
   constexpr int NR = 1 << R;
@@ -276,7 +277,10 @@ __device__ __forceinline__ void gate_phases(const GatePass<T>& P, cx_t<T>* __res
 #pragma unroll
     for (int ph = 0; ph < NPH; ++ph) {
       if (ph > 0) phase_exchange<T, R>(P, ph, x, tile, cshift, te, ph == 1, pos, sub, sh_pos, sh_row);
-      phase_apply<T, R>(P, ph, x, base | sub);
+      if (ph + 1 < NPH)
+        phase_apply<T, R>(P, ph, x, base | sub);
+      else
+        phase_apply<T, R, GL>(P, ph, x, base | sub);
     }
   } else {
     for (int ph = 0; ph < P.n_phases; ++ph) {
@@ -440,10 +444,10 @@ __global__ __launch_bounds__(kGateThreads) void gate_pass_kernel(const GatePass<
 }
 
 // Register-phase passes, one kernel per phase count NPH (1 .. 3; 0: any), so that each unrolls
-// its phases.  SPLIT: the columns of a wide factor are split in two, a work-group owns one half
-// of a tile's columns (the gates act on rows only) with 256 threads and half the LDS, so four
-// work-groups share a CU and their loads, phases and stores overlap more evenly.
-template <class T, int NPH, bool SPLIT>
+// its phases, and (wide passes) per gate count GL of the last phase.  SPLIT: the columns of a
+// wide factor are split in two, a work-group owns one half of a tile's columns (the gates act on
+// rows only) with 256 threads and half the LDS, so that five work-groups share a CU.
+template <class T, int NPH, bool SPLIT, int GL>
 __global__ __launch_bounds__(SPLIT ? kGateThreads / 2 : kGateThreads, SPLIT ? 4 : 1) void gate_phase_kernel(
     const GatePass<T> pass, cx_t<T>* __restrict__ L, int cshift) {
   // read the pass where the launch put it (the first kernel argument): uniform scalar loads,
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(SPLIT ? kGateThreads / 2 : kGateThreads, SPLIT ? 4 
   cx_t<T>* tile = reinterpret_cast<cx_t<T>*>(gate_smem);
   const uint32_t half = SPLIT ? (blockIdx.x & 1u) : 0u;
   const uint32_t t = SPLIT ? (blockIdx.x >> 1) : blockIdx.x;
-  gate_phases<T, 4, NPH>(P, L + (size_t)half * (1u << cshift), (size_t)P.ld, tile, cshift, tile_base(P, t));
+  gate_phases<T, 4, NPH, GL>(P, L + (size_t)half * (1u << cshift), (size_t)P.ld, tile, cshift, tile_base(P, t));
 }
 
 template <class T>
@@ -500,21 +504,34 @@ hipError_t launch_gate_pass(const GatePass<T>& p, cx_t<T>* L, hipStream_t s) {
     const size_t sh = split ? shm / 2 : shm;
     auto go = [&](auto kernel) { hipLaunchKernelGGL(kernel, grid, block, sh, s, p, L, cs); };
     if constexpr (sizeof(T) == 4) {
-      if (split) {
+      if (split && p.n_phases >= 1 && p.n_phases <= 3) {
+        const int gl = std::min(std::max(p.last_gates, 0), 4);
+#define LRDM_SPLIT_GL(NPH)                                      \
+  switch (gl) {                                                 \
+    case 0: go(gate_phase_kernel<T, NPH, true, 0>); break;      \
+    case 1: go(gate_phase_kernel<T, NPH, true, 1>); break;      \
+    case 2: go(gate_phase_kernel<T, NPH, true, 2>); break;      \
+    case 3: go(gate_phase_kernel<T, NPH, true, 3>); break;      \
+    default: go(gate_phase_kernel<T, NPH, true, 4>); break;     \
+  }
         switch (p.n_phases) {
-          case 1: go(gate_phase_kernel<T, 1, true>); break;
-          case 2: go(gate_phase_kernel<T, 2, true>); break;
-          case 3: go(gate_phase_kernel<T, 3, true>); break;
-          default: go(gate_phase_kernel<T, 0, true>); break;
+          case 1: LRDM_SPLIT_GL(1); break;
+          case 2: LRDM_SPLIT_GL(2); break;
+          default: LRDM_SPLIT_GL(3); break;
         }
+#undef LRDM_SPLIT_GL
+        return hipGetLastError();
+      }
+      if (split) {
+        go(gate_phase_kernel<T, 0, true, 4>);
         return hipGetLastError();
       }
     }
     switch (p.n_phases) {
-      case 1: go(gate_phase_kernel<T, 1, false>); break;
-      case 2: go(gate_phase_kernel<T, 2, false>); break;
-      case 3: go(gate_phase_kernel<T, 3, false>); break;
-      default: go(gate_phase_kernel<T, 0, false>); break;
+      case 1: go(gate_phase_kernel<T, 1, false, 4>); break;
+      case 2: go(gate_phase_kernel<T, 2, false, 4>); break;
+      case 3: go(gate_phase_kernel<T, 3, false, 4>); break;
+      default: go(gate_phase_kernel<T, 0, false, 4>); break;
     }
     return hipGetLastError();
   }

@@ -42,6 +42,7 @@ enum GateOpType : int { OP_1Q = 0, OP_2Q = 1, OP_DIAG1 = 2, OP_DIAG2 = 3, OP_WEI
 // n_phases = 0: one LDS sweep per operation.
 template <class T> struct GatePass {
   int n, k, ld, ncols, n_ops, n_phases;
+  int last_gates;      // one-qubit gates of the last phase (its other register bits get the identity)
   int local_q[8];      // local bit j <-> qubit local_q[j]
   int sorted_q[8];     // the same qubits in ascending order (row-index deposit)
   int op_type[kGateMaxOps];

@@ -518,6 +518,7 @@ void build_phases(GatePass<T>& p, int& nc) {
       p.op_code[o] = (ra + 1) * 5 + (rb + 1);
     }
   }
+  p.last_gates = ph.back().ng;
   p.n_phases = nph;
 }
 

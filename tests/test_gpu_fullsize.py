@@ -106,7 +106,7 @@ def test_gate_layer_n20_elementwise(lr):
 
 
 @pytest.mark.parametrize("overlap", [0, 1])
-@pytest.mark.parametrize("layers", [1, 4])
+@pytest.mark.parametrize("layers", [1, 4, 40])
 def test_brickwork_n20_r64_against_oracle(lr, layers, overlap):
     """Also with LRDM_FLAG_OVERLAP (the split Gram of the next qubit from the 4-way Gram of the
     bit pair, eigensolves on a second stream), the configuration the benchmark times."""

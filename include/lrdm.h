@@ -186,8 +186,9 @@ lrdm_status lrdm_synchronize(lrdm_t h);
  * LRDM_FLAG_OVERLAP, of the pair transform, 6 = the 4-way Gram of a bit pair (LRDM_FLAG_OVERLAP:
  * its two passes over L and their reduction).  Between lrdm_timing_begin and
  * lrdm_timing_end every launch of that class is bracketed by HIP events on the stream it runs
- * on; lrdm_timing_end synchronises and returns the number of launches and their mean
- * duration in milliseconds.  At most 65536 launches are recorded. */
+ * on (the gate passes of one flush, launched back to back, by one pair around them all);
+ * lrdm_timing_end synchronises and returns the number of launches and their mean duration in
+ * milliseconds.  At most 65536 event pairs are recorded. */
 lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class);
 
 /* Launch shapes the autotuner (paper_2009_06657_amd/autotune.py) chooses per workload; they

@@ -180,6 +180,7 @@ struct lrdm_ctx {
   // timing
   int timing_class = -1;
   std::vector<hipEvent_t> ev;
+  std::vector<int> ev_launches;   // launches inside each recorded event pair
   int ev_used = 0;
   // host staging
   std::vector<uint64_t> term_stage;
@@ -265,9 +266,10 @@ void timed_begin(lrdm_t h, int cls, hipStream_t s = nullptr) {
   if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
   hipEventRecord(h->ev[h->ev_used], s ? s : h->stream);
 }
-void timed_end(lrdm_t h, int cls, hipStream_t s = nullptr) {
+void timed_end(lrdm_t h, int cls, hipStream_t s = nullptr, int launches = 1) {
   if (h->timing_class != cls || h->ev_used + 2 > (int)h->ev.size()) return;
   hipEventRecord(h->ev[h->ev_used + 1], s ? s : h->stream);
+  h->ev_launches[h->ev_used / 2] = launches;
   h->ev_used += 2;
 }
 
@@ -528,6 +530,7 @@ lrdm_status flush_gates_t(lrdm_t h) {
   if (h->tune.gate_local_max) kloc_max = std::min(kloc_max, h->tune.gate_local_max);
   std::vector<char> placed(h->gates.size(), 0);
   size_t remaining = h->gates.size();
+  int npass = 0;
   while (remaining > 0) {
     GatePass<T> p;
     std::memset(&p, 0, sizeof(p));
@@ -589,10 +592,11 @@ lrdm_status flush_gates_t(lrdm_t h) {
       }
       continue;
     }
-    timed_begin(h, 0);
+    // the passes of one flush run back to back on the stream: one event pair brackets them all
+    if (npass++ == 0) timed_begin(h, 0);
     HIPCHK(h, launch_gate_pass<T>(p, static_cast<cx_t<T>*>(h->state), h->stream));
-    timed_end(h, 0);
   }
+  if (npass) timed_end(h, 0, nullptr, npass);
   h->gates.clear();
   return LRDM_OK;
 }
@@ -1655,6 +1659,7 @@ lrdm_status lrdm_timing_begin(lrdm_t h, int kernel_class) {
   if (kernel_class < 0 || kernel_class > 6) return fail(h, LRDM_E_ARG, "kernel_class must be in [0, 6]");
   if (h->ev.empty()) {
     h->ev.resize(2 * kMaxTimed);
+    h->ev_launches.assign(kMaxTimed, 1);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   }
   h->timing_class = kernel_class;
@@ -1671,11 +1676,13 @@ lrdm_status lrdm_timing_end(lrdm_t h, int* launches, double* mean_ms, double* to
     HIPCHK(h, hipStreamSynchronize(h->aux));
   }
   double tot = 0;
-  const int nl = h->ev_used / 2;
-  for (int i = 0; i < nl; ++i) {
+  const int npairs = h->ev_used / 2;
+  int nl = 0;
+  for (int i = 0; i < npairs; ++i) {
     float ms = 0;
     HIPCHK(h, hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
     tot += ms;
+    nl += h->ev_launches[i];
   }
   if (launches) *launches = nl;
   if (total_ms) *total_ms = tot;

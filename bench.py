@@ -657,7 +657,7 @@ def main():
     elapsed = time.perf_counter() - t0
 
     # per-class kernel times: one further step per class, every launch of that class bracketed
-    # by HIP events on the stream it runs on
+    # by HIP events on the stream it runs on (a flush's back-to-back gate passes by one pair)
     br = {}
     for cls in (() if args.no_breakdown else (0, 1, 2, 3, 4, 5, 6)):
         dm.timing_begin(cls)

@@ -17,6 +17,8 @@
 // 128-byte line that a wave writes with consecutive stores, non-temporal ones reached HBM as
 // partial lines and raised the written bytes by a third).  Every row is read before any row is
 // written, and no other work-group touches these rows.
+#include <algorithm>
+
 #include "lrdm_internal.h"
 
 namespace lrdm {
@@ -252,6 +254,121 @@ hipError_t launch_project_batched(int FO, const ProjJob<T>* jobs, int njobs, uin
   return hipGetLastError();
 }
 
+// Resident-W projection for the wide split view in complex64 (c_in = c_out = 64: X is
+// 2^(n-1) x 128 complex, W 128 x 128 complex).  Every work-group copies W once into LDS as two
+// real planes (rows padded to 130 floats: the four lane groups of a wave read rows 8 apart, which
+// then fall on different banks) and keeps it there; each wave then streams its own 16-row blocks
+// of X from HBM straight into registers (the next block's loads in flight while it works on the
+// current one), so there is no barrier after the copy of W.  The complex product takes four real
+// MFMAs per (k, tile): Y_re += W_re x X_re + W_im x (-X_im), Y_im += W_im x X_re + W_re x X_im.
+// Lane group g = lane / 16 takes k = 32 c + 8 g + j (j < 8) of K chunk c, so a lane's operand of
+// X for a whole chunk is 8 consecutive complex values of its row (64 bytes); W is read at the same
+// k.  Rows are read before they are written, by the same wave only.
+constexpr int kPRThreads = 256;        // 4 waves, one per SIMD (the whole register file each)
+constexpr int kPRK = 128;              // complex K (both halves of X)
+constexpr int kPRO = 128;              // complex outputs (both halves)
+constexpr int kPRS = 130;              // LDS row stride of a W plane (floats)
+constexpr size_t kPRShm = (size_t)2 * kPRK * kPRS * sizeof(float);
+
+__device__ __forceinline__ uint32_t pr_row(uint32_t y, int h, int q) {
+  return ((y >> q) << (q + 1)) | (y & ((1u << q) - 1u)) | ((uint32_t)h << q);
+}
+
+// one half of X row y (complex columns 64 h .. 64 h + 63): chunks 2 h and 2 h + 1
+__device__ __forceinline__ void pr_load_half(const float2* __restrict__ L, int ld, int q, uint32_t y, int h, int kq,
+                                             pv4f (&x)[2][4]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const float2* src = L + (size_t)pr_row(y, h, q) * ld + 32 * c + 8 * kq;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[c][u] = *reinterpret_cast<const pv4f*>(src + 2 * u);
+  }
+}
+
+// the MFMAs of input half h (chunks 2 h, 2 h + 1) into the output tiles t0 .. t0 + 3
+__device__ __forceinline__ void pr_half(const float* __restrict__ wre, const float* __restrict__ wim, int h, int kq,
+                                        int m, int t0, const pv4f (&x)[2][4], pv4f (&ar)[8], pv4f (&ai)[8]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 32 * (2 * h + c) + 8 * kq + j;
+      const float xr = x[c][j >> 1][2 * (j & 1)], xi = x[c][j >> 1][2 * (j & 1) + 1];
+      const float* wr = wre + k * kPRS + m;
+      const float* wi = wim + k * kPRS + m;
+#pragma unroll
+      for (int t = t0; t < t0 + 4; ++t) {
+        const float a_r = wr[16 * t], a_i = wi[16 * t];
+        ar[t] = pmfma16(a_r, xr, ar[t]);
+        ar[t] = pmfma16(a_i, -xi, ar[t]);
+        ai[t] = pmfma16(a_i, xr, ai[t]);
+        ai[t] = pmfma16(a_r, xi, ai[t]);
+      }
+    }
+}
+
+__global__ __launch_bounds__(kPRThreads, 1) void project_resident_kernel(float2* __restrict__ L, int ld, int q,
+                                                                         const float2* __restrict__ W, int skip,
+                                                                         uint32_t rows) {
+  extern __shared__ __attribute__((aligned(16))) float prs[];
+  float* wre = prs;
+  float* wim = prs + kPRK * kPRS;
+  for (int e = threadIdx.x; e < kPRK * kPRO; e += kPRThreads) {
+    const float2 w = W[e];
+    const int k = e / kPRO, o = e % kPRO;
+    wre[k * kPRS + o] = w.x;
+    wim[k * kPRS + o] = w.y;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const uint32_t nblk = rows / 16;
+  const uint32_t step = gridDim.x * (kPRThreads / 64);
+  uint32_t b = blockIdx.x * (kPRThreads / 64) + wave;
+  // output half 1 from input half 0 is zero (skip & 1), output half 0 from input half 1 (skip & 2)
+  const bool z10 = (skip & 1) != 0, z01 = (skip & 2) != 0;
+  // x0: the input half 0 of the current block (its loads issued one half ahead), x1: half 1
+  pv4f x0[2][4], x1[2][4];
+  if (b < nblk) pr_load_half(L, ld, q, 16 * b + m, 0, kq, x0);
+  for (; b < nblk; b += step) {
+    const uint32_t y = 16 * b + m;
+    pr_load_half(L, ld, q, y, 1, kq, x1);
+    pv4f ar[8], ai[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      ar[t] = pv4f{0, 0, 0, 0};
+      ai[t] = pv4f{0, 0, 0, 0};
+    }
+    pr_half(wre, wim, 0, kq, m, 0, x0, ar, ai);
+    if (!z10) pr_half(wre, wim, 0, kq, m, 4, x0, ar, ai);
+    if (b + step < nblk) pr_load_half(L, ld, q, 16 * (b + step) + m, 0, kq, x0);
+    if (!z01) pr_half(wre, wim, 1, kq, m, 0, x1, ar, ai);
+    pr_half(wre, wim, 1, kq, m, 4, x1, ar, ai);
+    // lane (kq, m) holds output columns 16 t + 4 kq + v (v < 4) of row m
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      float2* dst = L + (size_t)pr_row(y, t >> 2, q) * ld + ((16 * t + 4 * kq) & 63);
+      *reinterpret_cast<pv4f*>(dst) = pv4f{ar[t][0], ai[t][0], ar[t][1], ai[t][1]};
+      *reinterpret_cast<pv4f*>(dst + 2) = pv4f{ar[t][2], ai[t][2], ar[t][3], ai[t][3]};
+    }
+  }
+}
+
+static hipError_t launch_project_resident(float2* L, int n, int ld, int q, const float2* W, int skip, int cus,
+                                          hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(project_resident_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPRShm);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const uint32_t rows = 1u << (n - 1);
+  const uint32_t wgs = (uint32_t)std::max(1, std::min(cus > 0 ? cus : 256, 1024));
+  hipLaunchKernelGGL(project_resident_kernel, dim3(wgs), dim3(kPRThreads), kPRShm, s, L, ld, q, W, skip, rows);
+  return hipGetLastError();
+}
+
 template <class T, int FO>
 static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
                                 const cx_t<T>* W, int skip, hipStream_t s) {
@@ -268,8 +385,12 @@ static hipError_t launch_proj_f(cx_t<T>* L, int n, int ld, int c_in, int nsplit,
 
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
-                          const cx_t<T>* W, int skip, hipStream_t s) {
+                          const cx_t<T>* W, int skip, hipStream_t s, int cus) {
   const int FO = 2 * nsplit * c_out;
+  if constexpr (sizeof(T) == 4) {
+    if (nsplit == 2 && c_in == 64 && c_out == 64 && n >= 8 && ld >= 64 && q >= 0 && q < n)
+      return launch_project_resident(L, n, ld, q, W, skip, cus, s);
+  }
   switch (FO) {
     case 16: return launch_proj_f<T, 16>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
     case 32: return launch_proj_f<T, 32>(L, n, ld, c_in, nsplit, q, c_out, W, skip, s);
@@ -315,7 +436,7 @@ template hipError_t launch_project4<float>(float2*, int, int, int, int, int, int
 template hipError_t launch_project4<double>(double2*, int, int, int, int, int, int, const double2*, hipStream_t);
 template hipError_t launch_project_batched<float>(int, const ProjJob<float>*, int, uint32_t, hipStream_t);
 template hipError_t launch_project_batched<double>(int, const ProjJob<double>*, int, uint32_t, hipStream_t);
-template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, int, hipStream_t);
-template hipError_t launch_project<double>(double2*, int, int, int, int, int, int, const double2*, int, hipStream_t);
+template hipError_t launch_project<float>(float2*, int, int, int, int, int, int, const float2*, int, hipStream_t, int);
+template hipError_t launch_project<double>(double2*, int, int, int, int, int, int, const double2*, int, hipStream_t, int);
 
 }  // namespace lrdm

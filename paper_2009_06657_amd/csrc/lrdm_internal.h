@@ -219,7 +219,7 @@ hipError_t launch_eig(const double* S, int Fc, const Channel& ch, int nsplit, in
 // value of the qubit to the other); those MFMAs are left out.
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int q, int c_out,
-                          const cx_t<T>* W, int skip, hipStream_t s);
+                          const cx_t<T>* W, int skip, hipStream_t s, int cus = 0);   // cus: CUs of s
 
 // Projection of a channel on the qubit pair (q0, q1): the 4-way view X4 = [L_0 | L_1 | L_2 | L_3]
 // (u = b(q0) + 2 b(q1), 2^(n-2) rows) times W (4c x 4c_out), in place.

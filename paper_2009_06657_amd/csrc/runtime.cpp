@@ -701,7 +701,7 @@ lrdm_status settle_t(lrdm_t h) {
     }
     timed_begin(h, 4, gs);
     HIPCHK(h, launch_project<T>(static_cast<cx_t<T>*>(h->state), h->n, h->lay.ld, c, 2, h->pend_q, c,
-                                h->w_bulk<T>(h->wslot), h->pend_skip, gs));
+                                h->w_bulk<T>(h->wslot), h->pend_skip, gs, h->overlap ? h->gemm_cus : h->ncu));
     timed_end(h, 4, gs);
   }
   return join_aux(h);   // overlap mode: the caller's stream after both of the handle's streams
@@ -857,7 +857,8 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
     // ... then that projection, once its W is ready
     HIPCHK(h, hipStreamWaitEvent(gs, h->ev_b2g, 0));
     timed_begin(h, 4, gs);
-    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, 2, p, c, h->w_bulk<T>(h->wslot), h->pend_skip, gs));
+    HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, 2, p, c, h->w_bulk<T>(h->wslot), h->pend_skip, gs,
+                                h->overlap ? h->gemm_cus : h->ncu));
     timed_end(h, 4, gs);
     h->proj_pending = false;
     // aux: the split Gram on q of the projected factor, from G4 and the projection's FP64 W
@@ -905,7 +906,7 @@ lrdm_status compress_t(lrdm_t h, int r_target, double eps, int tie, int renorm, 
   } else {
     timed_begin(h, 4);
     HIPCHK(h, launch_project<T>(L, h->n, h->lay.ld, c, nsplit, q, c_out, W,
-                                nsplit == 2 ? reach_skip(channel_reach(ch)) : 0, h->stream));
+                                nsplit == 2 ? reach_skip(channel_reach(ch)) : 0, h->stream, h->ncu));
     timed_end(h, 4);
   }
   h->ncols = c_out;

@@ -560,6 +560,240 @@ int gram4_blocks_cross(int n) {
   return (int)(chunks < 256 ? chunks : 256);
 }
 
+// The whole 4-way Gram G4 = Y^H Y for c = 64 in complex64, streamed through registers.  Row y of
+// Y (256 complex) is the four rows of L with the bit pair (p, q) = (0,0), (1,0), (0,1), (1,1)
+// inserted, so column group G (16 columns) of Y is columns 16 (G mod 4) of the L row of segment
+// G / 4.  A lane (g, m) of a wave holds Y[y0 + g][16 G + m] for the groups G it needs: these are
+// the MFMA operands of the 16 x 16 blocks (I, J) over a 4-row step, so the 136 upper blocks
+// accumulate with no LDS and no barrier: S_IJ += Y_I^H Y_J as Re += Yr_I Yr_J + Yi_I Yi_J and
+// Im += Yr_I Yi_J - Yi_I Yr_J.  On a diagonal block Im is A - A^T with A = Yr_I^T Yi_I, so one
+// MFMA gives it and the reduction takes the antisymmetric part.  The eight waves of a work-group
+// stream the same rows (the repeated reads hit the caches); wave s owns 17 blocks (two diagonal,
+// 66 MFMAs a step for every wave) whose groups lie in four of the eight group pairs
+// {2k, 2k+1}, so it loads 8 groups a step and four steps of rows stay in flight.  The ownership
+// table is a balanced covering of the block triangle by unions of four pairs (found by a flow
+// search; the compile-time check below proves that it covers every block once).  The
+// work-group's partial is [block u][re, im][lane * 4 + v] for the entry (4 g + v, m) of block u.
+constexpr int kG4Blocks = 136;                 // upper 16 x 16 blocks of the 256 x 256 complex G4
+constexpr int kG4Part = kG4Blocks * 2 * 256;   // floats per work-group partial
+constexpr int kG4Threads = 512;                // eight waves, two per SIMD
+constexpr int kG4Own = 17;                     // blocks per wave
+constexpr int kG4Split = 4;                    // partial ranges summed in parallel by the reduction
+
+constexpr int kG4Pair[8][4] = {
+    {1, 3, 4, 6},
+    {0, 4, 6, 7},
+    {1, 2, 4, 5},
+    {1, 2, 3, 7},
+    {0, 2, 3, 6},
+    {0, 1, 5, 7},
+    {3, 4, 5, 6},
+    {0, 3, 5, 7}};
+constexpr int kG4Blk[8][kG4Own][2] = {
+    {{2, 2}, {3, 3}, {2, 3}, {2, 6}, {2, 7}, {2, 8}, {2, 9}, {2, 12}, {2, 13}, {3, 6}, {3, 7}, {3, 8}, {3, 9}, {3, 12}, {3, 13}, {6, 8}, {12, 13}},
+    {{0, 0}, {1, 1}, {0, 8}, {0, 9}, {1, 8}, {1, 9}, {1, 13}, {8, 9}, {8, 12}, {8, 14}, {8, 15}, {9, 14}, {9, 15}, {12, 14}, {12, 15}, {13, 14}, {13, 15}},
+    {{4, 4}, {5, 5}, {2, 5}, {2, 11}, {3, 4}, {3, 5}, {3, 10}, {3, 11}, {4, 5}, {4, 8}, {4, 9}, {4, 10}, {4, 11}, {5, 8}, {5, 9}, {5, 10}, {5, 11}},
+    {{6, 6}, {7, 7}, {2, 4}, {2, 14}, {2, 15}, {3, 14}, {3, 15}, {4, 6}, {4, 7}, {4, 14}, {4, 15}, {5, 6}, {5, 7}, {5, 14}, {5, 15}, {6, 15}, {7, 14}},
+    {{12, 12}, {13, 13}, {0, 4}, {0, 5}, {0, 12}, {0, 13}, {1, 4}, {1, 5}, {1, 7}, {1, 12}, {4, 12}, {4, 13}, {5, 12}, {5, 13}, {6, 12}, {6, 13}, {7, 12}},
+    {{10, 10}, {11, 11}, {0, 2}, {0, 3}, {0, 10}, {0, 11}, {1, 2}, {1, 3}, {1, 10}, {1, 11}, {2, 10}, {10, 11}, {10, 14}, {10, 15}, {11, 14}, {11, 15}, {14, 15}},
+    {{8, 8}, {9, 9}, {6, 9}, {7, 8}, {7, 9}, {7, 13}, {8, 10}, {8, 11}, {8, 13}, {9, 10}, {9, 11}, {9, 12}, {9, 13}, {10, 12}, {10, 13}, {11, 12}, {11, 13}},
+    {{14, 14}, {15, 15}, {0, 1}, {0, 6}, {0, 7}, {0, 14}, {0, 15}, {1, 6}, {1, 14}, {1, 15}, {6, 7}, {6, 10}, {6, 11}, {6, 14}, {7, 10}, {7, 11}, {7, 15}}};
+
+__host__ __device__ constexpr int g4_upper(int I, int J) { return I * 16 - I * (I - 1) / 2 + (J - I); }
+
+// Register slot of group G in wave s's buffer (-1: not loaded by that wave).
+__host__ __device__ constexpr int g4_slot(int s, int G) {
+  for (int t = 0; t < 4; ++t)
+    if (kG4Pair[s][t] == G >> 1) return 2 * t + (G & 1);
+  return -1;
+}
+
+constexpr bool g4_table_ok() {
+  int seen[16][16] = {};
+  for (int s = 0; s < 8; ++s)
+    for (int b = 0; b < kG4Own; ++b) {
+      const int I = kG4Blk[s][b][0], J = kG4Blk[s][b][1];
+      if (I < 0 || J > 15 || I > J || g4_slot(s, I) < 0 || g4_slot(s, J) < 0) return false;
+      if ((b < 2) != (I == J)) return false;
+      ++seen[I][J];
+    }
+  for (int I = 0; I < 16; ++I)
+    for (int J = I; J < 16; ++J)
+      if (seen[I][J] != 1) return false;
+  return true;
+}
+static_assert(g4_table_ok(), "every upper block of G4 must have exactly one owning wave");
+
+template <int S>
+__device__ __forceinline__ void g4_load(const float2* __restrict__ L, int ld, uint32_t x0, int p, int q, int m,
+                                        float2 (&v)[8]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = kG4Pair[S][t];   // groups 2k, 2k+1: segment k / 2, columns 32 (k mod 2) + {0, 16}
+    const int sg = k >> 1;
+    const uint32_t x = x0 | ((uint32_t)(sg & 1) << p) | ((uint32_t)(sg >> 1) << q);
+    const float2* src = L + (size_t)x * ld + 32 * (k & 1) + m;
+    v[2 * t] = src[0];
+    v[2 * t + 1] = src[16];
+  }
+}
+
+template <int S, int B>
+__device__ __forceinline__ void g4_block(const float2 (&x)[8], const float (&nxi)[8], v4f& re, v4f& im) {
+  constexpr int I = kG4Blk[S][B][0], J = kG4Blk[S][B][1];
+  constexpr int a = g4_slot(S, I), b = g4_slot(S, J);
+  re = mfma16(x[a].x, x[b].x, re);
+  re = mfma16(x[a].y, x[b].y, re);
+  im = mfma16(x[a].x, x[b].y, im);
+  if constexpr (I != J) im = mfma16(nxi[a], x[b].x, im);
+}
+
+template <int S>
+__device__ __forceinline__ void g4_wave(const float2* __restrict__ L, int ld, int p, int q, float* __restrict__ out,
+                                        uint32_t r_begin, uint32_t r_end, int lane) {
+  const int m = lane & 15, g = lane >> 4;
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  v4f re[kG4Own], im[kG4Own];
+#pragma unroll
+  for (int k = 0; k < kG4Own; ++k) {
+    re[k] = v4f{0, 0, 0, 0};
+    im[k] = v4f{0, 0, 0, 0};
+  }
+  if (r_begin >= r_end) {   // an idle work-group still writes its (zero) partial
+    r_begin = r_end = 0;
+  }
+  auto step = [&](const float2(&x)[8]) {
+    float nxi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nxi[k] = -x[k].y;
+    static_for<kG4Own>([&](auto b) {
+      constexpr int B = decltype(b)::value;
+      g4_block<S, B>(x, nxi, re[B], im[B]);
+    });
+  };
+  auto row = [&](uint32_t r) { return insert2(r + g, lo, hi); };
+  // look-ahead rows past the slab's end load the current 16 rows again rather than branch
+  auto ahead = [&](uint32_t r) { return r < r_end ? r : r - 16; };
+  // four register buffers in turn: each step's rows are requested three steps before their MFMAs
+  // (the scheduling barriers keep every load ahead of the MFMAs that follow it: left alone, the
+  // scheduler sinks the loads to their first use to save registers)
+  float2 b0[8], b1[8], b2[8], b3[8];
+  g4_load<S>(L, ld, row(r_begin), p, q, m, b0);
+  g4_load<S>(L, ld, row(r_begin + 4), p, q, m, b1);
+  g4_load<S>(L, ld, row(r_begin + 8), p, q, m, b2);
+  for (uint32_t r0 = r_begin; r0 < r_end; r0 += 16) {
+    g4_load<S>(L, ld, row(r0 + 12), p, q, m, b3);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b0);
+    g4_load<S>(L, ld, row(ahead(r0 + 16)), p, q, m, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b1);
+    g4_load<S>(L, ld, row(ahead(r0 + 20)), p, q, m, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b2);
+    g4_load<S>(L, ld, row(ahead(r0 + 24)), p, q, m, b2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(b3);
+  }
+  static_for<kG4Own>([&](auto b) {
+    constexpr int B = decltype(b)::value;
+    constexpr int u = g4_upper(kG4Blk[S][B][0], kG4Blk[S][B][1]);
+    *reinterpret_cast<v4f*>(out + (2 * u) * 256 + lane * 4) = re[B];
+    *reinterpret_cast<v4f*>(out + (2 * u + 1) * 256 + lane * 4) = im[B];
+  });
+}
+
+// Work-group b streams rows [b rpt, (b + 1) rpt) of Y; rows and rpt are multiples of 16, so every
+// group of four 4-row steps is whole.
+__global__ __launch_bounds__(kG4Threads) __attribute__((amdgpu_waves_per_eu(2, 2))) void gram4_stream_kernel(
+    const float2* __restrict__ L, int ld, int p, int q, float* __restrict__ part, uint32_t rows, uint32_t rpt) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t r_begin = min(rows, blockIdx.x * rpt), r_end = min(rows, r_begin + rpt);
+  float* out = part + (size_t)blockIdx.x * kG4Part;
+  switch (wave) {
+    case 0: g4_wave<0>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 1: g4_wave<1>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 2: g4_wave<2>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 3: g4_wave<3>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 4: g4_wave<4>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 5: g4_wave<5>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    case 6: g4_wave<6>(L, ld, p, q, out, r_begin, r_end, lane); break;
+    default: g4_wave<7>(L, ld, p, q, out, r_begin, r_end, lane); break;
+  }
+}
+
+// First reduction level: work-group (u, sp) sums, in FP64 and a fixed order, the partials
+// [nb sp / kG4Split, nb (sp + 1) / kG4Split) of block u; thread t takes the four consecutive
+// floats 4 t of the block's 512 (the re plane, then the im plane).  Result:
+// sums[(u kG4Split + sp)][512], in the same order.
+constexpr int kG4SumThreads = 128;
+__global__ __launch_bounds__(kG4SumThreads) void gram4_stream_sum(const float* __restrict__ part, int nb,
+                                                                  double* __restrict__ sums) {
+  const int u = blockIdx.x / kG4Split, sp = blockIdx.x % kG4Split;
+  const int t = threadIdx.x, off = 2 * u * 256 + 4 * t;
+  const int b0 = nb * sp / kG4Split, b1 = nb * (sp + 1) / kG4Split;
+  double a[4] = {0, 0, 0, 0};
+  int b = b0;
+  constexpr int RB = 8;   // partials in flight per thread
+  for (; b + RB <= b1; b += RB) {
+    v4f v[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) v[k] = *reinterpret_cast<const v4f*>(part + (size_t)(b + k) * kG4Part + off);
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] += (double)v[k][c];
+  }
+  for (; b < b1; ++b) {
+    const v4f v = *reinterpret_cast<const v4f*>(part + (size_t)b * kG4Part + off);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] += (double)v[c];
+  }
+  double* dst = sums + (size_t)blockIdx.x * 512 + 4 * t;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) dst[c] = a[c];
+}
+
+// G4 (256 x 256 complex, row-major, FP64) from the range sums: work-group u, thread e = lane * 4 + v
+// for the entry (4 (lane / 16) + v, lane % 16) of block u.  Off-diagonal blocks are mirrored as
+// conjugates; a diagonal block's imaginary part is A - A^T.
+__global__ __launch_bounds__(256) void gram4_stream_combine(const double* __restrict__ sums,
+                                                            double* __restrict__ S4) {
+  const int u = blockIdx.x;
+  int I = 0, rem = u;
+  while (rem >= 16 - I) {
+    rem -= 16 - I;
+    ++I;
+  }
+  const int J = I + rem;
+  const int e = threadIdx.x, lane = e >> 2, v = e & 3;
+  const int i = 4 * (lane >> 4) + v, j = lane & 15;
+  const int et = (16 * (j >> 2) + i) * 4 + (j & 3);   // entry (j, i) of the block
+  const double* src = sums + (size_t)u * kG4Split * 512;
+  double re = 0.0, im = 0.0, imt = 0.0;
+#pragma unroll
+  for (int sp = 0; sp < kG4Split; ++sp) {
+    re += src[sp * 512 + e];
+    im += src[sp * 512 + 256 + e];
+    imt += src[sp * 512 + 256 + et];
+  }
+  if (I == J) im -= imt;
+  const int r = 16 * I + i, c = 16 * J + j;
+  S4[2 * ((size_t)r * 256 + c)] = re;
+  S4[2 * ((size_t)r * 256 + c) + 1] = im;
+  if (I != J) {
+    S4[2 * ((size_t)c * 256 + r)] = re;
+    S4[2 * ((size_t)c * 256 + r) + 1] = -im;
+  }
+}
+
+size_t gram4_stream_reals(int n) {
+  if (n < 6) return 0;
+  const uint64_t nb = std::min<uint64_t>(256, (1ull << (n - 2)) / 16);   // one work-group per CU at most
+  return (size_t)nb * kG4Part + (size_t)kG4Blocks * kG4Split * 512 * 2;
+}
+
 template <class T, int FH>
 static hipError_t launch_gram4_f(const cx_t<T>* L, int n, int ld, int c, int p, int q, T* part_h, T* part_c,
                                  double* S4, int max_blocks, hipStream_t s) {
@@ -569,6 +803,33 @@ static hipError_t launch_gram4_f(const cx_t<T>* L, int n, int ld, int c, int p, 
   // at most one work-group per CU the stream may use (a second round would double the time)
   const int nbh = std::max(1, std::min(gram4_blocks_halves(n), max_blocks / 2));
   const int nbc = std::max(1, std::min(gram4_blocks_cross(n), max_blocks));
+  if constexpr (sizeof(T) == 4 && FH == 256) {
+    // streamed form (rows a multiple of 16): the partials and then the range sums go to the one
+    // region that starts at part_h (at least gram4_stream_reals(n) floats in complex64); below
+    // 16 rows the tiled kernels run instead
+    const int NT = FH / 16;
+    const size_t room = std::max(((size_t)2 * gram4_blocks_halves(n) * (NT * (NT + 1) / 2) +
+                                  (size_t)gram4_blocks_cross(n) * NT * NT) * 256,
+                                 gram4_stream_reals(n));
+    const size_t sums = (size_t)kG4Blocks * kG4Split * 512 * 2;   // FP64, in floats
+    if (part_c != part_h + (size_t)2 * gram4_blocks_halves(n) * (NT * (NT + 1) / 2) * 256)
+      return hipErrorInvalidValue;
+    const size_t fit = room > sums ? (room - sums) / kG4Part : 0;
+    const int nb = (int)std::min<size_t>({(size_t)max_blocks, fit, rows / 16});
+    if (rows >= 16 && nb >= 1) {
+      const uint32_t rpt = (((rows + nb - 1) / nb) + 15) & ~15u;
+      double* sum_buf = reinterpret_cast<double*>(part_h + (size_t)nb * kG4Part);
+      hipLaunchKernelGGL(gram4_stream_kernel, dim3(nb), dim3(kG4Threads), 0, s, L, ld, p, q, part_h, rows, rpt);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(gram4_stream_sum, dim3(kG4Blocks * kG4Split), dim3(kG4SumThreads), 0, s, part_h, nb,
+                         sum_buf);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(gram4_stream_combine, dim3(kG4Blocks), dim3(256), 0, s, sum_buf, S4);
+      return hipGetLastError();
+    }
+  }
   {
     const uint32_t chunks = (rows + kGramKC - 1) / kGramKC;
     const uint32_t cpb = (chunks + nbh - 1) / nbh;

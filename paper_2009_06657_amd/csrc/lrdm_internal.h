@@ -255,13 +255,19 @@ hipError_t launch_chain_compose(double* Wp, const double* Wn, double* tmp, cx_t<
 // 4-way Gram G4 (4c x 4c complex FP64, row-major, index (bit q, bit p, column)) of the factor on
 // the bit pair (p, q): the halves with bit q = 0 and 1 (split Gram on p; partials part_h, 2
 // gram4_blocks_halves(n) blocks of the upper tiles of width 4c) and the cross block (partials
-// part_c, gram4_blocks_cross(n) blocks of every tile), reduced in a fixed order in FP64.
-// max_blocks: the CUs the stream may use (at most that many work-groups per pass).
+// part_c, gram4_blocks_cross(n) blocks of every tile), reduced in a fixed order in FP64.  For
+// complex64 with c = 64 and at least 16 rows one streamed pass forms every block instead (one
+// partial per work-group from part_h on, summed in FP64 in a fixed order; part_c must be where
+// the layout above puts it).  max_blocks: the CUs the stream may use (at most that many
+// work-groups per pass).
 template <class T>
 hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T* part_h, T* part_c, double* S4,
                         int max_blocks, hipStream_t s);
 int gram4_blocks_halves(int n);
 int gram4_blocks_cross(int n);
+// Floats of the complex64 c = 64 streamed form (one partial per work-group, then FP64 range
+// sums); the partial region of the 4-way Gram holds at least this much in complex64.
+size_t gram4_stream_reals(int n);
 // Split Gram on q (2c x 2c, written to S) of the factor after the projection W (2c x 2c, FP64)
 // on p, from G4 taken before that projection; T: 3 (2c)^2 complex FP64 scratch.
 hipError_t launch_pair_transform(const double* G4, const double* W, double* T, double* S, int c, hipStream_t s);

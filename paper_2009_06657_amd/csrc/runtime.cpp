@@ -109,7 +109,9 @@ bool compute_layout(int n, int r_max, lrdm_dtype dt, int m_max, unsigned flags, 
     const size_t nt = c4 / 16;   // 16-wide real tiles across one half (4c reals)
     const size_t nup = nt * (nt + 1) / 2;
     L.off_S4 = take(2 * c4 * c4 * 16);
-    L.off_part4 = take(((size_t)2 * gram4_blocks_halves(n) * nup + (size_t)gram4_blocks_cross(n) * nt * nt) * 256 * rs);
+    L.off_part4 = take(std::max(((size_t)2 * gram4_blocks_halves(n) * nup + (size_t)gram4_blocks_cross(n) * nt * nt) *
+                                    256 * rs,
+                                rs == 4 ? gram4_stream_reals(n) * 4 : (size_t)0));
     L.off_W4 = take(c4 * c4 * cs);
     L.off_M4 = take((size_t)(16 * 16 + 4 * 16) * 16);
   }

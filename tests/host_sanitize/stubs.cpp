@@ -279,7 +279,7 @@ hipError_t launch_eig(const double* S, int Fc, const Channel&, int nsplit, int c
 }
 template <class T>
 hipError_t launch_project(cx_t<T>* L, int n, int ld, int c_in, int nsplit, int, int c_out, const cx_t<T>* W, int,
-                          hipStream_t) {
+                          hipStream_t, int) {
   ++hs::launches;
   touch_L<T>(L, n, ld, c_in > c_out ? c_in : c_out, "proj L");
   touch(W, (size_t)(nsplit * c_in) * (nsplit * c_out) * sizeof(cx_t<T>), "proj W");
@@ -322,6 +322,11 @@ int gram4_blocks_cross(int n) {
   const uint64_t chunks = ((1ull << (n - 2)) + 31) / 32;
   return (int)(chunks < 256 ? chunks : 256);
 }
+size_t gram4_stream_reals(int n) {
+  if (n < 6) return 0;
+  const uint64_t nb = std::min<uint64_t>(256, (1ull << (n - 2)) / 16);
+  return (size_t)nb * 136 * 2 * 256 + (size_t)136 * 4 * 512 * 2;
+}
 template <class T>
 hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T* part_h, T* part_c, double* S4,
                         int, hipStream_t) {
@@ -334,6 +339,7 @@ hipError_t launch_gram4(const cx_t<T>* L, int n, int ld, int c, int p, int q, T*
   const size_t nt = (size_t)(4 * c) / 16;
   touch(part_h, (size_t)2 * gram4_blocks_halves(n) * (nt * (nt + 1) / 2) * 256 * sizeof(T), "gram4 halves partials");
   touch(part_c, (size_t)gram4_blocks_cross(n) * nt * nt * 256 * sizeof(T), "gram4 cross partials");
+  if (sizeof(T) == 4 && c == 64 && n >= 6) touch(part_h, gram4_stream_reals(n) * sizeof(T), "gram4 streamed partials");
   touch(S4, (size_t)(4 * c) * (4 * c) * 16, "gram4 S4");
   return hipSuccess;
 }
@@ -489,7 +495,7 @@ hipError_t launch_set_e0(cx_t<T>* L, hipStream_t) {
   template hipError_t launch_eig<T>(const double*, int, const Channel&, int, int, int, int, int, double, int,    \
                                     int, int, const EigBufs&, cx_t<T>*, hipStream_t);                           \
   template hipError_t launch_project<T>(cx_t<T>*, int, int, int, int, int, int, const cx_t<T>*, int,            \
-                                        hipStream_t);                                                          \
+                                        hipStream_t, int);                                                          \
   template hipError_t launch_probabilities<T>(const cx_t<T>*, int, int, int, double*, hipStream_t);            \
   template hipError_t launch_zstats<T>(const cx_t<T>*, int, int, int, double*, int, double*, hipStream_t);     \
   template hipError_t launch_pauli<T>(const cx_t<T>*, const cx_t<T>*, int, int, int, const uint64_t*,          \

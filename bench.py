@@ -47,8 +47,8 @@ def algorithmic_flops(n: int, r_pad: int, cls: int, m: int = 2, k: int = 64, blo
     rows, w = 2 ** (n - 1), 2 * r_pad
     if cls == 1:
         return 8.0 * rows * w * w / 2
-    if cls == 6:   # 4-way Gram of a bit pair: the two halves (split Grams over half the rows each,
-        # Hermitian) and the full cross block C = X_0^H X_1 over 2^(n-2) rows
+    if cls == 6:   # 4-way Gram of a bit pair, the Hermitian Y^H Y with Y = [X_0 | X_1] over 2^(n-2)
+        # rows: the two halves (split Grams over half the rows each) and the full cross block
         return 2 * 8.0 * (rows / 2) * w * w / 2 + 8.0 * (rows / 2) * w * w
     if cls == 4:
         return 8.0 * rows * w * w * blocks / 4

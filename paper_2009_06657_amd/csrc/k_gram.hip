@@ -568,7 +568,7 @@ int gram4_blocks_cross(int n) {
 // accumulate with no LDS and no barrier: S_IJ += Y_I^H Y_J as Re += Yr_I Yr_J + Yi_I Yi_J and
 // Im += Yr_I Yi_J - Yi_I Yr_J.  On a diagonal block Im is A - A^T with A = Yr_I^T Yi_I, so one
 // MFMA gives it and the reduction takes the antisymmetric part.  The eight waves of a work-group
-// stream the same rows (the repeated reads hit the caches); wave s owns 17 blocks (two diagonal,
+// stream the same rows (the repeated reads hit L2); wave s owns 17 blocks (two diagonal,
 // 66 MFMAs a step for every wave) whose groups lie in four of the eight group pairs
 // {2k, 2k+1}, so it loads 8 groups a step and four steps of rows stay in flight.  The ownership
 // table is a balanced covering of the block triangle by unions of four pairs (found by a flow
@@ -682,6 +682,11 @@ __device__ __forceinline__ void g4_wave(const float2* __restrict__ L, int ld, in
   g4_load<S>(L, ld, row(r_begin + 4), p, q, m, b1);
   g4_load<S>(L, ld, row(r_begin + 8), p, q, m, b2);
   for (uint32_t r0 = r_begin; r0 < r_end; r0 += 16) {
+    // every 16 steps the eight waves meet (each runs the same number of iterations): left free,
+    // they drift apart until lines one wave brought into L2 are evicted before the last of the
+    // four waves that read them gets there (2.5 times the bytes of L fetched; with the barrier,
+    // exactly the bytes of L, in the same time)
+    if (((r0 - r_begin) & 63) == 0) __syncthreads();
     g4_load<S>(L, ld, row(r0 + 12), p, q, m, b3);
     __builtin_amdgcn_sched_barrier(0);
     step(b0);

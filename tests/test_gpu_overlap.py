@@ -173,6 +173,25 @@ def test_overlap_reset_and_outputs_mid_program(lr):
     dm.close(); ref.close()
 
 
+@pytest.mark.parametrize("n,blocks", [(6, 0), (7, 0), (8, 3), (9, 5)])
+def test_streamed_pair_gram_edges_against_oracle(lr, n, blocks):
+    """The streamed 4-way Gram (complex64, r_pad = 64) at its smallest sizes: 16 rows of Y in one
+    work-group (n = 6), and work-group counts that leave the last work-group without rows
+    (n = 8 with 3 work-groups, n = 9 with 5), against the oracle."""
+    prog = C.cfg3_program(n=n, r=64, layers=2)
+    dm = lr.LowRankDM(n, 64, lr.C64, prog.m_max, lr.FLAG_OVERLAP)
+    if blocks:
+        dm.set_tuning(gram4_blocks=blocks)
+    _say(f"[stream gram] n={n} r=64 gram4_blocks={blocks or 'default'}")
+    lr.run_program(dm, prog)
+    P = dm.probabilities().cpu().numpy()
+    Pref = oracle.probabilities(oracle.run_lret(prog))
+    err = float(np.max(np.abs(P - Pref)))
+    _say(f"  max|dP| {err:.2e}")
+    assert err <= 1e-5
+    dm.close()
+
+
 @pytest.mark.parametrize("flags", [0, 2])
 def test_tuned_launch_shapes_against_oracle(lr, flags):
     """Launch shapes away from the defaults (fewer split-K Gram blocks, a smaller gate tile, fewer

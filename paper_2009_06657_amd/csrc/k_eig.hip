@@ -593,6 +593,35 @@ __device__ __forceinline__ void eig_body(const double* __restrict__ S, int Fc, c
           A[a][b] = acc;
         }
       }
+    } else if (nsplit == 2 && m == 2 && N == NP) {
+      // two Kraus operators at the full order: rows i and i + N / 2 of G (copies 0 and 1, thread
+      // slots a and a + BR / 2) take the same row of S's blocks, so every S entry loaded serves
+      // both; the sums are formed in the same order as below
+      const double2* __restrict__ S2 = reinterpret_cast<const double2*>(S);
+      constexpr int HB = BR / 2, HN = NP / 2;
+  #pragma unroll
+      for (int a = 0; a < HB; ++a) {
+        const int i = R + NH * a;   // < N / 2
+        double2 t[BC][4];
+  #pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int w = (BC * Cc + b) & (HN - 1);
+  #pragma unroll
+          for (int uv = 0; uv < 4; ++uv) t[b][uv] = S2[(size_t)((uv >> 1) * c + i) * Fc + ((uv & 1) * c + w)];
+        }
+  #pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const int bj = (BC * Cc + b) / HN;
+          z64 a0 = zmk(0, 0), a1 = zmk(0, 0);
+  #pragma unroll
+          for (int uv = 0; uv < 4; ++uv) {
+            a0 = zadd(a0, zmul(Mab[bj * 4 + uv], zmk(t[b][uv].x, t[b][uv].y)));
+            a1 = zadd(a1, zmul(Mab[(m + bj) * 4 + uv], zmk(t[b][uv].x, t[b][uv].y)));
+          }
+          A[a][b] = a0;
+          A[a + HB][b] = a1;
+        }
+      }
     } else {
       // split view: S has halves of c columns; G's copies take the first cw = N / m of them, a
       // power of two (the factor's later columns are zero while its rank is still growing)

@@ -565,12 +565,12 @@ int gram4_blocks_cross(int n) {
 // inserted, so column group G (16 columns) of Y is columns 16 (G mod 4) of the L row of segment
 // G / 4.  A lane (g, m) of a wave holds Y[y0 + g][16 G + m] for the groups G it needs: these are
 // the MFMA operands of the 16 x 16 blocks (I, J) over a 4-row step, so the 136 upper blocks
-// accumulate with no LDS and no barrier: S_IJ += Y_I^H Y_J as Re += Yr_I Yr_J + Yi_I Yi_J and
+// accumulate in registers with no LDS: S_IJ += Y_I^H Y_J as Re += Yr_I Yr_J + Yi_I Yi_J and
 // Im += Yr_I Yi_J - Yi_I Yr_J.  On a diagonal block Im is A - A^T with A = Yr_I^T Yi_I, so one
 // MFMA gives it and the reduction takes the antisymmetric part.  The eight waves of a work-group
 // stream the same rows (the repeated reads hit L2); wave s owns 17 blocks (two diagonal,
 // 66 MFMAs a step for every wave) whose groups lie in four of the eight group pairs
-// {2k, 2k+1}, so it loads 8 groups a step and four steps of rows stay in flight.  The ownership
+// {2k, 2k+1}, so it loads 8 groups a step, three steps ahead of their MFMAs.  The ownership
 // table is a balanced covering of the block triangle by unions of four pairs (found by a flow
 // search; the compile-time check below proves that it covers every block once).  The
 // work-group's partial is [block u][re, im][lane * 4 + v] for the entry (4 g + v, m) of block u.
